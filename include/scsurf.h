@@ -1,0 +1,254 @@
+/*
+ * scsurf: online surface correction on a voxel-hashed TSDF, for one MI355X
+ * (gfx950).  C ABI of the data-parallel hot path of
+ *   R. Maier, R. Schaller, D. Cremers, "Efficient Online Surface Correction
+ *   for Real-time Large-Scale 3D Reconstruction", arXiv 1709.03763.
+ *
+ * Every call enqueues its device work on the caller's HIP stream (`stream`,
+ * a hipStream_t passed as void*; NULL means the null stream) and returns
+ * without synchronising unless stated.  Buffers marked "device" must be
+ * device memory that stays valid until the stream has passed the call;
+ * buffers marked "host" are read or written before the call returns.  The
+ * caller owns every buffer it passes; the library owns the volume (hash
+ * table, block pool, counters, scratch, captured graphs).  One volume must
+ * not be used from two streams at once.
+ *
+ * Errors: argument errors are returned at once with nothing enqueued.
+ * Errors found on the device (a full hash table or pool, de-integration of
+ * an unallocated block, a weight leaving [0, 2^14)) set a sticky error word
+ * in the volume, read by sc_volume_query; after such an error the field is
+ * unspecified and the volume must be reset and rebuilt by re-integrating the
+ * stored keyframes.  No C++ exception crosses this interface.
+ *
+ * Geometry (Sec. 3, "Preliminaries"): a pose T = (R, t) maps camera to world
+ * coordinates, g(T, p) = R p + t, with R row-major.  Cameras are pinhole,
+ * u = fx X / Z + cx, v = fy Y / Z + cy, pixel centres at integer
+ * coordinates, OpenCV axes (x right, y down, z forward).  Depth is z-depth
+ * in metres; 0 marks an invalid pixel.
+ *
+ * Decision convention (shared by this library and its test oracle, written
+ * independently by each): voxel n in Z^3 has centre s*n, block b = floor(n/8)
+ * holds 8x8x8 voxels indexed x + 8y + 64z.  Its camera point is the block
+ * origin mapped to the camera in FP64 and rounded to FP32, plus the in-block
+ * offset added in FP32 along x, then y, then z with per-axis steps
+ * fl32(s * R[axis][row]).  The nearest pixel is floor(fl32(fl32(fx*X)/Z)+cx
+ * + 1/2) (FP32, correctly rounded, no contraction).  The voxel is touched by
+ * a keyframe at a pose iff Z > 0, the pixel is inside the image, the
+ * keyframe weight q(W*) = rint(W* 2^10) / 2^10 at the pixel is positive, and
+ * |fl32(Z*(pixel) - Z)| <= trunc.
+ */
+#ifndef SCSURF_H
+#define SCSURF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sc_status;
+#define SC_OK 0
+#define SC_EINVAL (-1)     /* bad argument; nothing enqueued */
+#define SC_ENOMEM (-2)     /* a device or host allocation failed */
+#define SC_EHASHFULL (-3)  /* sticky: no free bucket in the block hash table */
+#define SC_EPOOLFULL (-4)  /* sticky: block pool exhausted (max_blocks) */
+#define SC_ENOTALLOC (-5)  /* sticky: de-integration touched an unallocated block */
+#define SC_EWEIGHT (-6)    /* sticky: a voxel weight would leave [0, 2^14) */
+#define SC_EDEVICE (-7)    /* a HIP runtime call failed */
+#define SC_ENOLIB (-8)     /* no usable gfx950 device */
+#define SC_ERANGE (-9)     /* sticky: a keyframe pixel's frustum cell spans more than 16 blocks per axis */
+
+#define SC_COLOR_RGBA8 0 /* voxel colour 4 x uint8 (RGB + pad); keyframe colour uint8 H x W x 4 */
+#define SC_COLOR_F32 1   /* voxel colour 3 x float in [0,1]; keyframe colour float H x W x 3 */
+
+#define SC_SEL_EQ3 0         /* Eq. (3): the m most-moved consecutive keyframes, ascending index */
+#define SC_SEL_TOPM 1        /* the m most-moved keyframes, descending pose change */
+#define SC_SEL_ALL_ORDERED 2 /* every changed keyframe, descending pose change */
+
+/* Pinhole intrinsics (Sec. 3); width x height pixels. */
+typedef struct {
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} sc_intrinsics;
+
+/* Camera-to-world pose (Sec. 3): x_world = R x_cam + t, R row-major. */
+typedef struct {
+    double R[9];
+    double t[3];
+} sc_pose;
+
+/* Voxel-hashed SDF (Sec. 3, "SDF volume"). */
+typedef struct {
+    float voxel_size;      /* metres */
+    float trunc;           /* truncation band mu, metres */
+    int64_t n_buckets;     /* hash buckets, a power of two */
+    int64_t max_blocks;    /* block pool capacity (8^3 voxels each) */
+    int32_t color_mode;    /* SC_COLOR_RGBA8 or SC_COLOR_F32 */
+    int32_t max_batch_ops; /* capacity of one batched update, in keyframe operations (<= 4096) */
+} sc_volume_params;
+
+/* A fused keyframe (Sec. 4.1): depth Z*, fusion weight W*, colour C*. */
+typedef struct {
+    const float* depth;  /* device, H x W, metres */
+    const float* weight; /* device, H x W; quantised to 2^-10 when used */
+    const void* color;   /* device, per the volume's colour mode */
+} sc_keyframe;
+
+/* Keyframe fusion parameters (Sec. 3, "Keyframe Fusion"). */
+typedef struct {
+    float z_min, z_max; /* valid depth range, metres */
+    float disc_rel;     /* reject a pixel whose 4-neighbour depth differs by more than disc_rel * Z */
+    float occ_rel;      /* a colour observation is visible if |Z_i - z| <= occ_rel * z */
+} sc_fuse_params;
+
+typedef struct sc_volume sc_volume;
+
+/* ---- volume lifecycle --------------------------------------------------- */
+
+/* Creates an empty volume on the current device.  The block pool
+ * (max_blocks x 6 KiB in RGBA8 mode, 10 KiB in F32 mode) and the hash table
+ * are allocated and cleared here.  *out is NULL on failure. */
+sc_status sc_volume_create(const sc_volume_params* params, sc_volume** out);
+
+/* Frees every device and host resource of the volume (synchronises). */
+void sc_volume_destroy(sc_volume* vol);
+
+/* Empties the volume (all blocks freed, error word cleared); enqueued. */
+sc_status sc_volume_reset(sc_volume* vol, void* stream);
+
+/* Synchronises `stream` and returns the allocated block count and the sticky
+ * device error (SC_OK or one of the sticky codes above). */
+sc_status sc_volume_query(sc_volume* vol, void* stream, int64_t* n_blocks, int32_t* sticky_error);
+
+/* Copies the first min(n_blocks, cap) allocated blocks, in pool order, into
+ * device buffers: block coordinates (int32 x 3), D (float x 512), W (float x
+ * 512) and colour (uint32 RGBA8 x 512, or float x 3 x 512 planar).  Any
+ * output may be NULL.  *n_out (host) receives n_blocks.  Synchronises. */
+sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, float* D, float* W, void* C,
+                           int64_t cap, int64_t* n_out);
+
+/* ---- keyframe fusion (Sec. 3 "Keyframe Fusion", Eq. 1) ------------------- */
+
+/* Per-pixel depth weight w_z = cos(theta) Z^-2, theta the angle between the
+ * depth normal and the camera axis, quantised to 2^-10; 0 marks pixels that
+ * are invalid or near a depth discontinuity.  depth: device n x H x W;
+ * wz_out: device n x H x W. */
+sc_status sc_depth_weight(const float* depth, int32_t n_frames, const sc_intrinsics* intr,
+                          const sc_fuse_params* params, float* wz_out, void* stream);
+
+/* Colour pre-processing of n frames: unsharp masking with the binomial
+ * [1 4 6 4 1]/16 kernel (amount 1), exact, in units of 1/256 (device uint16
+ * n x H x W x 3), and the blurriness weight w_b = 1 - blur of each frame
+ * (device double n), blur the re-blur measure of Crete et al. (2007). */
+sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int32_t height, uint16_t* sharp_out,
+                        double* wb_out, void* stream);
+
+/* Fuses n consecutive frames into one keyframe with pose T* = poses[ref]:
+ * forward-warped weighted depth average (Eq. 1) and weighted-median colour of
+ * the back-warped, sharpened input colours with weights w_b * w_z.  depth:
+ * device n x H x W float; rgb: device n x H x W x 3 uint8; poses: host n.
+ * Outputs (device, H x W): kf_depth, kf_weight (on the 2^-10 grid), kf_rgba
+ * (uint8 x 4, alpha 255 on valid pixels).  n_frames <= 64.  Scratch is held
+ * by the library between calls and reused. */
+sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames, int32_t ref,
+                  const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth, float* kf_weight,
+                  uint8_t* kf_rgba, void* stream);
+
+/* ---- voxel blocks (Sec. 3 "SDF volume") --------------------------------- */
+
+/* Allocates the blocks whose coordinates are listed (device int32 n x 3,
+ * duplicates allowed): hash probe and insert, one pool slot per new key.
+ * slots_out (device int32 n, may be NULL) receives each entry's pool slot. */
+sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_t* slots_out, void* stream);
+
+/* Integrates one keyframe at pose T (Sec. 3: blocks are first allocated,
+ * then voxels updated with a running weighted average):
+ *   W' = W + w, D' = (D W + d w) / W', C' = (C W + c w) / W',
+ * d = Z*(pixel) - Z (projective distance along z), w = q(W*(pixel)).  RGBA8
+ * colour is rounded to nearest, ties to even, after the update. */
+sc_status tsdf_integrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
+                         void* stream);
+
+/* De-integrates one keyframe at pose T, Eq. (2) (Sec. 4.3):
+ *   W' = W - w, D' = (D W - d w) / W', C' = (C W - c w) / W',
+ * with W' = 0 giving the empty voxel (0, 0, 0).  Never allocates. */
+sc_status tsdf_deintegrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
+                           void* stream);
+
+/* ---- surface correction (Sec. 4.3) --------------------------------------- */
+
+/* Host-only selection of keyframes to re-integrate.  Pose change
+ * ||s o t_i - s o t_i'||, t the Z-Y-X Euler angles and translation,
+ * s = (2,2,2,1,1,1); mode SC_SEL_*.  Writes indices in processing order to
+ * `out` (host, >= K) and the distances to dist_out (host, K, may be NULL).
+ * Returns the number selected, or a negative status. */
+int32_t sc_select(const sc_pose* T, const sc_pose* T_new, int32_t K, int32_t m, int32_t mode, int32_t* out,
+                  double* dist_out);
+
+/* The same selection from given distances (host, K). */
+int32_t sc_select_dist(const double* dist, int32_t K, int32_t m, int32_t mode, int32_t* out);
+
+/* Applies one pose-graph update in a single batched pass: selects keyframes
+ * (mode, m), de-integrates each selected keyframe at its integration pose
+ * and re-integrates it at its new pose (all de-integrations first, then all
+ * re-integrations, each in processing order; Sec. 4.3), every voxel applying
+ * its operations in that order.  One persistent, graph-captured launch does
+ * the voxel work.  All keyframes must share width and height.
+ * T_integrated (host, n_kf) is updated to T_new for the selected keyframes.
+ * selected_out (host, n_kf, may be NULL) receives the processing order and
+ * *n_selected (host, may be NULL) its length. */
+sc_status reintegrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                            sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
+                            int32_t* selected_out, int32_t* n_selected, void* stream);
+
+/* The plain per-keyframe path with the same semantics as reintegrate_batch:
+ * one tsdf_deintegrate per selected keyframe, then one tsdf_integrate each. */
+sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                            sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
+                            int32_t* selected_out, int32_t* n_selected, void* stream);
+
+/* Schedule of the batched voxel pass: voxels per lane (8, 4, 2 or 1; a
+ * block is handled by 8 / vpl wavefronts), wavefronts per workgroup when a
+ * block takes one wavefront, and persistent workgroups per compute unit.
+ * sc_set_schedule validates and stores it in the volume; sc_get_schedule
+ * reads it back. */
+typedef struct {
+    int32_t vpl;
+    int32_t waves_per_wg;
+    int32_t wgs_per_cu;
+} sc_schedule;
+sc_status sc_set_schedule(sc_volume* vol, const sc_schedule* sched);
+sc_status sc_get_schedule(sc_volume* vol, sc_schedule* sched);
+
+/* Autotuner: times every schedule on a private copy of the volume running the
+ * given update (nothing in `vol` changes), stores the fastest in the volume,
+ * and writes it to *best (host, may be NULL) with its time in *best_ms. */
+sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                      const sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
+                      sc_schedule* best, float* best_ms, void* stream);
+
+/* ---- adjoint of integration --------------------------------------------- */
+
+/* Backward of integrating n_kf keyframes at poses T_k Exp(xi_k) (xi at 0)
+ * into the volume, with the pixel and band decisions of the forward held
+ * fixed.  With a = w_k / W(v) per touched (voxel, keyframe):
+ *   dL/dZ_k(u)   += sum_{v -> u} a dL/dD(v)
+ *   dL/dC_k(u)   += sum_{v -> u} a dL/dC(v)               (F32 colour only)
+ *   dL/dxi_k     += sum_v a dL/dD(v) (0, 0, 1, p_y, -p_x, 0), p = T_k^-1 x_v
+ * grad_D (device, n_blocks x 512) and grad_C (device, n_blocks x 3 x 512,
+ * may be NULL) are indexed by pool slot; the volume must hold the field after
+ * the forward.  Outputs are accumulated (callers zero them): grad_depth
+ * (device n_kf x H x W), grad_color (device n_kf x H x W x 3, may be NULL),
+ * grad_xi (device n_kf x 6, FP32). */
+sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                                  const sc_pose* T, const float* grad_D, const float* grad_C, float* grad_depth,
+                                  float* grad_color, float* grad_xi, void* stream);
+
+/* Library version string. */
+const char* sc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCSURF_H */

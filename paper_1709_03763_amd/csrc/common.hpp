@@ -1,0 +1,118 @@
+// Internal definitions shared by the HIP translation units of libscsurf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "scsurf.h"
+
+namespace sc {
+
+constexpr int kBlockVox = 512;             // 8 x 8 x 8 voxels per block
+constexpr uint64_t kKeyEmpty = ~0ull;      // never a packed key (bit 63 is clear in every key)
+constexpr float kWeightScale = 1024.0f;    // sample weights live on the 2^-10 grid
+constexpr float kWeightLimit = 16384.0f;   // 2^14: sums stay exact in FP32 below this
+constexpr int kMaxBatchOps = 4096;
+
+// 21 bits per axis, two's complement, x in the high bits.
+__host__ __device__ inline uint64_t pack_key(int x, int y, int z)
+{
+    return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) | (uint64_t)(z & 0x1FFFFF);
+}
+
+__host__ __device__ inline int sext21(uint64_t v)
+{
+    int x = (int)(v & 0x1FFFFF);
+    return (x & 0x100000) ? x - 0x200000 : x;
+}
+
+__host__ __device__ inline void unpack_key(uint64_t k, int& x, int& y, int& z)
+{
+    x = sext21(k >> 42);
+    y = sext21(k >> 21);
+    z = sext21(k);
+}
+
+// Spatial hash of block coordinates (three large primes, XOR), as used by
+// voxel hashing; the table size is a power of two.
+__host__ __device__ inline uint32_t hash_block(int x, int y, int z)
+{
+    return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u);
+}
+
+// One keyframe operation (integrate or de-integrate a keyframe at a pose):
+// everything the voxel pass needs, precomputed on the host.
+struct OpDesc {
+    const float* depth;   // Z*, H x W
+    const float* weight;  // W*, H x W
+    const void* color;    // RGBA8 (uint32 per pixel) or float x 3
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    double R[9];          // camera -> world rotation, row-major
+    double t[3];          // camera -> world translation
+    float a[3][3];        // a[axis][row] = fl32(s * R[axis][row]): camera step of one voxel along a world axis
+    int32_t sign;         // +1 integrate, -1 de-integrate
+    int32_t kf;           // keyframe index within the call (for gradients)
+};
+
+// Device view of a volume.
+struct VolDev {
+    uint64_t* keys;        // n_buckets packed block keys (kKeyEmpty = free)
+    int32_t* vals;         // n_buckets pool slots
+    uint64_t* slot_keys;   // max_blocks: key of each pool slot
+    float* pool;           // max_blocks x stride floats
+    uint32_t* n_blocks;    // allocated blocks (pool cursor)
+    int32_t* err;          // sticky error word
+    uint32_t bucket_mask;
+    int32_t max_blocks;
+    int32_t stride;        // floats per block: 1536 (RGBA8) or 2560 (F32)
+    int32_t color_mode;
+    float s;               // voxel size
+    float mu;              // truncation
+};
+
+// Candidate-block table used to deduplicate the blocks that keyframe
+// operations may touch (scratch owned by the volume).
+struct CandDev {
+    uint64_t* keys;       // cand buckets
+    uint64_t* mask;       // cand buckets x words: bit o set if operation o proposed the block
+    uint32_t* list;       // occupied buckets in insertion order
+    uint32_t* sorted;     // occupied buckets ordered by operation count (batched path)
+    uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity), [4] batch work cursor
+    uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
+    uint32_t mask_bits;   // cand buckets - 1
+    uint32_t cap;         // list capacity
+    int32_t words;        // 64-bit mask words per bucket
+};
+
+// Batched-update header in device memory, so a captured graph can be
+// replayed with a different number of operations.
+struct BatchHdr {
+    int32_t n_ops;
+    int32_t tiles_x, tiles_y;
+    int32_t pad;
+};
+
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+}  // namespace sc
+
+// The opaque handle behind the C ABI.
+struct sc_volume {
+    sc_volume_params p;
+    int device;
+    sc::VolDev dev;
+    sc::CandDev cand;
+    sc::OpDesc* d_ops;       // device, max_batch_ops (+ one for the plain path)
+    sc::OpDesc* h_ops;       // pinned host staging
+    sc::BatchHdr* d_hdr;     // device
+    sc::BatchHdr* h_hdr;     // pinned host staging
+    uint32_t cand_buckets;
+    int parity;              // plain-path candidate counter parity
+    hipStream_t cap_stream;  // private stream used for graph capture
+    hipEvent_t staged;       // recorded after the batch descriptors were copied to the device
+    hipGraphExec_t graph[4][1]; // captured batched sequence per voxels-per-lane choice
+    int graph_keys[4];       // schedule the graph of each slot was captured with
+    sc_schedule sched;
+    int n_cu;
+};

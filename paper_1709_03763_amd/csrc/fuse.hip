@@ -1,0 +1,507 @@
+// Keyframe fusion (Sec. 3, "Keyframe Fusion"; Eq. 1).
+//
+//   depth_weight   w_z = cos(theta) Z^-2 per pixel, quantised to 2^-10, with
+//                  rejection near depth discontinuities
+//   warp_kernel    forward warp of every surviving pixel into the keyframe,
+//                  p* = g(T*^-1, g(T_i, pi^-1(x, Z_i(x)))), accumulated at the
+//                  nearest pixel of pi(p*) in exact int64 fixed point (w on the
+//                  2^-10 grid, z on the 2^-20 m grid), so that colliding
+//                  atomics cannot change a bit; Eq. 1's running weighted mean
+//                  equals sum(w z) / sum(w)
+//   sharpen        unsharp mask C + (C - G * C), G the binomial [1 4 6 4 1]/16
+//                  kernel, exact in units of 1/256
+//   blur sums      re-blur measure on integer luminance (exact int64 sums)
+//   color_kernel   back-warp of each keyframe pixel into every frame,
+//                  bilinear sample of the sharpened colour, weight w_b * w_z,
+//                  per-channel lower weighted median
+//
+// Decisions are FP32 with the written operation order (-ffp-contract=off).
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace sc {
+
+constexpr int kMaxFrames = 64;
+
+struct FuseFrames {
+    float Rf[kMaxFrames][12];  // forward: T*^-1 T_i, rows of R then t
+    float Rb[kMaxFrames][12];  // backward: T_i^-1 T*
+};
+
+__device__ inline bool zvalid(float z, float zmin, float zmax) { return z >= zmin && z <= zmax; }
+
+__device__ inline void backproject(float u, float v, float z, const sc_intrinsics& in, float P[3])
+{
+    P[0] = ((u - in.cx) * z) / in.fx;
+    P[1] = ((v - in.cy) * z) / in.fy;
+    P[2] = z;
+}
+
+__device__ inline void xform(const float* T, const float P[3], float q[3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) q[r] = ((T[3 * r + 0] * P[0] + T[3 * r + 1] * P[1]) + T[3 * r + 2] * P[2]) + T[9 + r];
+}
+
+__device__ inline bool project(const sc_intrinsics& in, const float q[3], float& uf, float& vf, int& iu, int& iv)
+{
+    if (!(q[2] > 0.0f)) return false;
+    uf = (in.fx * q[0]) / q[2] + in.cx;
+    vf = (in.fy * q[1]) / q[2] + in.cy;
+    const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
+    if (!(fu >= 0.0f && fu <= (float)(in.width - 1) && fv >= 0.0f && fv <= (float)(in.height - 1))) return false;
+    iu = (int)fu;
+    iv = (int)fv;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// depth weight
+// ---------------------------------------------------------------------------
+
+__global__ void depth_weight_kernel(const float* __restrict__ Z, int n, sc_intrinsics in, sc_fuse_params p,
+                                    float* __restrict__ wz)
+{
+    const int W = in.width, H = in.height;
+    const int64_t np = (int64_t)W * H;
+    const int f = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n || idx >= np) return;
+    const int u = (int)(idx % W), v = (int)(idx / W);
+    const float* Zf = Z + (size_t)f * np;
+    float out = 0.0f;
+    const float z = Zf[idx];
+    if (zvalid(z, p.z_min, p.z_max) && u >= 1 && u <= W - 2 && v >= 1 && v <= H - 2) {
+        const float zl = Zf[idx - 1], zr = Zf[idx + 1], zu = Zf[idx - W], zd = Zf[idx + W];
+        const bool ok = zvalid(zl, p.z_min, p.z_max) && zvalid(zr, p.z_min, p.z_max) && zvalid(zu, p.z_min, p.z_max) &&
+                        zvalid(zd, p.z_min, p.z_max);
+        const float th = p.disc_rel * z;
+        if (ok && !(fabsf(zl - z) > th) && !(fabsf(zr - z) > th) && !(fabsf(zu - z) > th) && !(fabsf(zd - z) > th)) {
+            float Pl[3], Pr[3], Pu[3], Pd[3];
+            backproject((float)(u - 1), (float)v, zl, in, Pl);
+            backproject((float)(u + 1), (float)v, zr, in, Pr);
+            backproject((float)u, (float)(v - 1), zu, in, Pu);
+            backproject((float)u, (float)(v + 1), zd, in, Pd);
+            const float a0 = Pr[0] - Pl[0], a1 = Pr[1] - Pl[1], a2 = Pr[2] - Pl[2];
+            const float b0 = Pd[0] - Pu[0], b1 = Pd[1] - Pu[1], b2 = Pd[2] - Pu[2];
+            const float nx = a1 * b2 - a2 * b1;
+            const float ny = a2 * b0 - a0 * b2;
+            const float nz = a0 * b1 - a1 * b0;
+            const float nn = (nx * nx + ny * ny) + nz * nz;
+            if (nn > 0.0f) {
+                const float c = fabsf(nz) / sqrtf(nn);
+                const float w = c / (z * z);
+                out = rintf(w * kWeightScale) / kWeightScale;
+            }
+        }
+    }
+    wz[(size_t)f * np + idx] = out;
+}
+
+// ---------------------------------------------------------------------------
+// depth fusion
+// ---------------------------------------------------------------------------
+
+__global__ void warp_kernel(const float* __restrict__ Z, const float* __restrict__ wz, int n, sc_intrinsics in,
+                            const FuseFrames* __restrict__ fr, unsigned long long* KW, unsigned long long* KZ)
+{
+    const int W = in.width, H = in.height;
+    const int64_t np = (int64_t)W * H;
+    const int f = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n || idx >= np) return;
+    const float w = wz[(size_t)f * np + idx];
+    if (!(w > 0.0f)) return;
+    const int u = (int)(idx % W), v = (int)(idx / W);
+    float P[3], q[3];
+    backproject((float)u, (float)v, Z[(size_t)f * np + idx], in, P);
+    xform(fr->Rf[f], P, q);
+    float uf, vf;
+    int iu, iv;
+    if (!project(in, q, uf, vf, iu, iv)) return;
+    const long long wk = (long long)rintf(w * kWeightScale);
+    const long long zk = (long long)rintf(q[2] * 1048576.0f);
+    const int64_t t = (int64_t)iv * W + iu;
+    atomicAdd(KW + t, (unsigned long long)wk);
+    atomicAdd(KZ + t, (unsigned long long)(wk * zk));
+}
+
+__global__ void depth_final_kernel(const unsigned long long* KW, const unsigned long long* KZ, int64_t np, float* Zs,
+                                   float* Ws)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const long long kw = (long long)KW[i];
+    if (kw > 0) {
+        const long long kz = (long long)KZ[i];
+        Ws[i] = (float)((double)kw / 1024.0);
+        Zs[i] = (float)(((double)kz / (double)kw) * 0x1p-20);
+    } else {
+        Ws[i] = 0.0f;
+        Zs[i] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// colour pre-processing
+// ---------------------------------------------------------------------------
+
+__device__ inline int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+__global__ void sharpen_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H, uint16_t* __restrict__ out)
+{
+    const int64_t np = (int64_t)W * H;
+    const int f = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n || idx >= np) return;
+    const int u = (int)(idx % W), v = (int)(idx / W);
+    const uint8_t* C = rgb + (size_t)f * np * 3;
+    const int g[5] = {1, 4, 6, 4, 1};
+    int S[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = -2; j <= 2; ++j) {
+        const int vv = clampi(v + j, 0, H - 1);
+        int row[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = -2; i <= 2; ++i) {
+            const int uu = clampi(u + i, 0, W - 1);
+            const uint8_t* px = C + 3 * ((size_t)vv * W + uu);
+            row[0] += g[i + 2] * px[0];
+            row[1] += g[i + 2] * px[1];
+            row[2] += g[i + 2] * px[2];
+        }
+        S[0] += g[j + 2] * row[0];
+        S[1] += g[j + 2] * row[1];
+        S[2] += g[j + 2] * row[2];
+    }
+    const uint8_t* c0 = C + 3 * idx;
+    uint16_t* o = out + (size_t)f * np * 3 + 3 * idx;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int val = 512 * (int)c0[k] - S[k];
+        o[k] = (uint16_t)clampi(val, 0, 65280);
+    }
+}
+
+__device__ inline int luma(const uint8_t* px) { return (77 * px[0] + 150 * px[1] + 29 * px[2] + 128) >> 8; }
+
+// sums[f*4 + {0,1,2,3}] = sF_h, sV_h, sF_v, sV_v (re-blur with a 9-tap box,
+// kept as 9x integer sums; the box difference telescopes to two samples).
+__global__ __launch_bounds__(256) void blur_sums_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H,
+                                                        unsigned long long* sums)
+{
+    const int64_t np = (int64_t)W * H;
+    const int f = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long acc[4] = {0, 0, 0, 0};
+    if (f < n && idx < np) {
+        const int u = (int)(idx % W), v = (int)(idx / W);
+        const uint8_t* C = rgb + (size_t)f * np * 3;
+        auto Y = [&](int uu, int vv) { return luma(C + 3 * ((size_t)vv * W + uu)); };
+        const int y0 = Y(u, v);
+        if (u >= 1) {
+            const long long dF = 9LL * abs(y0 - Y(u - 1, v));
+            const long long dB = abs(Y(clampi(u + 4, 0, W - 1), v) - Y(clampi(u - 5, 0, W - 1), v));
+            acc[0] = dF;
+            acc[1] = dF > dB ? dF - dB : 0;
+        }
+        if (v >= 1) {
+            const long long dF = 9LL * abs(y0 - Y(u, v - 1));
+            const long long dB = abs(Y(u, clampi(v + 4, 0, H - 1)) - Y(u, clampi(v - 5, 0, H - 1)));
+            acc[2] = dF;
+            acc[3] = dF > dB ? dF - dB : 0;
+        }
+    }
+    __shared__ long long red[4][256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4 && f < n) atomicAdd(sums + 4 * f + threadIdx.x, (unsigned long long)red[threadIdx.x][0]);
+}
+
+__global__ void blur_final_kernel(const unsigned long long* sums, int n, double* wb)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    const long long sFh = (long long)sums[4 * f], sVh = (long long)sums[4 * f + 1];
+    const long long sFv = (long long)sums[4 * f + 2], sVv = (long long)sums[4 * f + 3];
+    const double bh = sFh > 0 ? (double)(sFh - sVh) / (double)sFh : 0.0;
+    const double bv = sFv > 0 ? (double)(sFv - sVv) / (double)sFv : 0.0;
+    wb[f] = 1.0 - (bh > bv ? bh : bv);
+}
+
+// ---------------------------------------------------------------------------
+// colour fusion
+// ---------------------------------------------------------------------------
+
+struct Obs {
+    float c[3];
+    uint32_t w;  // weight on the 2^-20 grid
+};
+
+// One thread per keyframe pixel; observations staged in LDS (dynamic,
+// n frames per thread).
+__global__ void color_kernel(const float* __restrict__ Z, const float* __restrict__ wz,
+                             const uint16_t* __restrict__ cs, const double* __restrict__ wb, int n,
+                             sc_intrinsics in, float occ_rel, const FuseFrames* __restrict__ fr, float* Zs, float* Ws,
+                             uint8_t* rgba)
+{
+    extern __shared__ Obs obs_lds[];
+    const int W = in.width, H = in.height;
+    const int64_t np = (int64_t)W * H;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= np) return;
+    Obs* obs = obs_lds + (size_t)threadIdx.x * n;
+    uint8_t* out = rgba + 4 * idx;
+    if (!(Ws[idx] > 0.0f)) {
+        out[0] = out[1] = out[2] = out[3] = 0;
+        return;
+    }
+    const int u = (int)(idx % W), v = (int)(idx / W);
+    float P[3];
+    backproject((float)u, (float)v, Zs[idx], in, P);
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        float q[3], uf, vf;
+        int iu, iv;
+        xform(fr->Rb[i], P, q);
+        if (!project(in, q, uf, vf, iu, iv)) continue;
+        const size_t base = (size_t)i * np;
+        const float wzi = wz[base + (size_t)iv * W + iu];
+        if (!(wzi > 0.0f)) continue;
+        if (!(fabsf(Z[base + (size_t)iv * W + iu] - q[2]) <= occ_rel * q[2])) continue;
+        const float x0 = floorf(uf), y0 = floorf(vf);
+        if (!(x0 >= 0.0f && x0 + 1.0f <= (float)(W - 1) && y0 >= 0.0f && y0 + 1.0f <= (float)(H - 1))) continue;
+        const float ax = uf - x0, ay = vf - y0;
+        const int ix = (int)x0, iy = (int)y0;
+        const float wc = (float)wb[i] * wzi;
+        const float wcs = rintf(wc * 1048576.0f);
+        if (!(wcs > 0.0f)) continue;
+        const uint16_t* C = cs + base * 3;
+        Obs o;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float c00 = (float)C[3 * ((size_t)iy * W + ix) + k], c10 = (float)C[3 * ((size_t)iy * W + ix + 1) + k];
+            const float c01 = (float)C[3 * ((size_t)(iy + 1) * W + ix) + k];
+            const float c11 = (float)C[3 * ((size_t)(iy + 1) * W + ix + 1) + k];
+            const float top = c00 + ax * (c10 - c00);
+            const float bot = c01 + ax * (c11 - c01);
+            o.c[k] = top + ay * (bot - top);
+        }
+        o.w = (uint32_t)wcs;
+        obs[m++] = o;
+    }
+    if (m == 0) {
+        Zs[idx] = 0.0f;
+        Ws[idx] = 0.0f;
+        out[0] = out[1] = out[2] = out[3] = 0;
+        return;
+    }
+    uint64_t total = 0;
+    for (int j = 0; j < m; ++j) total += obs[j].w;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // lower weighted median: the smallest (value, frame) whose cumulative
+        // weight in (value, frame) order reaches half the total
+        int best = -1;
+        float bc = 0.0f;
+        for (int j = 0; j < m; ++j) {
+            const float cj = obs[j].c[k];
+            uint64_t below = 0;
+            for (int l = 0; l < m; ++l) {
+                const float cl = obs[l].c[k];
+                if (cl < cj || (cl == cj && l < j)) below += obs[l].w;
+            }
+            if (2 * (below + obs[j].w) >= total) {
+                if (best < 0 || cj < bc) {
+                    best = j;
+                    bc = cj;
+                }
+            }
+        }
+        float val = rintf(bc / 256.0f);
+        val = fminf(fmaxf(val, 0.0f), 255.0f);
+        out[k] = (uint8_t)val;
+    }
+    out[3] = 255;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+
+struct FuseWs {
+    std::mutex mu;
+    int device = -1;
+    size_t cap_px = 0, cap_frames = 0;
+    float* wz = nullptr;
+    uint16_t* cs = nullptr;
+    unsigned long long* acc = nullptr;   // KW, KZ
+    unsigned long long* sums = nullptr;  // 4 per frame
+    double* wb = nullptr;
+    FuseFrames* d_fr = nullptr;
+    FuseFrames* h_fr = nullptr;
+    hipEvent_t staged = nullptr;
+};
+
+static FuseWs g_ws;
+
+static sc_status ws_reserve(size_t np, size_t frames)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (g_ws.device != dev) {
+        // a different device: start over (old buffers belong to another device)
+        g_ws.cap_px = g_ws.cap_frames = 0;
+        g_ws.wz = nullptr;
+        g_ws.cs = nullptr;
+        g_ws.acc = nullptr;
+        g_ws.sums = nullptr;
+        g_ws.wb = nullptr;
+        g_ws.d_fr = nullptr;
+        g_ws.h_fr = nullptr;
+        g_ws.staged = nullptr;
+        g_ws.device = dev;
+    }
+    if (!g_ws.d_fr) {
+        if (hipMalloc(&g_ws.d_fr, sizeof(FuseFrames)) != hipSuccess) return SC_ENOMEM;
+        if (hipHostMalloc((void**)&g_ws.h_fr, sizeof(FuseFrames), hipHostMallocDefault) != hipSuccess) return SC_ENOMEM;
+        if (hipEventCreateWithFlags(&g_ws.staged, hipEventDisableTiming) != hipSuccess) return SC_EDEVICE;
+        if (hipEventRecord(g_ws.staged, 0) != hipSuccess) return SC_EDEVICE;
+        if (hipMalloc(&g_ws.sums, sizeof(unsigned long long) * 4 * kMaxFrames) != hipSuccess) return SC_ENOMEM;
+        if (hipMalloc(&g_ws.wb, sizeof(double) * kMaxFrames) != hipSuccess) return SC_ENOMEM;
+    }
+    if (np * frames > g_ws.cap_px * g_ws.cap_frames || np > g_ws.cap_px) {
+        if (hipDeviceSynchronize() != hipSuccess) return SC_EDEVICE;
+        (void)hipFree(g_ws.wz);
+        (void)hipFree(g_ws.cs);
+        (void)hipFree(g_ws.acc);
+        const size_t px = std::max(np, g_ws.cap_px);
+        const size_t fr = std::max(frames, g_ws.cap_frames);
+        g_ws.wz = nullptr;
+        g_ws.cs = nullptr;
+        g_ws.acc = nullptr;
+        if (hipMalloc(&g_ws.wz, sizeof(float) * px * fr) != hipSuccess) return SC_ENOMEM;
+        if (hipMalloc(&g_ws.cs, sizeof(uint16_t) * 3 * px * fr) != hipSuccess) return SC_ENOMEM;
+        if (hipMalloc(&g_ws.acc, sizeof(unsigned long long) * 2 * px) != hipSuccess) return SC_ENOMEM;
+        g_ws.cap_px = px;
+        g_ws.cap_frames = fr;
+    }
+    return SC_OK;
+}
+
+static bool intr_valid(const sc_intrinsics* in)
+{
+    return in && in->width >= 3 && in->height >= 3 && in->fx > 0.0f && in->fy > 0.0f && in->width <= 16384 &&
+           in->height <= 16384;
+}
+
+// relative pose A^-1 B in FP64 with the written order, rounded to FP32
+static void rel_pose(const sc_pose& A, const sc_pose& B, float out[12])
+{
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            const double x = (A.R[0 * 3 + r] * B.R[0 * 3 + c] + A.R[1 * 3 + r] * B.R[1 * 3 + c]) + A.R[2 * 3 + r] * B.R[2 * 3 + c];
+            out[3 * r + c] = (float)x;
+        }
+        const double y = (A.R[0 * 3 + r] * (B.t[0] - A.t[0]) + A.R[1 * 3 + r] * (B.t[1] - A.t[1])) +
+                         A.R[2 * 3 + r] * (B.t[2] - A.t[2]);
+        out[9 + r] = (float)y;
+    }
+}
+
+static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& in, const sc_fuse_params& p, float* out,
+                                hipStream_t s)
+{
+    const int64_t np = (int64_t)in.width * in.height;
+    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n);
+    depth_weight_kernel<<<grid, 256, 0, s>>>(depth, n, in, p, out);
+}
+
+static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, double* wb, hipStream_t s)
+{
+    const int64_t np = (int64_t)W * H;
+    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n);
+    sharpen_kernel<<<grid, 256, 0, s>>>(rgb, n, W, H, sharp);
+    fill_u64(reinterpret_cast<uint64_t*>(g_ws.sums), 0ull, 4 * (size_t)n, s);
+    blur_sums_kernel<<<grid, 256, 0, s>>>(rgb, n, W, H, g_ws.sums);
+    blur_final_kernel<<<1, 64, 0, s>>>(g_ws.sums, n, wb);
+}
+
+}  // namespace sc
+
+using namespace sc;
+
+extern "C" {
+
+sc_status sc_depth_weight(const float* depth, int32_t n_frames, const sc_intrinsics* intr, const sc_fuse_params* params,
+                          float* wz_out, void* stream)
+{
+    if (!depth || !wz_out || n_frames <= 0 || n_frames > 65535 || !intr_valid(intr) || !params) return SC_EINVAL;
+    launch_depth_weight(depth, n_frames, *intr, *params, wz_out, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int32_t height, uint16_t* sharp_out,
+                        double* wb_out, void* stream)
+{
+    if (!rgb || !sharp_out || !wb_out || n_frames <= 0 || n_frames > kMaxFrames || width < 2 || height < 2 ||
+        width > 16384 || height > 16384)
+        return SC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    const sc_status st = ws_reserve((size_t)width * height, (size_t)n_frames);
+    if (st != SC_OK) return st;
+    launch_color_prep(rgb, n_frames, width, height, sharp_out, wb_out, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames, int32_t ref,
+                  const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth, float* kf_weight,
+                  uint8_t* kf_rgba, void* stream)
+{
+    if (!depth || !rgb || !poses || n_frames <= 0 || n_frames > kMaxFrames || ref < 0 || ref >= n_frames ||
+        !intr_valid(intr) || !params || !kf_depth || !kf_weight || !kf_rgba)
+        return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const sc_intrinsics in = *intr;
+    const int64_t np = (int64_t)in.width * in.height;
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    sc_status st = ws_reserve((size_t)np, (size_t)n_frames);
+    if (st != SC_OK) return st;
+    if (hipEventSynchronize(g_ws.staged) != hipSuccess) return SC_EDEVICE;
+    for (int i = 0; i < n_frames; ++i) {
+        rel_pose(poses[ref], poses[i], g_ws.h_fr->Rf[i]);
+        rel_pose(poses[i], poses[ref], g_ws.h_fr->Rb[i]);
+    }
+    if (hipMemcpyAsync(g_ws.d_fr, g_ws.h_fr, sizeof(FuseFrames), hipMemcpyHostToDevice, s) != hipSuccess)
+        return SC_EDEVICE;
+    if (hipEventRecord(g_ws.staged, s) != hipSuccess) return SC_EDEVICE;
+    // depth
+    launch_depth_weight(depth, n_frames, in, *params, g_ws.wz, s);
+    fill_u64(reinterpret_cast<uint64_t*>(g_ws.acc), 0ull, 2 * (size_t)np, s);
+    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
+    warp_kernel<<<grid, 256, 0, s>>>(depth, g_ws.wz, n_frames, in, g_ws.d_fr, g_ws.acc, g_ws.acc + np);
+    depth_final_kernel<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(g_ws.acc, g_ws.acc + np, np, kf_depth, kf_weight);
+    // colour
+    launch_color_prep(rgb, n_frames, in.width, in.height, g_ws.cs, g_ws.wb, s);
+    int threads = 256;
+    while (threads > 64 && (size_t)threads * n_frames * sizeof(Obs) > 48 * 1024) threads >>= 1;
+    const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
+    color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
+        depth, g_ws.wz, g_ws.cs, g_ws.wb, n_frames, in, params->occ_rel, g_ws.d_fr, kf_depth, kf_weight, kf_rgba);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+}  // extern "C"

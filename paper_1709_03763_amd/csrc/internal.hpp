@@ -1,0 +1,16 @@
+// Host-side helpers shared between the translation units of libscsurf.
+#pragma once
+
+#include "common.hpp"
+
+namespace sc {
+
+void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
+             int kf_index, OpDesc* op);
+bool keyframe_ok(const sc_keyframe* kf);
+sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
+                   hipStream_t s);
+
+}  // namespace sc

@@ -1,0 +1,495 @@
+// Voxel-hashed TSDF volume (Sec. 3, "SDF volume"): lifecycle, block
+// allocation, and the plain per-keyframe integration (running weighted
+// average) and de-integration (Sec. 4.3, Eq. 2).
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "internal.hpp"
+
+namespace sc {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void fill_u64_kernel(uint64_t* p, uint64_t v, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 8192);
+    fill_u64_kernel<<<grid, 256, 0, s>>>(p, v, n);
+}
+
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 8192);
+    fill_u32_kernel<<<grid, 256, 0, s>>>(p, v, n);
+}
+
+// ---------------------------------------------------------------------------
+// hash_alloc: wavefront ballot deduplication, CAS insert, LDS-staged queue
+// of new blocks and one pool reservation per workgroup
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void hash_alloc_kernel(VolDev v, const int32_t* xyz, int64_t n)
+{
+    __shared__ uint64_t s_key[256];
+    __shared__ uint32_t q_bucket[256];
+    __shared__ uint32_t q_n;
+    __shared__ uint32_t q_base;
+    const int tid = threadIdx.x;
+    const int wave0 = tid & ~63;
+    if (tid == 0) q_n = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    const bool have = i < n;
+    int bx = 0, by = 0, bz = 0;
+    uint64_t key = kKeyEmpty;
+    if (have) {
+        bx = xyz[3 * i];
+        by = xyz[3 * i + 1];
+        bz = xyz[3 * i + 2];
+        key = pack_key(bx, by, bz);
+    }
+    s_key[tid] = key;
+    __syncthreads();
+    // one leader per distinct key within each wavefront: the lowest lane holding it
+    bool leader = have;
+    for (int l = wave0; l < tid && leader; ++l) leader = s_key[l] != key;
+    if (leader) {
+        uint32_t h = hash_block(bx, by, bz) & v.bucket_mask;
+        bool done = false;
+        for (uint32_t probe = 0; probe <= v.bucket_mask; ++probe) {
+            const uint64_t old = atomicCAS((unsigned long long*)(v.keys + h), (unsigned long long)kKeyEmpty,
+                                           (unsigned long long)key);
+            if (old == kKeyEmpty) {
+                const uint32_t q = atomicAdd(&q_n, 1u);
+                q_bucket[q] = h;
+                done = true;
+                break;
+            }
+            if (old == key) {
+                done = true;
+                break;
+            }
+            h = (h + 1) & v.bucket_mask;
+        }
+        if (!done) set_error(v.err, SC_EHASHFULL);
+    }
+    __syncthreads();
+    if (tid == 0) q_base = q_n ? atomicAdd(v.n_blocks, q_n) : 0u;
+    __syncthreads();
+    for (uint32_t j = tid; j < q_n; j += blockDim.x) {
+        const uint32_t slot = q_base + j;
+        const uint32_t h = q_bucket[j];
+        if (slot >= (uint32_t)v.max_blocks) {
+            v.vals[h] = -1;
+            set_error(v.err, SC_EPOOLFULL);
+        } else {
+            v.slot_keys[slot] = v.keys[h];
+            v.vals[h] = (int)slot;
+        }
+    }
+}
+
+__global__ void hash_lookup_kernel(VolDev v, const int32_t* xyz, int64_t n, int32_t* slots)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int bx = xyz[3 * i], by = xyz[3 * i + 1], bz = xyz[3 * i + 2];
+    slots[i] = vol_find(v, pack_key(bx, by, bz), bx, by, bz);
+}
+
+// ---------------------------------------------------------------------------
+// plain path: one keyframe operation
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void cand_plain_kernel(OpDesc op, VolDev v, CandDev cd, int parity)
+{
+    __shared__ uint64_t lds[kLdsSet];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        cd.counters[1 - parity] = 0u;
+        cd.counters[2 + (1 - parity)] = 0u;
+    }
+    cand_tile(op, v, cd, cd.counters + parity, blockIdx.x, blockIdx.y, -1, lds);
+}
+
+// Applies one operation to one candidate block with one wavefront, eight
+// voxels per lane (lane = x + 8 y, loop over z), coalesced in brick order.
+template <int CM>
+__device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, int lane)
+{
+    int bx, by, bz;
+    unpack_key(key, bx, by, bz);
+    float q[3];
+    block_origin(op, v.s, bx, by, bz, q);
+    const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+    float base[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
+    uint32_t tmask = 0;
+    int pix[8];
+    float dd[8], ww[8];
+#pragma unroll
+    for (int kz = 0; kz < 8; ++kz) {
+        const float fz = (float)kz;
+        const float px = base[0] + fz * op.a[2][0];
+        const float py = base[1] + fz * op.a[2][1];
+        const float pz = base[2] + fz * op.a[2][2];
+        if (touch(op, v.mu, px, py, pz, pix[kz], ww[kz], dd[kz])) tmask |= 1u << kz;
+    }
+    if (__ballot(tmask != 0) == 0) return;
+    const int slot = (op.sign > 0) ? vol_insert_wave(v, key, bx, by, bz, lane) : (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
+    if (slot < 0) {
+        if (op.sign < 0) set_error(v.err, SC_ENOTALLOC);
+        return;
+    }
+    float* blk = v.pool + (size_t)slot * v.stride;
+    bool bad = false;
+#pragma unroll
+    for (int kz = 0; kz < 8; ++kz) {
+        if (!((tmask >> kz) & 1u)) continue;
+        const int i = lane + 64 * kz;
+        float D = blk[i], W = blk[512 + i];
+        if (CM == SC_COLOR_RGBA8) {
+            uint32_t* Cp = reinterpret_cast<uint32_t*>(blk) + 1024;
+            uint32_t C = Cp[i];
+            const uint32_t c = reinterpret_cast<const uint32_t*>(op.color)[pix[kz]];
+            bad |= !update_rgba8(D, W, C, dd[kz], ww[kz], c, op.sign);
+            Cp[i] = C;
+        } else {
+            float C[3] = {blk[1024 + i], blk[1536 + i], blk[2048 + i]};
+            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * pix[kz];
+            const float c[3] = {cp[0], cp[1], cp[2]};
+            bad |= !update_f32(D, W, C, dd[kz], ww[kz], c, op.sign);
+            blk[1024 + i] = C[0];
+            blk[1536 + i] = C[1];
+            blk[2048 + i] = C[2];
+        }
+        blk[i] = D;
+        blk[512 + i] = W;
+    }
+    if (__ballot(bad) != 0) set_error(v.err, SC_EWEIGHT);
+}
+
+// Persistent: each wavefront pops candidate blocks until the list is
+// exhausted (no lane-dependent branches in the loop).
+template <int CM>
+__global__ __launch_bounds__(256) void update_plain_kernel(OpDesc op, VolDev v, CandDev cd, int parity)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = min(cd.counters[parity], cd.cap);
+    for (;;) {
+        const uint32_t i = wave_fetch_add1(cd.counters + 2 + parity, lane);
+        if (i >= n) break;
+        const uint32_t h = bcast(cd.list[i]);
+        const uint64_t key = bcast64(cd.keys[h]);
+        block_one_op<CM>(op, v, key, lane);
+        cd.keys[h] = kKeyEmpty;
+    }
+}
+
+__global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float* W, void* C)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= n) return;
+    const float* blk = v.pool + (size_t)b * v.stride;
+    for (int i = threadIdx.x; i < kBlockVox; i += blockDim.x) {
+        if (D) D[b * kBlockVox + i] = blk[i];
+        if (W) W[b * kBlockVox + i] = blk[512 + i];
+        if (C) {
+            if (v.color_mode == SC_COLOR_RGBA8) {
+                reinterpret_cast<uint32_t*>(C)[b * kBlockVox + i] = reinterpret_cast<const uint32_t*>(blk)[1024 + i];
+            } else {
+                float* Cf = reinterpret_cast<float*>(C) + b * 3 * kBlockVox;
+                Cf[i] = blk[1024 + i];
+                Cf[512 + i] = blk[1536 + i];
+                Cf[1024 + i] = blk[2048 + i];
+            }
+        }
+    }
+    if (xyz && threadIdx.x == 0) {
+        int x, y, z;
+        unpack_key(v.slot_keys[b], x, y, z);
+        xyz[3 * b] = x;
+        xyz[3 * b + 1] = y;
+        xyz[3 * b + 2] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
+             int kf_index, OpDesc* op)
+{
+    memset(op, 0, sizeof(*op));
+    op->depth = kf->depth;
+    op->weight = kf->weight;
+    op->color = kf->color;
+    op->width = in->width;
+    op->height = in->height;
+    op->fx = in->fx;
+    op->fy = in->fy;
+    op->cx = in->cx;
+    op->cy = in->cy;
+    memcpy(op->R, T->R, sizeof(op->R));
+    memcpy(op->t, T->t, sizeof(op->t));
+    const double s = (double)vol->p.voxel_size;
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) op->a[c][r] = (float)(s * T->R[3 * c + r]);
+    op->sign = sign;
+    op->kf = kf_index;
+}
+
+static bool intr_ok(const sc_intrinsics* in)
+{
+    return in && in->width > 0 && in->height > 0 && in->fx > 0.0f && in->fy > 0.0f && in->width <= 16384 &&
+           in->height <= 16384;
+}
+
+bool keyframe_ok(const sc_keyframe* kf) { return kf && kf->depth && kf->weight && kf->color; }
+
+sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
+                   hipStream_t s)
+{
+    if (!vol || !keyframe_ok(kf) || !intr_ok(in) || !T) return SC_EINVAL;
+    OpDesc op;
+    make_op(vol, kf, in, T, sign, 0, &op);
+    const int p = vol->parity;
+    vol->parity ^= 1;
+    dim3 tiles((in->width + kTile - 1) / kTile, (in->height + kTile - 1) / kTile);
+    cand_plain_kernel<<<tiles, 256, 0, s>>>(op, vol->dev, vol->cand, p);
+    const int grid = vol->n_cu * 4;
+    if (vol->p.color_mode == SC_COLOR_RGBA8)
+        update_plain_kernel<SC_COLOR_RGBA8><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
+    else
+        update_plain_kernel<SC_COLOR_F32><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+}  // namespace sc
+
+using namespace sc;
+
+#define HIP_TRY(x)                                \
+    do {                                          \
+        if ((x) != hipSuccess) return SC_EDEVICE; \
+    } while (0)
+
+extern "C" {
+
+const char* sc_version(void) { return "scsurf 0.1 (gfx950)"; }
+
+sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
+{
+    if (!out) return SC_EINVAL;
+    *out = nullptr;
+    if (!p || !(p->voxel_size > 0.0f) || !(p->trunc > 0.0f) || !is_pow2(p->n_buckets) || p->n_buckets > (1ll << 30) ||
+        p->max_blocks <= 0 || p->max_blocks > (1ll << 30) ||
+        (p->color_mode != SC_COLOR_RGBA8 && p->color_mode != SC_COLOR_F32) || p->max_batch_ops <= 0 ||
+        p->max_batch_ops > kMaxBatchOps)
+        return SC_EINVAL;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SC_ENOLIB;
+    sc_volume* vol = new (std::nothrow) sc_volume();
+    if (!vol) return SC_ENOMEM;
+    memset(vol, 0, sizeof(*vol));
+    vol->p = *p;
+    vol->device = dev;
+    vol->n_cu = prop.multiProcessorCount;
+    vol->sched.vpl = 8;
+    vol->sched.waves_per_wg = 4;
+    vol->sched.wgs_per_cu = 4;
+    VolDev& d = vol->dev;
+    d.bucket_mask = (uint32_t)(p->n_buckets - 1);
+    d.max_blocks = (int32_t)p->max_blocks;
+    d.stride = (p->color_mode == SC_COLOR_RGBA8) ? 3 * kBlockVox : 5 * kBlockVox;
+    d.color_mode = p->color_mode;
+    d.s = p->voxel_size;
+    d.mu = p->trunc;
+    // candidate table: as many buckets as the volume, capped; one mask word per 64 batch operations
+    uint64_t cb = (uint64_t)std::min<int64_t>(std::max<int64_t>(p->n_buckets, 1 << 16), 1 << 23);
+    vol->cand_buckets = (uint32_t)cb;
+    CandDev& c = vol->cand;
+    c.mask_bits = (uint32_t)(cb - 1);
+    c.cap = (uint32_t)(cb / 2);
+    c.words = (p->max_batch_ops + 63) / 64;
+    bool ok = true;
+    ok &= hipMalloc(&d.keys, sizeof(uint64_t) * p->n_buckets) == hipSuccess;
+    ok &= hipMalloc(&d.vals, sizeof(int32_t) * p->n_buckets) == hipSuccess;
+    ok &= hipMalloc(&d.slot_keys, sizeof(uint64_t) * p->max_blocks) == hipSuccess;
+    ok &= hipMalloc(&d.pool, sizeof(float) * (size_t)d.stride * p->max_blocks) == hipSuccess;
+    ok &= hipMalloc(&d.n_blocks, 64) == hipSuccess;
+    ok &= hipMalloc(&d.err, 64) == hipSuccess;
+    ok &= hipMalloc(&c.keys, sizeof(uint64_t) * cb) == hipSuccess;
+    ok &= hipMalloc(&c.mask, sizeof(uint64_t) * cb * c.words) == hipSuccess;
+    ok &= hipMalloc(&c.list, sizeof(uint32_t) * c.cap) == hipSuccess;
+    ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * c.cap) == hipSuccess;
+    ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
+    ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
+    ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
+    ok &= hipHostMalloc((void**)&vol->h_ops, sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) == hipSuccess;
+    ok &= hipMalloc(&vol->d_hdr, sizeof(BatchHdr)) == hipSuccess;
+    ok &= hipHostMalloc((void**)&vol->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
+    ok &= hipStreamCreateWithFlags(&vol->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&vol->staged, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        sc_volume_destroy(vol);
+        return SC_ENOMEM;
+    }
+    hipStream_t s = 0;
+    sc_status st = sc_volume_reset(vol, s);
+    if (st == SC_OK && hipEventRecord(vol->staged, s) != hipSuccess) st = SC_EDEVICE;
+    if (st != SC_OK || hipStreamSynchronize(s) != hipSuccess) {
+        sc_volume_destroy(vol);
+        return SC_EDEVICE;
+    }
+    *out = vol;
+    return SC_OK;
+}
+
+void sc_volume_destroy(sc_volume* vol)
+{
+    if (!vol) return;
+    hipDeviceSynchronize();
+    for (auto& row : vol->graph)
+        for (auto& g : row)
+            if (g) hipGraphExecDestroy(g);
+    hipFree(vol->dev.keys);
+    hipFree(vol->dev.vals);
+    hipFree(vol->dev.slot_keys);
+    hipFree(vol->dev.pool);
+    hipFree(vol->dev.n_blocks);
+    hipFree(vol->dev.err);
+    hipFree(vol->cand.keys);
+    hipFree(vol->cand.mask);
+    hipFree(vol->cand.list);
+    hipFree(vol->cand.sorted);
+    hipFree(vol->cand.counters);
+    hipFree(vol->cand.bins);
+    hipFree(vol->d_ops);
+    hipFree(vol->d_hdr);
+    if (vol->h_ops) hipHostFree(vol->h_ops);
+    if (vol->h_hdr) hipHostFree(vol->h_hdr);
+    if (vol->cap_stream) hipStreamDestroy(vol->cap_stream);
+    if (vol->staged) hipEventDestroy(vol->staged);
+    delete vol;
+}
+
+sc_status sc_volume_reset(sc_volume* vol, void* stream)
+{
+    if (!vol) return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    fill_u64(vol->dev.keys, kKeyEmpty, (size_t)vol->p.n_buckets, s);
+    fill_u32(reinterpret_cast<uint32_t*>(vol->dev.vals), 0xFFFFFFFFu, (size_t)vol->p.n_buckets, s);
+    fill_u32(reinterpret_cast<uint32_t*>(vol->dev.pool), 0u, (size_t)vol->dev.stride * vol->p.max_blocks, s);
+    fill_u32(vol->dev.n_blocks, 0u, 16, s);
+    fill_u32(reinterpret_cast<uint32_t*>(vol->dev.err), 0u, 16, s);
+    const CandDev& c = vol->cand;
+    fill_u64(c.keys, kKeyEmpty, vol->cand_buckets, s);
+    fill_u64(c.mask, 0ull, (size_t)vol->cand_buckets * c.words, s);
+    fill_u32(c.counters, 0u, 64, s);
+    fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
+    vol->parity = 0;
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status sc_volume_query(sc_volume* vol, void* stream, int64_t* n_blocks, int32_t* sticky_error)
+{
+    if (!vol) return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t nb = 0;
+    int32_t e = 0;
+    HIP_TRY(hipMemcpyAsync(&nb, vol->dev.n_blocks, sizeof(nb), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&e, vol->dev.err, sizeof(e), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (n_blocks) *n_blocks = std::min<int64_t>((int64_t)nb, vol->p.max_blocks);
+    if (sticky_error) *sticky_error = e;
+    return SC_OK;
+}
+
+sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, float* D, float* W, void* C, int64_t cap,
+                           int64_t* n_out)
+{
+    if (!vol || cap < 0) return SC_EINVAL;
+    int64_t nb = 0;
+    sc_status st = sc_volume_query(vol, stream, &nb, nullptr);
+    if (st != SC_OK) return st;
+    const int64_t n = std::min(nb, cap);
+    hipStream_t s = (hipStream_t)stream;
+    if (n > 0) export_kernel<<<(unsigned)n, 256, 0, s>>>(vol->dev, n, block_xyz, D, W, C);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    if (n_out) *n_out = nb;
+    return SC_OK;
+}
+
+sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_t* slots_out, void* stream)
+{
+    if (!vol || n < 0 || (n > 0 && !block_xyz)) return SC_EINVAL;
+    if (n == 0) return SC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    hash_alloc_kernel<<<grid, 256, 0, s>>>(vol->dev, block_xyz, n);
+    if (slots_out) hash_lookup_kernel<<<grid, 256, 0, s>>>(vol->dev, block_xyz, n, slots_out);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status tsdf_integrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
+                         void* stream)
+{
+    return plain_op(vol, kf, intr, T, +1, (hipStream_t)stream);
+}
+
+sc_status tsdf_deintegrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
+                           void* stream)
+{
+    return plain_op(vol, kf, intr, T, -1, (hipStream_t)stream);
+}
+
+sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                            sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
+                            int32_t* selected_out, int32_t* n_selected, void* stream)
+{
+    if (!vol || !kfs || n_kf <= 0 || !T_integrated || !T_new || !intr_ok(intr)) return SC_EINVAL;
+    for (int i = 0; i < n_kf; ++i)
+        if (!keyframe_ok(&kfs[i])) return SC_EINVAL;
+    int32_t* order = new (std::nothrow) int32_t[n_kf];
+    if (!order) return SC_ENOMEM;
+    const int32_t ns = sc_select(T_integrated, T_new, n_kf, m, mode, order, nullptr);
+    if (ns < 0) {
+        delete[] order;
+        return ns;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    sc_status st = SC_OK;
+    for (int j = 0; j < ns && st == SC_OK; ++j) st = plain_op(vol, &kfs[order[j]], intr, &T_integrated[order[j]], -1, s);
+    for (int j = 0; j < ns && st == SC_OK; ++j) st = plain_op(vol, &kfs[order[j]], intr, &T_new[order[j]], +1, s);
+    if (st == SC_OK) {
+        for (int j = 0; j < ns; ++j) T_integrated[order[j]] = T_new[order[j]];
+        if (selected_out) memcpy(selected_out, order, sizeof(int32_t) * ns);
+        if (n_selected) *n_selected = ns;
+    }
+    delete[] order;
+    return st;
+}
+
+}  // extern "C"

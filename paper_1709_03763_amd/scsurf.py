@@ -1,0 +1,380 @@
+"""Thin Python binding of libscsurf (C ABI in include/scsurf.h).
+
+Argument marshalling only: torch supplies device memory and streams, every
+step of the hot path runs in the library's HIP kernels.  The binding fails
+loudly when the library is missing or the device is not gfx950; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscsurf.so")
+
+SC_OK, SC_EINVAL, SC_ENOMEM, SC_EHASHFULL, SC_EPOOLFULL, SC_ENOTALLOC, SC_EWEIGHT, SC_EDEVICE, SC_ENOLIB = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+SC_ERANGE = -9
+STATUS = {0: "SC_OK", -1: "SC_EINVAL", -2: "SC_ENOMEM", -3: "SC_EHASHFULL", -4: "SC_EPOOLFULL",
+          -5: "SC_ENOTALLOC", -6: "SC_EWEIGHT", -7: "SC_EDEVICE", -8: "SC_ENOLIB", -9: "SC_ERANGE"}
+COLOR_RGBA8, COLOR_F32 = 0, 1
+SEL_EQ3, SEL_TOPM, SEL_ALL_ORDERED = 0, 1, 2
+
+
+class ScError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class sc_intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class sc_pose(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3)]
+
+
+class sc_volume_params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("trunc", ctypes.c_float), ("n_buckets", ctypes.c_int64),
+                ("max_blocks", ctypes.c_int64), ("color_mode", ctypes.c_int32), ("max_batch_ops", ctypes.c_int32)]
+
+
+class sc_keyframe(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("color", ctypes.c_void_p)]
+
+
+class sc_fuse_params(ctypes.Structure):
+    _fields_ = [("z_min", ctypes.c_float), ("z_max", ctypes.c_float), ("disc_rel", ctypes.c_float),
+                ("occ_rel", ctypes.c_float)]
+
+
+class sc_schedule(ctypes.Structure):
+    _fields_ = [("vpl", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32)]
+
+
+EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
+           "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
+           "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
+           "sc_set_schedule", "sc_get_schedule", "sc_autotune", "tsdf_integrate_backward"]
+
+_lib = None
+
+
+def lib():
+    """Loads libscsurf.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libscsurf.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.sc_version.restype = ctypes.c_char_p
+    L.sc_volume_create.argtypes = [ctypes.POINTER(sc_volume_params), ctypes.POINTER(P)]
+    L.sc_volume_destroy.argtypes = [P]
+    L.sc_volume_destroy.restype = None
+    L.sc_volume_reset.argtypes = [P, P]
+    L.sc_volume_query.argtypes = [P, P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.sc_volume_export.argtypes = [P, P, P, P, P, P, i64, ctypes.POINTER(i64)]
+    L.sc_depth_weight.argtypes = [P, i32, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_fuse_params), P, P]
+    L.sc_color_prep.argtypes = [P, i32, i32, i32, P, P, P]
+    L.kf_fuse.argtypes = [P, P, ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_intrinsics),
+                          ctypes.POINTER(sc_fuse_params), P, P, P, P]
+    L.hash_alloc.argtypes = [P, P, i64, P, P]
+    for f in (L.tsdf_integrate, L.tsdf_deintegrate):
+        f.argtypes = [P, ctypes.POINTER(sc_keyframe), ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), P]
+    L.sc_select.argtypes = [ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, i32, P, P]
+    L.sc_select_dist.argtypes = [P, i32, i32, i32, P]
+    for f in (L.reintegrate_batch, L.reintegrate_plain):
+        f.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose),
+                      ctypes.POINTER(sc_pose), i32, i32, P, ctypes.POINTER(i32), P]
+    L.sc_set_schedule.argtypes = [P, ctypes.POINTER(sc_schedule)]
+    L.sc_get_schedule.argtypes = [P, ctypes.POINTER(sc_schedule)]
+    L.sc_autotune.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
+                              ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_schedule),
+                              ctypes.POINTER(ctypes.c_float), P]
+    L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
+                                          ctypes.POINTER(sc_pose), P, P, P, P, P, P]
+    for name in EXPORTS:
+        if name != "sc_version" and name != "sc_volume_destroy":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def check(status: int, what: str):
+    if status != SC_OK:
+        raise ScError(status, what)
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+
+
+def stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def dptr(t: torch.Tensor, dtype=None, what="tensor") -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def intrinsics(intr) -> sc_intrinsics:
+    return sc_intrinsics(float(intr.fx), float(intr.fy), float(intr.cx), float(intr.cy), int(intr.width),
+                         int(intr.height))
+
+
+def pose(R, t) -> sc_pose:
+    p = sc_pose()
+    p.R[:] = [float(x) for x in np.asarray(R, np.float64).reshape(9)]
+    p.t[:] = [float(x) for x in np.asarray(t, np.float64).reshape(3)]
+    return p
+
+
+def poses(R, t):
+    R = np.asarray(R, np.float64).reshape(-1, 3, 3)
+    t = np.asarray(t, np.float64).reshape(-1, 3)
+    arr = (sc_pose * len(R))()
+    for i in range(len(R)):
+        arr[i] = pose(R[i], t[i])
+    return arr
+
+
+def poses_to_numpy(arr):
+    R = np.array([np.array(p.R[:]).reshape(3, 3) for p in arr])
+    t = np.array([np.array(p.t[:]) for p in arr])
+    return R, t
+
+
+@dataclass
+class Keyframe:
+    """A fused keyframe on the device: depth Z* (H,W) f32, weight W* (H,W) f32,
+    colour RGBA8 (H,W,4) u8 or F32 (H,W,3) f32."""
+    depth: torch.Tensor
+    weight: torch.Tensor
+    color: torch.Tensor
+
+    def c(self) -> sc_keyframe:
+        return sc_keyframe(dptr(self.depth, torch.float32, "depth"), dptr(self.weight, torch.float32, "weight"),
+                           dptr(self.color, None, "color"))
+
+
+def keyframes(kfs):
+    arr = (sc_keyframe * len(kfs))()
+    for i, k in enumerate(kfs):
+        arr[i] = k.c()
+    return arr
+
+
+def fuse_params(z_min=0.3, z_max=4.0, disc_rel=0.05, occ_rel=0.05) -> sc_fuse_params:
+    return sc_fuse_params(z_min, z_max, disc_rel, occ_rel)
+
+
+# ----------------------------------------------------------------------------
+# API
+# ----------------------------------------------------------------------------
+
+
+def version() -> str:
+    return lib().sc_version().decode()
+
+
+class Volume:
+    """Voxel-hashed TSDF owned by the library (Sec. 3, SDF volume)."""
+
+    def __init__(self, voxel_size: float, trunc: float, n_buckets: int, max_blocks: int, color_mode: int = COLOR_RGBA8,
+                 max_batch_ops: int = 512):
+        self.params = sc_volume_params(voxel_size, trunc, n_buckets, max_blocks, color_mode, max_batch_ops)
+        self.color_mode = color_mode
+        self._h = ctypes.c_void_p()
+        check(lib().sc_volume_create(ctypes.byref(self.params), ctypes.byref(self._h)), "sc_volume_create")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sc_volume_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self, stream=None):
+        check(lib().sc_volume_reset(self._h, stream_handle(stream)), "sc_volume_reset")
+
+    def query(self, stream=None):
+        n = ctypes.c_int64()
+        e = ctypes.c_int32()
+        check(lib().sc_volume_query(self._h, stream_handle(stream), ctypes.byref(n), ctypes.byref(e)),
+              "sc_volume_query")
+        return int(n.value), int(e.value)
+
+    def export(self, stream=None):
+        """Allocated blocks in pool order: dict of device tensors."""
+        n, _ = self.query(stream)
+        dev = torch.device("cuda")
+        xyz = torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev)
+        D = torch.empty((max(n, 1), 512), dtype=torch.float32, device=dev)
+        W = torch.empty((max(n, 1), 512), dtype=torch.float32, device=dev)
+        if self.color_mode == COLOR_RGBA8:
+            C = torch.empty((max(n, 1), 512, 4), dtype=torch.uint8, device=dev)
+        else:
+            C = torch.empty((max(n, 1), 3, 512), dtype=torch.float32, device=dev)
+        nout = ctypes.c_int64()
+        check(lib().sc_volume_export(self._h, stream_handle(stream), xyz.data_ptr(), D.data_ptr(), W.data_ptr(),
+                                     C.data_ptr(), n, ctypes.byref(nout)), "sc_volume_export")
+        return {"blocks": xyz[:n], "D": D[:n], "W": W[:n], "C": C[:n]}
+
+    def export_sorted(self, stream=None):
+        """Allocated blocks sorted by (x, y, z) as NumPy arrays; colour as
+        (n, 512, 3) in RGB order."""
+        f = {k: v.cpu().numpy() for k, v in self.export(stream).items()}
+        b = f["blocks"].astype(np.int64)
+        order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
+        C = f["C"][order]
+        C = C[..., :3] if self.color_mode == COLOR_RGBA8 else np.transpose(C, (0, 2, 1))
+        return {"blocks": b[order], "D": f["D"][order], "W": f["W"][order], "C": C}
+
+    def check_error(self, stream=None):
+        n, e = self.query(stream)
+        check(e, "device error")
+        return n
+
+    def integrate(self, kf: Keyframe, intr, R, t, stream=None):
+        k = kf.c()
+        check(lib().tsdf_integrate(self._h, ctypes.byref(k), ctypes.byref(intrinsics(intr)), ctypes.byref(pose(R, t)),
+                                   stream_handle(stream)), "tsdf_integrate")
+
+    def deintegrate(self, kf: Keyframe, intr, R, t, stream=None):
+        k = kf.c()
+        check(lib().tsdf_deintegrate(self._h, ctypes.byref(k), ctypes.byref(intrinsics(intr)),
+                                     ctypes.byref(pose(R, t)), stream_handle(stream)), "tsdf_deintegrate")
+
+    def hash_alloc(self, block_xyz: torch.Tensor, want_slots=True, stream=None):
+        n = block_xyz.shape[0]
+        slots = torch.empty(n, dtype=torch.int32, device=block_xyz.device) if want_slots else None
+        check(lib().hash_alloc(self._h, dptr(block_xyz, torch.int32, "block_xyz"), n,
+                               slots.data_ptr() if slots is not None else None, stream_handle(stream)), "hash_alloc")
+        return slots
+
+    def _reint(self, fn, kfs, intr, T_int, T_new, m, mode, stream):
+        karr = keyframes(kfs)
+        Ti = poses(*T_int)
+        Tn = poses(*T_new)
+        sel = (ctypes.c_int32 * len(kfs))()
+        ns = ctypes.c_int32()
+        check(fn(self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), Ti, Tn, m, mode, sel, ctypes.byref(ns),
+                 stream_handle(stream)), fn.__name__)
+        R, t = poses_to_numpy(Ti)
+        return list(sel[:ns.value]), (R, t)
+
+    def reintegrate_batch(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
+        """One pose-graph update, batched.  Returns (processing order, updated
+        integration poses (R, t))."""
+        return self._reint(lib().reintegrate_batch, kfs, intr, T_int, T_new, m, mode, stream)
+
+    def reintegrate_plain(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
+        return self._reint(lib().reintegrate_plain, kfs, intr, T_int, T_new, m, mode, stream)
+
+    def set_schedule(self, vpl, waves_per_wg, wgs_per_cu):
+        s = sc_schedule(vpl, waves_per_wg, wgs_per_cu)
+        check(lib().sc_set_schedule(self._h, ctypes.byref(s)), "sc_set_schedule")
+
+    def get_schedule(self):
+        s = sc_schedule()
+        check(lib().sc_get_schedule(self._h, ctypes.byref(s)), "sc_get_schedule")
+        return (s.vpl, s.waves_per_wg, s.wgs_per_cu)
+
+    def autotune(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
+        karr = keyframes(kfs)
+        best = sc_schedule()
+        ms = ctypes.c_float()
+        check(lib().sc_autotune(self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), poses(*T_int),
+                                poses(*T_new), m, mode, ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)),
+              "sc_autotune")
+        return (best.vpl, best.waves_per_wg, best.wgs_per_cu), float(ms.value)
+
+    def integrate_backward(self, kfs, intr, R, t, grad_D, grad_C, grad_depth, grad_color, grad_xi, stream=None):
+        karr = keyframes(kfs)
+        check(lib().tsdf_integrate_backward(
+            self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), poses(R, t), dptr(grad_D, torch.float32, "grad_D"),
+            dptr(grad_C, torch.float32, "grad_C") if grad_C is not None else None,
+            dptr(grad_depth, torch.float32, "grad_depth"),
+            dptr(grad_color, torch.float32, "grad_color") if grad_color is not None else None,
+            dptr(grad_xi, torch.float32, "grad_xi"), stream_handle(stream)), "tsdf_integrate_backward")
+
+
+def select(T_int, T_new, m, mode=SEL_EQ3):
+    """Host selection (Sec. 4.3): (processing order, distances)."""
+    Ti = poses(*T_int)
+    Tn = poses(*T_new)
+    K = len(Ti)
+    out = (ctypes.c_int32 * max(K, 1))()
+    dist = (ctypes.c_double * max(K, 1))()
+    n = lib().sc_select(Ti, Tn, K, m, mode, out, dist)
+    if n < 0:
+        raise ScError(n, "sc_select")
+    return list(out[:n]), np.array(dist[:K])
+
+
+def select_dist(dist, m, mode=SEL_EQ3):
+    d = np.ascontiguousarray(dist, np.float64)
+    K = len(d)
+    out = (ctypes.c_int32 * max(K, 1))()
+    n = lib().sc_select_dist(d.ctypes.data_as(ctypes.c_void_p), K, m, mode, out)
+    if n < 0:
+        raise ScError(n, "sc_select_dist")
+    return list(out[:n])
+
+
+def depth_weight(depth: torch.Tensor, intr, params=None, stream=None) -> torch.Tensor:
+    depth = depth if depth.dim() == 3 else depth[None]
+    out = torch.empty_like(depth)
+    p = params or fuse_params()
+    check(lib().sc_depth_weight(dptr(depth, torch.float32, "depth"), depth.shape[0], ctypes.byref(intrinsics(intr)),
+                                ctypes.byref(p), out.data_ptr(), stream_handle(stream)), "sc_depth_weight")
+    return out
+
+
+def color_prep(rgb: torch.Tensor, stream=None):
+    rgb = rgb if rgb.dim() == 4 else rgb[None]
+    n, H, W, _ = rgb.shape
+    sharp = torch.empty((n, H, W, 3), dtype=torch.uint16, device=rgb.device)
+    wb = torch.empty(n, dtype=torch.float64, device=rgb.device)
+    check(lib().sc_color_prep(dptr(rgb, torch.uint8, "rgb"), n, W, H, sharp.data_ptr(), wb.data_ptr(),
+                              stream_handle(stream)), "sc_color_prep")
+    return sharp, wb
+
+
+def kf_fuse(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref=0, stream=None) -> Keyframe:
+    """Fuses frames (n,H,W) / (n,H,W,3) at poses (R, t) into one keyframe."""
+    n, H, W = depth.shape
+    dev = depth.device
+    kd = torch.empty((H, W), dtype=torch.float32, device=dev)
+    kw = torch.empty((H, W), dtype=torch.float32, device=dev)
+    kc = torch.empty((H, W, 4), dtype=torch.uint8, device=dev)
+    p = params or fuse_params()
+    check(lib().kf_fuse(dptr(depth, torch.float32, "depth"), dptr(rgb, torch.uint8, "rgb"), poses(R, t), n, ref,
+                        ctypes.byref(intrinsics(intr)), ctypes.byref(p), kd.data_ptr(), kw.data_ptr(), kc.data_ptr(),
+                        stream_handle(stream)), "kf_fuse")
+    return Keyframe(kd, kw, kc)

@@ -1,0 +1,173 @@
+"""GPU parity of the batched re-integration (Sec. 4.3): one pose-graph update
+applied in one graph-captured sequence with a persistent voxel pass, against
+the FP64 oracle's sequential de-integrations and re-integrations and against
+the plain per-keyframe path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import selection as osel
+from paper_1709_03763_amd import scsurf, synth
+from tests.helpers import as_f32_color, compare_fields, oracle_keyframes
+
+pytestmark = pytest.mark.gpu
+
+S, MU = 0.01, 0.04
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _dev_kf(kf, f32=False):
+    c = np.ascontiguousarray(kf["color"], np.float32 if f32 else np.uint8)
+    return scsurf.Keyframe(torch.from_numpy(np.ascontiguousarray(kf["depth"])).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(kf["weight"])).cuda(), torch.from_numpy(c).cuda())
+
+
+@pytest.fixture(scope="module")
+def scene():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(3)
+    groups = [np.arange(5) + 5 * k for k in range(0, 16, 2)]
+    kfs = oracle_keyframes(wl, groups)
+    R = np.array([wl.R[g[0]] for g in groups])
+    t = np.array([wl.t[g[0]] for g in groups])
+    return wl, kfs, R, t
+
+
+def _integrated(wl, kfs, R, t, f32=False, **kw):
+    mode = scsurf.COLOR_F32 if f32 else scsurf.COLOR_RGBA8
+    vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16, color_mode=mode, **kw)
+    okf = [as_f32_color(k) for k in kfs] if f32 else kfs
+    dks = [_dev_kf(k, f32) for k in okf]
+    ref = oracle.Volume(S, MU, color_f32=f32)
+    for k in range(len(kfs)):
+        vol.integrate(dks[k], wl.intr, R[k], t[k])
+        assert ref.integrate(okf[k], wl.intr, R[k], t[k]) == oracle.OK
+    return vol, ref, dks, okf
+
+
+def _oracle_update(ref, okf, wl, R, t, Rn, tn, order):
+    for k in order:
+        assert ref.deintegrate(okf[k], wl.intr, R[k], t[k]) == oracle.OK
+    for k in order:
+        assert ref.integrate(okf[k], wl.intr, Rn[k], tn[k]) == oracle.OK
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("mode", [scsurf.SEL_EQ3, scsurf.SEL_TOPM, scsurf.SEL_ALL_ORDERED])
+def test_batch_matches_oracle_and_plain(scene, f32, mode):
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 11)
+    _say(f"batch f32={f32} mode={mode}")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t, f32)
+    order, (Ru, tu) = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 4, mode)
+    exp = osel.select(osel.distances(R, t, Rn, tn), 4, mode)
+    assert order == exp
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, exp)
+    vol.check_error()
+    gb = vol.export_sorted()
+    compare_fields(gb, ref.export(), exact_color=not f32)
+    # the plain path applies the same operations in the same order per voxel:
+    # identical bits
+    _say(f"plain f32={f32} mode={mode}")
+    vol2, _, dks2, _ = _integrated(wl, kfs, R, t, f32)
+    vol2.reintegrate_plain(dks2, wl.intr, (R, t), (Rn, tn), 4, mode)
+    vol2.check_error()
+    gp = vol2.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(gb[key], gp[key])
+    vol.close()
+    vol2.close()
+
+
+@pytest.mark.parametrize("sched", [(8, 4, 4), (8, 4, 1), (4, 2, 8), (2, 4, 4), (1, 8, 2)])
+def test_every_schedule_gives_identical_bits(scene, sched):
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 5)
+    _say(f"schedule {sched}")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t)
+    vol.set_schedule(*sched)
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
+    vol.check_error()
+    compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
+def test_graph_replays_across_successive_updates(scene):
+    """Several pose-graph updates in a row reuse the captured graph; every
+    state must match the oracle (replays after the first included)."""
+    wl, kfs, R, t = scene
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t)
+    Rc, tc = R.copy(), t.copy()
+    for u in range(4):
+        Rn, tn = synth.perturb_all(Rc, tc, 0.01, 0.5, 100 + u)
+        _say(f"update {u}")
+        order, (Rc2, tc2) = vol.reintegrate_batch(dks, wl.intr, (Rc, tc), (Rn, tn), 3, scsurf.SEL_EQ3)
+        exp = osel.select(osel.distances(Rc, tc, Rn, tn), 3, scsurf.SEL_EQ3)
+        assert order == exp
+        _oracle_update(ref, okf, wl, Rc, tc, Rn, tn, exp)
+        Rc, tc = Rc2, tc2
+        vol.check_error()
+        compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
+def test_chunked_batches_match(scene):
+    """More operations than one batch holds: processed in consecutive chunks
+    with the same per-voxel order."""
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 3)
+    _say("chunked")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t, max_batch_ops=3)
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    assert len(order) == len(kfs)
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
+    vol.check_error()
+    compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
+def test_autotune_leaves_volume_unchanged(scene):
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 9)
+    _say("autotune")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t)
+    before = vol.export_sorted()
+    best, ms = vol.autotune(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    assert best[0] in (8, 4, 2, 1) and ms > 0
+    assert vol.get_schedule() == best
+    after = vol.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(before[key], after[key])
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
+    vol.check_error()
+    compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
+def test_batch_detects_unallocated_deintegration(scene):
+    wl, kfs, R, t = scene
+    _say("batch ENOTALLOC")
+    vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+    dks = [_dev_kf(k) for k in kfs[:2]]
+    Rn, tn = synth.perturb_all(R[:2], t[:2], 0.02, 1.0, 1)
+    vol.reintegrate_batch(dks, wl.intr, (R[:2], t[:2]), (Rn, tn), 2, scsurf.SEL_EQ3)
+    assert vol.query()[1] == scsurf.SC_ENOTALLOC
+    vol.close()
+
+
+def test_no_pose_change_selects_nothing(scene):
+    wl, kfs, R, t = scene
+    _say("empty update")
+    vol, ref, dks, okf = _integrated(wl, kfs[:3], R[:3], t[:3])
+    before = vol.export_sorted()
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R[:3], t[:3]), (R[:3], t[:3]), 3, scsurf.SEL_ALL_ORDERED)
+    assert order == []
+    after = vol.export_sorted()
+    np.testing.assert_array_equal(before["D"], after["D"])
+    vol.close()

@@ -1,0 +1,56 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and its host-only selection matches the oracle's (Sec. 4.3)."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import selection as osel
+from paper_1709_03763_amd import scsurf, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "scsurf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:sc_status|int32_t|void|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = scsurf.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(scsurf.EXPORTS)
+    assert scsurf.version().startswith("scsurf")
+
+
+def test_library_selection_fig4():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "fig4_selection.json")))
+    d = np.array(g["distance"], float)
+    assert [i + 1 for i in scsurf.select_dist(d, g["m"], scsurf.SEL_EQ3)] == g["eq3_frames_1based"]
+    assert [i + 1 for i in scsurf.select_dist(d, g["m"], scsurf.SEL_TOPM)] == g["topm_frames_1based"]
+
+
+@pytest.mark.parametrize("mode", [scsurf.SEL_EQ3, scsurf.SEL_TOPM, scsurf.SEL_ALL_ORDERED])
+def test_library_selection_matches_oracle(mode):
+    wl = synth.workload(4)
+    R, t = wl.R[::5], wl.t[::5]
+    for seed in range(3):
+        Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, seed)
+        Rn[:50], tn[:50] = R[:50], t[:50]  # unchanged keyframes
+        order, dist = scsurf.select((R, t), (Rn, tn), 20, mode)
+        od = osel.distances(R, t, Rn, tn)
+        np.testing.assert_array_equal(dist, od)
+        assert order == osel.select(od, 20, mode)
+
+
+def test_library_rejects_bad_arguments():
+    with pytest.raises(scsurf.ScError):
+        scsurf.select_dist([1.0, 2.0], 0, scsurf.SEL_EQ3)
+    with pytest.raises(scsurf.ScError):
+        scsurf.select_dist([1.0, 2.0], 1, 7)
