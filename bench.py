@@ -1,0 +1,326 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched surface correction on one MI355X.
+
+Workload (the batched re-integration configuration): a 10 x 10 x 3 m room
+with 40 seeded boxes and spheres, 1000 synthetic 640x480 RGB-D frames fused
+5 per keyframe into 200 keyframes (kf_fuse), each keyframe cut to a seeded
+valid-pixel fraction in [0.4, 1.0] by a contiguous column strip, integrated
+into a voxel-hashed TSDF (1 cm voxels, 4 cm truncation, 2^21 buckets, FP32
+TSDF + RGBA8 colour + FP32 weight).  A pose-graph update moves all 200 poses
+by N(0, 3 cm / 1.5 deg); one step re-integrates every changed keyframe in
+order of pose change (de-integrate at the integration pose, re-integrate at
+the new pose) with reintegrate_batch.  Steps alternate between the two pose
+sets, so every step has the same amount of work.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "keyframes re-integrated/sec (de+re) and voxel updates/sec; % of HBM peak"
+HBM_PEAK_GBS = 8000.0
+VOXEL_BYTES = 12  # FP32 D + FP32 W + RGBA8 colour
+KF_PIXEL_BYTES = 12  # keyframe depth + weight + RGBA8 colour
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_main_traffic.json")
+KERNEL_SOURCES = ["paper_1709_03763_amd/csrc/batch.hip", "paper_1709_03763_amd/csrc/kernels.hpp",
+                  "paper_1709_03763_amd/csrc/common.hpp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def build_workload(torch, scsurf, synth, n_kf, seed):
+    wl = synth.workload(4)
+    groups = synth.keyframe_groups(wl)[:n_kf]
+    dev = torch.device("cuda")
+    log(f"rendering {n_kf * wl.kappa} frames at {wl.intr.width}x{wl.intr.height}")
+    t0 = time.time()
+    frames = []
+    for g0 in range(0, n_kf, 20):
+        gs = groups[g0:g0 + 20]
+        idx = np.concatenate(gs)
+        z, rgb = synth.frames(wl, idx, device="cuda")
+        for j, g in enumerate(gs):
+            frames.append((z[j * wl.kappa:(j + 1) * wl.kappa], rgb[j * wl.kappa:(j + 1) * wl.kappa], g))
+        log(f"  rendered {min(g0 + 20, n_kf)}/{n_kf} keyframe groups ({time.time() - t0:.0f} s)")
+    # keyframe fusion, timed as a stage
+    dz = [torch.from_numpy(f[0]).to(dev) for f in frames]
+    dc = [torch.from_numpy(f[1]).to(dev) for f in frames]
+    torch.cuda.synchronize()
+    kfs = []
+    t0 = time.perf_counter()
+    for k, (z, rgb, g) in enumerate(frames):
+        kfs.append(scsurf.kf_fuse(dz[k], dc[k], wl.R[g], wl.t[g], wl.intr))
+    torch.cuda.synchronize()
+    fuse_s = time.perf_counter() - t0
+    del dz, dc
+    # uneven valid-pixel fractions
+    rng = np.random.default_rng(seed)
+    fracs = rng.uniform(0.4, 1.0, n_kf)
+    for k, kf in enumerate(kfs):
+        valid = kf.weight.cpu().numpy() > 0
+        keep = torch.from_numpy(synth.column_strip_mask(valid, fracs[k], rng)).to(dev)
+        kf.depth.mul_(keep)
+        kf.weight.mul_(keep)
+        kf.color.mul_(keep[..., None].to(torch.uint8))
+    R = np.array([wl.R[g[0]] for g in groups])
+    t = np.array([wl.t[g[0]] for g in groups])
+    return wl, kfs, R, t, fuse_s, fracs
+
+
+def cpu_baseline(oracle, kfs_np, intr, A, B, sample):
+    """The oracle re-integrating a sample of keyframes (FP64, host cores)."""
+    vol = oracle.Volume(0.01, 0.04)
+    for k in sample:
+        vol.integrate(kfs_np[k], intr, A[0][k], A[1][k])
+    t0 = time.perf_counter()
+    for k in sample:
+        assert vol.deintegrate(kfs_np[k], intr, A[0][k], A[1][k]) == oracle.OK
+    for k in sample:
+        assert vol.integrate(kfs_np[k], intr, B[0][k], B[1][k]) == oracle.OK
+    dt = time.perf_counter() - t0
+    return len(sample) / dt, dt
+
+
+def adjoint_stage(torch, scsurf, synth):
+    """Forward + backward of integration on the differentiation workload
+    (16 keyframes at 320x240, F32 colour), timed."""
+    from paper_1709_03763_amd import autograd as sca
+
+    wl = synth.workload(3)
+    groups = synth.keyframe_groups(wl)
+    z, rgb = synth.frames(wl, np.arange(wl.n_frames), device="cuda")
+    dev = torch.device("cuda")
+    kfs = [scsurf.kf_fuse(torch.from_numpy(z[g]).to(dev), torch.from_numpy(rgb[g]).to(dev), wl.R[g], wl.t[g], wl.intr)
+           for g in groups]
+    depth = torch.stack([k.depth for k in kfs]).requires_grad_(True)
+    color = torch.stack([k.color[..., :3].float() / 255.0 for k in kfs]).requires_grad_(True)
+    weight = torch.stack([k.weight for k in kfs])
+    xi = torch.zeros((len(kfs), 6), device=dev, requires_grad=True)
+    R = np.array([wl.R[g[0]] for g in groups])
+    t = np.array([wl.t[g[0]] for g in groups])
+    vol = scsurf.Volume(0.01, 0.04, 1 << 17, 1 << 16, color_mode=scsurf.COLOR_F32)
+    times = []
+    for rep in range(4):
+        for p in (depth, color, xi):
+            p.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D, C, W = sca.integrate(depth, color, weight, xi, vol, wl.intr, R, t)
+        loss = ((D * (W > 0)) ** 2).sum() + 0.1 * ((C - 0.5) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    vol.close()
+    return float(np.median(times[1:]) * 1e3)
+
+
+def traffic_from_profile(digest, launches_bytes):
+    """HBM bytes per launch of the voxel pass from the committed rocprofv3
+    counter summary, if it was taken from the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--keyframes", type=int, default=200)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run a device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the surface-correction path runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import oracle
+    from paper_1709_03763_amd import scsurf, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    scsurf.lib()
+    n_kf = args.keyframes
+    wl, kfs, R, t, fuse_s, fracs = build_workload(torch, scsurf, synth, n_kf, seed=4)
+    H, Wd = wl.intr.height, wl.intr.width
+    log(f"fused {n_kf} keyframes in {fuse_s * 1e3:.1f} ms")
+    A = (R, t)
+    B = synth.perturb_all(R, t, 0.03, 1.5, 4)
+    vol = scsurf.Volume(0.01, 0.04, 1 << 21, 1 << 21, scsurf.COLOR_RGBA8, max_batch_ops=512)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_kf):
+        vol.integrate(kfs[k], wl.intr, R[k], t[k])
+    torch.cuda.synchronize()
+    integrate_s = time.perf_counter() - t0
+    n_blocks = vol.check_error()
+    log(f"integrated {n_kf} keyframes in {integrate_s * 1e3:.1f} ms; {n_blocks} blocks")
+    mode = scsurf.SEL_ALL_ORDERED
+    state = [A, B]  # state[0] = current integration poses, state[1] = the other set
+
+    def step(fn):
+        order, _ = fn(kfs, wl.intr, state[0], state[1], n_kf, mode)
+        state[0], state[1] = state[1], state[0]
+        return order
+
+    sched = vol.get_schedule()
+    tune_ms = None
+    if not args.no_autotune:
+        sched, tune_ms = vol.autotune(kfs, wl.intr, state[0], state[1], n_kf, mode)
+        log(f"autotuned schedule {sched} ({tune_ms:.2f} ms)")
+    order = []
+    for _ in range(args.warmup):
+        order = step(vol.reintegrate_batch)
+    torch.cuda.synchronize()
+    vol.check_error()
+    n_sel = len(order) if order else n_kf
+    n_ops = 2 * n_sel
+    # timed region
+    vol.batch_timing(args.steps)
+    s0 = vol.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        order = step(vol.reintegrate_batch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    main_ms = vol.batch_timing_read()
+    s1 = vol.stats()
+    vol.batch_timing(0)
+    n_blocks_after = vol.check_error()
+    if len(main_ms) != args.steps:
+        raise RuntimeError(f"voxel-pass timing events recorded {len(main_ms)} of {args.steps} launches")
+    n_sel = len(order)
+    n_ops = 2 * n_sel
+    cand, pairs, upd, written = [(b - a) / args.steps for a, b in zip(s0, s1)]
+    log(f"batched: {ms_per_step:.3f} ms/step, voxel pass {np.mean(main_ms):.3f} ms, "
+        f"{cand:.0f} candidate blocks, {written:.0f} written, {upd / 1e6:.1f} M voxel updates, "
+        f"{n_blocks_after} blocks allocated")
+    value = n_sel / (ms_per_step / 1e3)
+    pass_ms = float(np.mean(main_ms))
+    alg_bytes = written * 512 * 2 * VOXEL_BYTES + n_ops * H * Wd * KF_PIXEL_BYTES
+    achieved = alg_bytes / (pass_ms / 1e3) / 1e9
+    digest = source_digest()
+    traffic = traffic_from_profile(digest, alg_bytes)
+
+    plain = None
+    if not args.no_plain and args.plain_steps > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(vol.reintegrate_plain)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+        vol.check_error()
+        plain = {"ms_per_step": round(pms, 3), "keyframes_per_s": round(n_sel / (pms / 1e3), 1),
+                 "batched_speedup": round(pms / ms_per_step, 2)}
+        log(f"plain: {pms:.3f} ms/step ({plain['batched_speedup']}x slower than batched)")
+
+    adj_ms = None
+    if not args.no_adjoint:
+        adj_ms = adjoint_stage(torch, scsurf, synth)
+        log(f"adjoint forward+backward (16 keyframes, 320x240): {adj_ms:.2f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        sample = list(np.random.default_rng(0).choice(n_kf, args.cpu_sample, replace=False))
+        kfs_np = [{"depth": kfs[k].depth.cpu().numpy(), "weight": kfs[k].weight.cpu().numpy(),
+                   "color": kfs[k].color.cpu().numpy()} for k in range(n_kf)]
+        rate, dt = cpu_baseline(oracle, kfs_np, wl.intr, A, B, sample)
+        cpu = {"value": round(rate, 4), "unit": "keyframes/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"{len(sample)} of the {n_kf} keyframes, each de-integrated at its integration pose and "
+                         f"re-integrated at its new pose on a volume holding those {len(sample)} ({dt:.1f} s)"}
+        log(f"oracle: {rate:.3f} keyframes/s on {oracle.threads()} threads")
+
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_gib} GiB done")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "keyframes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched re-integration: 10x10x3 m room with 40 boxes/spheres, 1000 frames at 640x480 "
+                        "fused 5 per keyframe into 200 keyframes with valid-pixel fractions U(0.4,1.0), "
+                        "voxel 1 cm, truncation 4 cm, 2^21 buckets, FP32 TSDF + RGBA8 colour + FP32 weight; "
+                        "one pose-graph update moving all 200 poses by N(0, 3 cm / 1.5 deg), keyframes "
+                        "ordered by pose change, de-integrated and re-integrated in one persistent launch",
+            "keyframes": n_kf, "operations": n_ops, "resolution": [Wd, H], "blocks": n_blocks_after,
+            "schedule": list(sched), "parallelism": "single GPU",
+        },
+        "voxel_updates_per_s": round(upd / (ms_per_step / 1e3), 1),
+        "voxel_updates_per_step": int(upd),
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "batch_main_wave_kernel" if sched[0] == 8 else "batch_main_group_kernel",
+                     "kernel_ms": round(pass_ms, 4), "algorithmic_bytes": int(alg_bytes),
+                     "blocks_written": int(written), "candidate_blocks": int(cand), "block_op_pairs": int(pairs),
+                     "source_digest": digest},
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "stages": {"kf_fuse_frames_per_s": round(n_kf * wl.kappa / fuse_s, 1),
+                   "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
+                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms},
+    }
+    print(json.dumps(out), flush=True)
+    vol.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -59,7 +59,8 @@ typedef int32_t sc_status;
 #define SC_ERANGE (-9)     /* sticky: a keyframe pixel's frustum cell spans more than 16 blocks per axis */
 
 #define SC_COLOR_RGBA8 0 /* voxel colour 4 x uint8 (RGB + pad); keyframe colour uint8 H x W x 4 */
-#define SC_COLOR_F32 1   /* voxel colour 3 x float in [0,1]; keyframe colour float H x W x 3 */
+#define SC_COLOR_F32 1   /* keyframe colour float H x W x 3 in [0,1]; voxel colour held as 3 x double
+                            (de-integration amplifies the stored colour's rounding by W / W') */
 
 #define SC_SEL_EQ3 0         /* Eq. (3): the m most-moved consecutive keyframes, ascending index */
 #define SC_SEL_TOPM 1        /* the m most-moved keyframes, descending pose change */
@@ -106,7 +107,7 @@ typedef struct sc_volume sc_volume;
 /* ---- volume lifecycle --------------------------------------------------- */
 
 /* Creates an empty volume on the current device.  The block pool
- * (max_blocks x 6 KiB in RGBA8 mode, 10 KiB in F32 mode) and the hash table
+ * (max_blocks x 6 KiB in RGBA8 mode, 16 KiB in F32 mode) and the hash table
  * are allocated and cleared here.  *out is NULL on failure. */
 sc_status sc_volume_create(const sc_volume_params* params, sc_volume** out);
 
@@ -122,7 +123,8 @@ sc_status sc_volume_query(sc_volume* vol, void* stream, int64_t* n_blocks, int32
 
 /* Copies the first min(n_blocks, cap) allocated blocks, in pool order, into
  * device buffers: block coordinates (int32 x 3), D (float x 512), W (float x
- * 512) and colour (uint32 RGBA8 x 512, or float x 3 x 512 planar).  Any
+ * 512) and colour (uint32 RGBA8 x 512, or float x 3 x 512 planar, rounded
+ * from the FP64 voxel colour).  Any
  * output may be NULL.  *n_out (host) receives n_blocks.  Synchronises. */
 sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, float* D, float* W, void* C,
                            int64_t cap, int64_t* n_out);
@@ -226,6 +228,23 @@ sc_status sc_get_schedule(sc_volume* vol, sc_schedule* sched);
 sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
                       const sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
                       sc_schedule* best, float* best_ms, void* stream);
+
+/* Measurement of the batched voxel pass: HIP events are recorded on the
+ * caller's stream immediately before and after the persistent voxel pass of
+ * each of the next `capacity` batched launches (0 disables and frees them).
+ * Synchronises the device. */
+sc_status sc_batch_timing(sc_volume* vol, int32_t capacity);
+
+/* Elapsed milliseconds of the voxel pass of each recorded launch (host
+ * array of at least the capacity); *n (host) receives their number.  Waits
+ * for the recorded events. */
+sc_status sc_batch_timing_read(sc_volume* vol, float* ms, int32_t* n);
+
+/* Cumulative counters of the batched voxel pass since the volume was
+ * created or reset (host int64[4]): candidate blocks processed, (block,
+ * operation) pairs tested, touched voxel updates applied, blocks written.
+ * Synchronises `stream`. */
+sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats);
 
 /* ---- adjoint of integration --------------------------------------------- */
 

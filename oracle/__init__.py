@@ -70,6 +70,8 @@ def lib():
         L.of_fuse_color.restype = None
         L.of_fuse_color.argtypes = [P, P, P, P, i32, i32, i32, P, P, P, i32, f32, P, P, P]
         L.ov_threads.restype = i32
+        L.ov_voxel_sequence.restype = i32
+        L.ov_voxel_sequence.argtypes = [P, P, P, P, i32, i32, P, i32, P, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -174,6 +176,28 @@ class Volume:
         pf = np.zeros((cnt, 3), np.float32)
         L.ov_record(self._h, _p(Z), _p(Wk), W, H, _p(it), _p(Rm), _p(tv), cnt, _p(n), _p(pix), _p(w), _p(d), _p(pf))
         return {"n": n, "pix": pix, "w": w, "d": d, "p": pf}
+
+    def voxel_sequence(self, kfs, intr, ops, n):
+        """Final (D, W, C, touches) of voxel n after operations ops = [(kf index,
+        sign, R, t), ...] applied in order from the empty state (RGBA8 colour)."""
+        Z = [_c(k["depth"], np.float32) for k in kfs]
+        Wk = [_c(k["weight"], np.float32) for k in kfs]
+        C = [_c(k["color"], np.uint8) for k in kfs]
+        H, W = Z[0].shape
+        PZ = (ctypes.c_void_p * len(kfs))(*[z.ctypes.data for z in Z])
+        PW = (ctypes.c_void_p * len(kfs))(*[w.ctypes.data for w in Wk])
+        PC = (ctypes.c_void_p * len(kfs))(*[c.ctypes.data for c in C])
+        kf = np.array([o[0] for o in ops], np.int32)
+        sg = np.array([o[1] for o in ops], np.int32)
+        R = np.ascontiguousarray(np.array([o[2] for o in ops], np.float64).reshape(-1, 9))
+        t = np.ascontiguousarray(np.array([o[3] for o in ops], np.float64).reshape(-1, 3))
+        nn = _c(n, np.int64)
+        D = np.zeros(1)
+        Wv = np.zeros(1)
+        Cv = np.zeros(3)
+        rc = lib().ov_voxel_sequence(self._h, PZ, PW, PC, W, H, _p(_intr(intr)), len(ops), _p(kf), _p(sg), _p(R),
+                                     _p(t), _p(nn), _p(D), _p(Wv), _p(Cv))
+        return float(D[0]), float(Wv[0]), Cv, int(rc)
 
     def touch_one(self, kf, intr, R, t, n):
         Z = _c(kf["depth"], np.float32)

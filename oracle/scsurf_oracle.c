@@ -634,6 +634,62 @@ int ov_touch_one(const ovol* v, const float* Z, const float* Wk, int W, int H, c
     return 1;
 }
 
+/* One voxel through a sequence of operations, from the empty state: the
+ * plain per-voxel definition used to check large volumes on samples.
+ * ops: n_ops keyframe indices, signs (+1 integrate, -1 de-integrate) and
+ * poses (R n_ops x 9, t n_ops x 3); keyframes: arrays of pointers.  Returns
+ * the number of operations that touched the voxel, or a negative error;
+ * out_D/out_W/out_C receive the final state (C: 3 values). */
+int ov_voxel_sequence(const ovol* v, const float* const* Z, const float* const* Wk, const uint8_t* const* rgba,
+                      int W, int H, const float* intr, int n_ops, const int* kf, const int* sign, const double* R,
+                      const double* t, const int64_t* n, double* out_D, double* out_W, double* out_C)
+{
+    ovol tmp = *v;
+    tmp.color_f32 = 0;
+    tmp.n = 0;
+    tmp.cap = 0;
+    tmp.bxyz = NULL;
+    tmp.D = tmp.W = tmp.C = NULL;
+    if (omap_init(&tmp.map, 16) != OV_OK) return OV_ENOMEM;
+    int64_t b[3] = {floor_div8(n[0]), floor_div8(n[1]), floor_div8(n[2])};
+    int k = (int)((n[0] - 8 * b[0]) + 8 * (n[1] - 8 * b[1]) + 64 * (n[2] - 8 * b[2]));
+    int64_t bi = ov_alloc_block(&tmp, b[0], b[1], b[2]);
+    int touched = 0, err = OV_OK;
+    for (int o = 0; o < n_ops && bi >= 0; ++o) {
+        oop P;
+        memset(&P, 0, sizeof(P));
+        P.Z = Z[kf[o]];
+        P.Wk = Wk[kf[o]];
+        P.rgba = rgba[kf[o]];
+        P.W = W;
+        P.H = H;
+        P.fx = intr[0];
+        P.fy = intr[1];
+        P.cx = intr[2];
+        P.cy = intr[3];
+        memcpy(P.R, R + 9 * o, sizeof(P.R));
+        memcpy(P.t, t + 3 * o, sizeof(P.t));
+        oop_setup(&P, &tmp);
+        touch_t T;
+        if (!touch(&tmp, &P, n, &T)) continue;
+        touched++;
+        int e = update_voxel(&tmp, bi, k, &T, sign[o]);
+        if (e != OV_OK && err == OV_OK) err = e;
+    }
+    if (bi >= 0) {
+        *out_D = tmp.D[BVOX * bi + k];
+        *out_W = tmp.W[BVOX * bi + k];
+        for (int c = 0; c < 3; ++c) out_C[c] = tmp.C[(BVOX * bi + k) * 3 + c];
+    }
+    omap_free(&tmp.map);
+    free(tmp.bxyz);
+    free(tmp.D);
+    free(tmp.W);
+    free(tmp.C);
+    if (bi < 0) return OV_ENOMEM;
+    return err != OV_OK ? err : touched;
+}
+
 /* Export sorted by block key order of insertion is not stable across
  * implementations, so the caller sorts.  Writes n x 3 block coordinates and
  * the per-voxel D, W (n x 512) and colour (n x 512 x 3). */

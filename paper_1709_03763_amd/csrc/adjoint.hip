@@ -29,7 +29,8 @@ __global__ __launch_bounds__(64) void backward_kernel(const OpDesc* __restrict__
     int bx, by, bz;
     unpack_key(key, bx, by, bz);
     float q[3];
-    block_origin(op, v.s, bx, by, bz, q);
+    double qz;
+    block_origin(op, v.s, bx, by, bz, q, qz);
     const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
     float base[3];
 #pragma unroll
@@ -44,8 +45,8 @@ __global__ __launch_bounds__(64) void backward_kernel(const OpDesc* __restrict__
         const float py = base[1] + fz * op.a[2][1];
         const float pz = base[2] + fz * op.a[2][2];
         int pix;
-        float w, d;
-        if (!touch(op, v.mu, px, py, pz, pix, w, d)) continue;
+        float w, z;
+        if (!touch(op, v.mu, px, py, pz, pix, w, z)) continue;
         const int i = lane + 64 * kz;
         const float Wv = blk[512 + i];
         if (!(Wv > 0.0f)) continue;

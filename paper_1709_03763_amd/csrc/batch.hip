@@ -70,6 +70,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
+    if (tid == 0) cd.stats[0] += min(cd.counters[4], cd.cap);
     const int per = (n_bins + 1023) / 1024;
     // thread tid owns bins (descending) [n_bins-1 - tid*per, ...]
     uint32_t sum = 0;
@@ -111,7 +112,7 @@ template <int CM, int VPL>
 struct LaneVox {
     float D[VPL], W[VPL];
     uint32_t C[VPL];       // RGBA8
-    float Cf[3][VPL];      // FP32 colour
+    double Cf[3][VPL];     // FP32-colour mode (held in FP64)
 };
 
 template <int CM, int VPL>
@@ -125,9 +126,10 @@ __device__ inline void load_vox(LaneVox<CM, VPL>& s, const float* blk, int lane,
         if (CM == SC_COLOR_RGBA8) {
             s.C[j] = reinterpret_cast<const uint32_t*>(blk)[1024 + i];
         } else {
-            s.Cf[0][j] = blk[1024 + i];
-            s.Cf[1][j] = blk[1536 + i];
-            s.Cf[2][j] = blk[2048 + i];
+            const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+            s.Cf[0][j] = Cd[i];
+            s.Cf[1][j] = Cd[512 + i];
+            s.Cf[2][j] = Cd[1024 + i];
         }
     }
 }
@@ -140,7 +142,7 @@ __device__ inline void zero_vox(LaneVox<CM, VPL>& s)
         s.D[j] = 0.0f;
         s.W[j] = 0.0f;
         s.C[j] = 0u;
-        s.Cf[0][j] = s.Cf[1][j] = s.Cf[2][j] = 0.0f;
+        s.Cf[0][j] = s.Cf[1][j] = s.Cf[2][j] = 0.0;
     }
 }
 
@@ -156,9 +158,10 @@ __device__ inline void store_vox(const LaneVox<CM, VPL>& s, float* blk, int lane
         if (CM == SC_COLOR_RGBA8) {
             reinterpret_cast<uint32_t*>(blk)[1024 + i] = s.C[j];
         } else {
-            blk[1024 + i] = s.Cf[0][j];
-            blk[1536 + i] = s.Cf[1][j];
-            blk[2048 + i] = s.Cf[2][j];
+            double* Cd = reinterpret_cast<double*>(blk + 1024);
+            Cd[i] = s.Cf[0][j];
+            Cd[512 + i] = s.Cf[1][j];
+            Cd[1024 + i] = s.Cf[2][j];
         }
     }
 }
@@ -169,14 +172,16 @@ __device__ inline void store_vox(const LaneVox<CM, VPL>& s, float* blk, int lane
 template <int CM, int VPL>
 __device__ inline void apply_op(const OpDesc& op, const VolDev& v, int bx, int by, int bz, int lane, int kz0,
                                 bool allocated, LaneVox<CM, VPL>& s, uint32_t& touched, bool& re_touch,
-                                bool& e_notalloc, bool& e_weight)
+                                bool& e_notalloc, bool& e_weight, uint32_t& n_upd)
 {
     float q[3];
-    block_origin(op, v.s, bx, by, bz, q);
+    double qz;
+    block_origin(op, v.s, bx, by, bz, q, qz);
     const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
     float base[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
+    const double bz64 = (qz + (double)(lane & 7) * op.az[0]) + (double)(lane >> 3) * op.az[1];
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
         const float fz = (float)(kz0 + j);
@@ -184,21 +189,23 @@ __device__ inline void apply_op(const OpDesc& op, const VolDev& v, int bx, int b
         const float py = base[1] + fz * op.a[2][1];
         const float pz = base[2] + fz * op.a[2][2];
         int pix;
-        float w, d;
-        if (!touch(op, v.mu, px, py, pz, pix, w, d)) continue;
+        float w, z;
+        if (!touch(op, v.mu, px, py, pz, pix, w, z)) continue;
+        const float d = distance(z, bz64 + (double)(kz0 + j) * op.az[2]);
         if (op.sign < 0 && !allocated) {
             e_notalloc = true;
             continue;
         }
         if (op.sign > 0) re_touch = true;
         touched |= 1u << j;
+        ++n_upd;
         if (CM == SC_COLOR_RGBA8) {
             const uint32_t c = __ldg(reinterpret_cast<const uint32_t*>(op.color) + pix);
             e_weight |= !update_rgba8(s.D[j], s.W[j], s.C[j], d, w, c, op.sign);
         } else {
             const float* cp = reinterpret_cast<const float*>(op.color) + 3 * pix;
             const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
-            float C3[3] = {s.Cf[0][j], s.Cf[1][j], s.Cf[2][j]};
+            double C3[3] = {s.Cf[0][j], s.Cf[1][j], s.Cf[2][j]};
             e_weight |= !update_f32(s.D[j], s.W[j], C3, d, w, c, op.sign);
             s.Cf[0][j] = C3[0];
             s.Cf[1][j] = C3[1];
@@ -225,6 +232,7 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
     constexpr int VPL = 8;
     const int lane = threadIdx.x & 63;
     const uint32_t n = min(cd.counters[4], cd.cap);
+    uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
         const uint32_t i = wave_fetch_add1(cd.counters + 5, lane);
         if (i >= n) break;
@@ -242,18 +250,24 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
         bool re_touch = false, e_na = false, e_w = false;
         for (int w = 0; w < cd.words; ++w) {
             uint64_t m = bcast64(cd.mask[(size_t)h * cd.words + w]);
+            n_pairs += __popcll(m);
             while (m) {
                 const int b = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
                 apply_op<CM, VPL>(ops[w * 64 + b], v, bx, by, bz, lane, 0, slot >= 0, st, touched, re_touch, e_na,
-                                  e_w);
+                                  e_w, n_upd);
             }
         }
         const int all = (__ballot(re_touch) ? 1 : 0) | (__ballot(e_na) ? 2 : 0) | (__ballot(e_w) ? 4 : 0);
         if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, bx, by, bz, lane);
         if (slot >= 0) store_vox<CM, VPL>(st, v.pool + (size_t)slot * v.stride, lane, 0, touched);
+        const bool wrote = __ballot(touched != 0) != 0;
+        n_written += (slot >= 0 && wrote) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
     }
+    atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
+    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
+    atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
 }
 
 // Persistent voxel pass, one workgroup of G = 8 / VPL wavefronts per block
@@ -271,6 +285,7 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
     const int wave = (int)bcast(threadIdx.x >> 6);
     const int kz0 = wave * VPL;
     const uint32_t n = min(cd.counters[4], cd.cap);
+    uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
         if (wave == 0) {
             const uint32_t it = wave_fetch_add1(cd.counters + 5, lane);
@@ -294,14 +309,16 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
         bool re_touch = false, e_na = false, e_w = false;
         for (int w = 0; w < cd.words; ++w) {
             uint64_t m = bcast64(cd.mask[(size_t)h * cd.words + w]);
+            n_pairs += __popcll(m);
             while (m) {
                 const int b = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
                 apply_op<CM, VPL>(ops[w * 64 + b], v, bx, by, bz, lane, kz0, slot >= 0, st, touched, re_touch, e_na,
-                                  e_w);
+                                  e_w, n_upd);
             }
         }
-        const int f = (__ballot(re_touch) ? 1 : 0) | (__ballot(e_na) ? 2 : 0) | (__ballot(e_w) ? 4 : 0);
+        const int f = (__ballot(re_touch) ? 1 : 0) | (__ballot(e_na) ? 2 : 0) | (__ballot(e_w) ? 4 : 0) |
+                      (__ballot(touched != 0) ? 8 : 0);
         if (f) atomicOr(&s_flags, f);
         __syncthreads();
         const int all = (int)bcast((uint32_t)s_flags);
@@ -314,8 +331,14 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
             slot = (int)bcast((uint32_t)s_slot);
         }
         if (slot >= 0) store_vox<CM, VPL>(st, v.pool + (size_t)slot * v.stride, lane, kz0, touched);
+        n_written += (slot >= 0 && (all & 8)) ? 1u : 0u;
         if (wave == 0) retire_candidate(cd, v, h, all, lane);
         __syncthreads();
+    }
+    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
+    if (wave == 0) {
+        atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
+        atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
     }
 }
 
@@ -329,7 +352,7 @@ static bool schedule_ok(const sc_schedule& s)
     return s.wgs_per_cu >= 1 && s.wgs_per_cu <= 32;
 }
 
-static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t s)
+static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t s, bool events)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
@@ -337,6 +360,7 @@ static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t 
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand);
+    if (events) (void)hipEventRecordWithFlags(vol->tev[0], s, hipEventRecordExternal);
     const bool rgba = vol->p.color_mode == SC_COLOR_RGBA8;
     const int grid = vol->n_cu * sch.wgs_per_cu;
     const int threads = (sch.vpl == 8) ? 256 : 64 * (8 / sch.vpl);
@@ -366,6 +390,7 @@ static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t 
             batch_main_group_kernel<SC_COLOR_F32, 1><<<grid, threads, 0, s>>>(vol->d_ops, vol->dev, vol->cand);
         break;
     }
+    if (events) (void)hipEventRecordWithFlags(vol->tev[1], s, hipEventRecordExternal);
 }
 
 static int sched_index(const sc_schedule& s)
@@ -374,27 +399,49 @@ static int sched_index(const sc_schedule& s)
     return v;
 }
 
-// Returns the graph for the current schedule, capturing it on first use.
+// Returns the graph for the current schedule, capturing it on first use.  The
+// capture records two events around the voxel pass; their nodes are kept so
+// that each launch can record per-launch timing events instead.
 static hipGraphExec_t graph_for(sc_volume* vol)
 {
     const int vi = sched_index(vol->sched);
     const int key = vol->sched.waves_per_wg * 64 + vol->sched.wgs_per_cu;
-    // graph[vi][0] holds the exec, graph_w/graph_h cache the schedule key per vpl
     if (vol->graph[vi][0] && vol->graph_keys[vi] == key) return vol->graph[vi][0];
     if (vol->graph[vi][0]) {
         (void)hipGraphExecDestroy(vol->graph[vi][0]);
         vol->graph[vi][0] = nullptr;
     }
+    if (vol->graph_src[vi]) {
+        (void)hipGraphDestroy(vol->graph_src[vi]);
+        vol->graph_src[vi] = nullptr;
+    }
     hipStream_t cs = vol->cap_stream;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    launch_sequence(vol, vol->sched, cs);
+    launch_sequence(vol, vol->sched, cs, true);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return nullptr;
+    // locate the two event-record nodes (in capture order)
+    size_t nn = 0;
+    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return nullptr;
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (nn && hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return nullptr;
+    vol->ev_node[vi][0] = vol->ev_node[vi][1] = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeEventRecord) continue;
+        hipEvent_t e = nullptr;
+        if (hipGraphEventRecordNodeGetEvent(nd, &e) != hipSuccess) continue;
+        if (e == vol->tev[0]) vol->ev_node[vi][0] = nd;
+        if (e == vol->tev[1]) vol->ev_node[vi][1] = nd;
+    }
     hipGraphExec_t ex = nullptr;
     const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return nullptr;
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return nullptr;
+    }
     vol->graph[vi][0] = ex;
+    vol->graph_src[vi] = g;
     vol->graph_keys[vi] = key;
     return ex;
 }
@@ -410,6 +457,18 @@ static sc_status run_chunk(sc_volume* vol, int n_ops, const sc_intrinsics* in, h
         return SC_EDEVICE;
     hipGraphExec_t g = graph_for(vol);
     if (!g) return SC_EDEVICE;
+    const int vi = sched_index(vol->sched);
+    if (vol->ev_node[vi][0] && vol->ev_node[vi][1]) {
+        hipEvent_t e0 = vol->tev[0], e1 = vol->tev[1];
+        if (vol->timing_n < vol->timing_cap) {
+            e0 = vol->timing_ev[2 * vol->timing_n];
+            e1 = vol->timing_ev[2 * vol->timing_n + 1];
+            vol->timing_n++;
+        }
+        if (hipGraphExecEventRecordNodeSetEvent(g, vol->ev_node[vi][0], e0) != hipSuccess ||
+            hipGraphExecEventRecordNodeSetEvent(g, vol->ev_node[vi][1], e1) != hipSuccess)
+            return SC_EDEVICE;
+    }
     if (hipGraphLaunch(g, s) != hipSuccess) return SC_EDEVICE;
     // the staging buffers may be rewritten only after the copies have run
     if (hipEventRecord(vol->staged, s) != hipSuccess) return SC_EDEVICE;
@@ -457,6 +516,45 @@ sc_status sc_set_schedule(sc_volume* vol, const sc_schedule* sched)
     if (!vol || !sched || !schedule_ok(*sched)) return SC_EINVAL;
     vol->sched = *sched;
     vol->sched.waves_per_wg = (vol->sched.vpl == 8) ? 4 : 8 / vol->sched.vpl;
+    return SC_OK;
+}
+
+sc_status sc_batch_timing(sc_volume* vol, int32_t capacity)
+{
+    if (!vol || capacity < 0 || capacity > (1 << 20)) return SC_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return SC_EDEVICE;
+    for (int i = 0; i < 2 * vol->timing_cap; ++i) (void)hipEventDestroy(vol->timing_ev[i]);
+    delete[] vol->timing_ev;
+    vol->timing_ev = nullptr;
+    vol->timing_cap = vol->timing_n = 0;
+    if (capacity == 0) return SC_OK;
+    vol->timing_ev = new (std::nothrow) hipEvent_t[2 * capacity];
+    if (!vol->timing_ev) return SC_ENOMEM;
+    for (int i = 0; i < 2 * capacity; ++i)
+        if (hipEventCreate(&vol->timing_ev[i]) != hipSuccess) return SC_EDEVICE;
+    vol->timing_cap = capacity;
+    return SC_OK;
+}
+
+sc_status sc_batch_timing_read(sc_volume* vol, float* ms, int32_t* n)
+{
+    if (!vol || !n || (vol->timing_n > 0 && !ms)) return SC_EINVAL;
+    for (int i = 0; i < vol->timing_n; ++i) {
+        if (hipEventSynchronize(vol->timing_ev[2 * i + 1]) != hipSuccess) return SC_EDEVICE;
+        if (hipEventElapsedTime(&ms[i], vol->timing_ev[2 * i], vol->timing_ev[2 * i + 1]) != hipSuccess)
+            return SC_EDEVICE;
+    }
+    *n = vol->timing_n;
+    return SC_OK;
+}
+
+sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats)
+{
+    if (!vol || !stats) return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(stats, vol->cand.stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return SC_EDEVICE;
     return SC_OK;
 }
 

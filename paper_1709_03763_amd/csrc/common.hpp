@@ -51,6 +51,7 @@ struct OpDesc {
     double R[9];          // camera -> world rotation, row-major
     double t[3];          // camera -> world translation
     float a[3][3];        // a[axis][row] = fl32(s * R[axis][row]): camera step of one voxel along a world axis
+    double az[3];         // s * R[axis][2] in FP64: camera-z step per voxel for the continuous distance
     int32_t sign;         // +1 integrate, -1 de-integrate
     int32_t kf;           // keyframe index within the call (for gradients)
 };
@@ -65,7 +66,7 @@ struct VolDev {
     int32_t* err;          // sticky error word
     uint32_t bucket_mask;
     int32_t max_blocks;
-    int32_t stride;        // floats per block: 1536 (RGBA8) or 2560 (F32)
+    int32_t stride;        // floats per block: 1536 (RGBA8) or 4096 (F32 mode, colour as double)
     int32_t color_mode;
     float s;               // voxel size
     float mu;              // truncation
@@ -80,6 +81,7 @@ struct CandDev {
     uint32_t* sorted;     // occupied buckets ordered by operation count (batched path)
     uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity), [4] batch work cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
+    unsigned long long* stats;  // cumulative: candidate blocks, (block, op) pairs, voxel updates, blocks written
     uint32_t mask_bits;   // cand buckets - 1
     uint32_t cap;         // list capacity
     int32_t words;        // 64-bit mask words per bucket
@@ -112,7 +114,12 @@ struct sc_volume {
     hipStream_t cap_stream;  // private stream used for graph capture
     hipEvent_t staged;       // recorded after the batch descriptors were copied to the device
     hipGraphExec_t graph[4][1]; // captured batched sequence per voxels-per-lane choice
+    hipGraph_t graph_src[4];    // the captured graphs (kept for their event-record nodes)
+    hipGraphNode_t ev_node[4][2]; // event-record nodes around the voxel pass
     int graph_keys[4];       // schedule the graph of each slot was captured with
+    hipEvent_t tev[2];       // default events recorded around the voxel pass
+    hipEvent_t* timing_ev;   // optional per-launch event pairs (2 * timing_cap)
+    int timing_cap, timing_n;
     sc_schedule sched;
     int n_cu;
 };

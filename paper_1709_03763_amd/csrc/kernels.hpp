@@ -48,15 +48,20 @@ __device__ inline uint32_t wave_fetch_add1(uint32_t* ctr, int lane)
 // ---------------------------------------------------------------------------
 
 // Camera-frame position of block (bx, by, bz)'s origin: R^T (8 s b - t) in
-// FP64, rounded once to FP32.
-__device__ inline void block_origin(const OpDesc& op, float s, int bx, int by, int bz, float q[3])
+// FP64, rounded once to FP32 for the decisions; its z also returned in FP64
+// for the continuous distance.
+__device__ inline void block_origin(const OpDesc& op, float s, int bx, int by, int bz, float q[3], double& qz)
 {
     const double s8 = 8.0 * (double)s;
     const double e0 = s8 * (double)bx - op.t[0];
     const double e1 = s8 * (double)by - op.t[1];
     const double e2 = s8 * (double)bz - op.t[2];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) q[r] = (float)((op.R[r] * e0 + op.R[3 + r] * e1) + op.R[6 + r] * e2);
+    for (int r = 0; r < 3; ++r) {
+        const double v = (op.R[r] * e0 + op.R[3 + r] * e1) + op.R[6 + r] * e2;
+        q[r] = (float)v;
+        if (r == 2) qz = v;
+    }
 }
 
 // Nearest pixel of the pinhole projection; false if behind the camera or
@@ -75,16 +80,20 @@ __device__ inline bool nearest_pixel(const OpDesc& op, float px, float py, float
 
 __device__ inline float qweight(float w) { return rintf(w * kWeightScale) * (1.0f / kWeightScale); }
 
-// Touched test of one voxel whose FP32 camera point is (px, py, pz).
-// On success returns the pixel, the quantised weight w and d = Z* - pz.
-__device__ inline bool touch(const OpDesc& op, float mu, float px, float py, float pz, int& pix, float& w, float& d)
+// Touched test of one voxel whose FP32 camera point is (px, py, pz).  On
+// success returns the pixel, the quantised weight w and the keyframe depth z
+// there (the band test uses fl32(z - pz)).
+__device__ inline bool touch(const OpDesc& op, float mu, float px, float py, float pz, int& pix, float& w, float& z)
 {
     if (!nearest_pixel(op, px, py, pz, pix)) return false;
     w = qweight(__ldg(op.weight + pix));
     if (!(w > 0.0f)) return false;
-    d = __ldg(op.depth + pix) - pz;
-    return fabsf(d) <= mu;
+    z = __ldg(op.depth + pix);
+    return fabsf(z - pz) <= mu;
 }
+
+// Continuous projective distance d = Z*(pixel) - p_z with p_z in FP64.
+__device__ inline float distance(float z, double pz64) { return (float)((double)z - pz64); }
 
 // ---------------------------------------------------------------------------
 // voxel updates
@@ -148,21 +157,25 @@ __device__ inline bool update_rgba8(float& D, float& W, uint32_t& C, float d, fl
     return true;
 }
 
-// FP32 colour in [0,1].
-__device__ inline bool update_f32(float& D, float& W, float C[3], float d, float w, const float c[3], int sign)
+// FP32-colour mode: keyframe colour FP32 in [0,1]; the voxel colour is held
+// in FP64, because Eq. (2) amplifies the rounding of the stored colour by
+// W / W' when most of a voxel's weight is removed.
+__device__ inline bool update_f32(float& D, float& W, double C[3], float d, float w, const float c[3], int sign)
 {
     const float W1 = (sign > 0) ? W + w : W - w;
     if (sign > 0 ? !(W1 < kWeightLimit) : (W1 < 0.0f)) return false;
     if (W1 == 0.0f) {
         D = 0.0f;
         W = 0.0f;
-        C[0] = C[1] = C[2] = 0.0f;
+        C[0] = C[1] = C[2] = 0.0;
         return true;
     }
     const float rcp = __builtin_amdgcn_rcpf(W1);
     D = (sign > 0 ? (D * W + d * w) : (D * W - d * w)) * rcp;
+    const double Wd = (double)W, wd = (double)w, W1d = (double)W1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) C[k] = (sign > 0 ? (C[k] * W + c[k] * w) : (C[k] * W - c[k] * w)) * rcp;
+    for (int k = 0; k < 3; ++k)
+        C[k] = (sign > 0 ? (C[k] * Wd + (double)c[k] * wd) : (C[k] * Wd - (double)c[k] * wd)) / W1d;
     W = W1;
     return true;
 }

@@ -135,11 +135,13 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
     int bx, by, bz;
     unpack_key(key, bx, by, bz);
     float q[3];
-    block_origin(op, v.s, bx, by, bz, q);
+    double qz;
+    block_origin(op, v.s, bx, by, bz, q, qz);
     const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
     float base[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
+    const double bz64 = (qz + (double)(lane & 7) * op.az[0]) + (double)(lane >> 3) * op.az[1];
     uint32_t tmask = 0;
     int pix[8];
     float dd[8], ww[8];
@@ -149,7 +151,11 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
         const float px = base[0] + fz * op.a[2][0];
         const float py = base[1] + fz * op.a[2][1];
         const float pz = base[2] + fz * op.a[2][2];
-        if (touch(op, v.mu, px, py, pz, pix[kz], ww[kz], dd[kz])) tmask |= 1u << kz;
+        float z;
+        if (touch(op, v.mu, px, py, pz, pix[kz], ww[kz], z)) {
+            tmask |= 1u << kz;
+            dd[kz] = distance(z, bz64 + (double)kz * op.az[2]);
+        }
     }
     if (__ballot(tmask != 0) == 0) return;
     const int slot = (op.sign > 0) ? vol_insert_wave(v, key, bx, by, bz, lane) : (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
@@ -171,13 +177,14 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
             bad |= !update_rgba8(D, W, C, dd[kz], ww[kz], c, op.sign);
             Cp[i] = C;
         } else {
-            float C[3] = {blk[1024 + i], blk[1536 + i], blk[2048 + i]};
+            double* Cd = reinterpret_cast<double*>(blk + 1024);
+            double C[3] = {Cd[i], Cd[512 + i], Cd[1024 + i]};
             const float* cp = reinterpret_cast<const float*>(op.color) + 3 * pix[kz];
             const float c[3] = {cp[0], cp[1], cp[2]};
             bad |= !update_f32(D, W, C, dd[kz], ww[kz], c, op.sign);
-            blk[1024 + i] = C[0];
-            blk[1536 + i] = C[1];
-            blk[2048 + i] = C[2];
+            Cd[i] = C[0];
+            Cd[512 + i] = C[1];
+            Cd[1024 + i] = C[2];
         }
         blk[i] = D;
         blk[512 + i] = W;
@@ -214,10 +221,11 @@ __global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float
             if (v.color_mode == SC_COLOR_RGBA8) {
                 reinterpret_cast<uint32_t*>(C)[b * kBlockVox + i] = reinterpret_cast<const uint32_t*>(blk)[1024 + i];
             } else {
+                const double* Cd = reinterpret_cast<const double*>(blk + 1024);
                 float* Cf = reinterpret_cast<float*>(C) + b * 3 * kBlockVox;
-                Cf[i] = blk[1024 + i];
-                Cf[512 + i] = blk[1536 + i];
-                Cf[1024 + i] = blk[2048 + i];
+                Cf[i] = (float)Cd[i];
+                Cf[512 + i] = (float)Cd[512 + i];
+                Cf[1024 + i] = (float)Cd[1024 + i];
             }
         }
     }
@@ -250,8 +258,10 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     memcpy(op->R, T->R, sizeof(op->R));
     memcpy(op->t, T->t, sizeof(op->t));
     const double s = (double)vol->p.voxel_size;
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
         for (int r = 0; r < 3; ++r) op->a[c][r] = (float)(s * T->R[3 * c + r]);
+        op->az[c] = s * T->R[3 * c + 2];
+    }
     op->sign = sign;
     op->kf = kf_index;
 }
@@ -321,7 +331,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     VolDev& d = vol->dev;
     d.bucket_mask = (uint32_t)(p->n_buckets - 1);
     d.max_blocks = (int32_t)p->max_blocks;
-    d.stride = (p->color_mode == SC_COLOR_RGBA8) ? 3 * kBlockVox : 5 * kBlockVox;
+    d.stride = (p->color_mode == SC_COLOR_RGBA8) ? 3 * kBlockVox : 8 * kBlockVox;
     d.color_mode = p->color_mode;
     d.s = p->voxel_size;
     d.mu = p->trunc;
@@ -345,12 +355,15 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * c.cap) == hipSuccess;
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
+    ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 8) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
     ok &= hipHostMalloc((void**)&vol->h_ops, sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) == hipSuccess;
     ok &= hipMalloc(&vol->d_hdr, sizeof(BatchHdr)) == hipSuccess;
     ok &= hipHostMalloc((void**)&vol->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
     ok &= hipStreamCreateWithFlags(&vol->cap_stream, hipStreamNonBlocking) == hipSuccess;
     ok &= hipEventCreateWithFlags(&vol->staged, hipEventDisableTiming) == hipSuccess;
+    ok &= hipEventCreate(&vol->tev[0]) == hipSuccess;
+    ok &= hipEventCreate(&vol->tev[1]) == hipSuccess;
     if (!ok) {
         sc_volume_destroy(vol);
         return SC_ENOMEM;
@@ -373,6 +386,13 @@ void sc_volume_destroy(sc_volume* vol)
     for (auto& row : vol->graph)
         for (auto& g : row)
             if (g) hipGraphExecDestroy(g);
+    for (auto& g : vol->graph_src)
+        if (g) hipGraphDestroy(g);
+    if (vol->tev[0]) hipEventDestroy(vol->tev[0]);
+    if (vol->tev[1]) hipEventDestroy(vol->tev[1]);
+    for (int i = 0; i < 2 * vol->timing_cap; ++i) hipEventDestroy(vol->timing_ev[i]);
+    delete[] vol->timing_ev;
+    hipFree(vol->cand.stats);
     hipFree(vol->dev.keys);
     hipFree(vol->dev.vals);
     hipFree(vol->dev.slot_keys);
@@ -408,6 +428,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u64(c.mask, 0ull, (size_t)vol->cand_buckets * c.words, s);
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
+    fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 8, s);
     vol->parity = 0;
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }

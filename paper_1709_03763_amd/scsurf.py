@@ -62,7 +62,8 @@ class sc_schedule(ctypes.Structure):
 EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
-           "sc_set_schedule", "sc_get_schedule", "sc_autotune", "tsdf_integrate_backward"]
+           "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
+           "sc_volume_stats", "tsdf_integrate_backward"]
 
 _lib = None
 
@@ -100,6 +101,9 @@ def lib():
     L.sc_autotune.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                               ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_schedule),
                               ctypes.POINTER(ctypes.c_float), P]
+    L.sc_batch_timing.argtypes = [P, i32]
+    L.sc_batch_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
+    L.sc_volume_stats.argtypes = [P, P, P]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:
@@ -313,6 +317,24 @@ class Volume:
                                 poses(*T_new), m, mode, ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)),
               "sc_autotune")
         return (best.vpl, best.waves_per_wg, best.wgs_per_cu), float(ms.value)
+
+    def batch_timing(self, capacity: int):
+        """Record HIP events around the voxel pass of the next `capacity` batched launches."""
+        self._timing_cap = capacity
+        check(lib().sc_batch_timing(self._h, capacity), "sc_batch_timing")
+
+    def batch_timing_read(self):
+        cap = max(getattr(self, "_timing_cap", 0), 1)
+        ms = (ctypes.c_float * cap)()
+        n = ctypes.c_int32()
+        check(lib().sc_batch_timing_read(self._h, ms, ctypes.byref(n)), "sc_batch_timing_read")
+        return list(ms[:n.value])
+
+    def stats(self, stream=None):
+        """(candidate blocks, block-operation pairs, voxel updates, blocks written), cumulative."""
+        out = (ctypes.c_int64 * 4)()
+        check(lib().sc_volume_stats(self._h, stream_handle(stream), out), "sc_volume_stats")
+        return tuple(int(x) for x in out)
 
     def integrate_backward(self, kfs, intr, R, t, grad_D, grad_C, grad_depth, grad_color, grad_xi, stream=None):
         karr = keyframes(kfs)

@@ -171,3 +171,36 @@ def test_no_pose_change_selects_nothing(scene):
     after = vol.export_sorted()
     np.testing.assert_array_equal(before["D"], after["D"])
     vol.close()
+
+
+def test_pass_counters_and_timing(scene):
+    """The voxel pass's counters (used for the roofline's algorithmic bytes)
+    equal what the oracle's touched sets imply, and the timing events fire."""
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 21)
+    _say("pass counters")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t)
+    vol.batch_timing(2)
+    s0 = vol.stats()
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    s1 = vol.stats()
+    ms = vol.batch_timing_read()
+    vol.batch_timing(0)
+    cand, pairs, upd, written = [b - a for a, b in zip(s0, s1)]
+    n_blocks = vol.check_error()
+    probe = oracle.Volume(S, MU)
+    blocks, n_upd, n_pairs = set(), 0, 0
+    for poses in ((R, t), (Rn, tn)):
+        for k in order:
+            rec = probe.record(okf[k], wl.intr, poses[0][k], poses[1][k])
+            n_upd += len(rec["pix"])
+            b = set(map(tuple, np.floor_divide(rec["n"], 8).tolist()))
+            n_pairs += len(b)
+            blocks |= b
+    print(f"candidates {cand} pairs {pairs} (>= {n_pairs}) updates {upd} written {written} blocks {n_blocks}",
+          flush=True)
+    assert upd == n_upd
+    assert written == len(blocks)
+    assert pairs >= n_pairs and cand >= written and written <= n_blocks
+    assert len(ms) == 1 and ms[0] > 0
+    vol.close()

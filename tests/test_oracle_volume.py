@@ -284,3 +284,22 @@ def test_weight_quantisation_drops_tiny_weights():
     v.integrate(_const_kf(np.float32(1.5), 0.0006), INTR, np.eye(3), np.zeros(3))
     f = v.export()
     assert np.all(f["W"][f["W"] > 0] == 2.0**-10)
+
+
+def test_voxel_sequence_equals_volume_path(c1):
+    """The per-voxel sequence (used to check large volumes on samples) equals
+    the volume path on every voxel of a small case."""
+    wl, kf = c1
+    Rp, tp = synth.perturb_fixed(wl.R[:1], wl.t[:1], 0.01, 0.5, 11)
+    v = oracle.Volume(S, MU)
+    v.integrate(kf, wl.intr, wl.R[0], wl.t[0])
+    v.deintegrate(kf, wl.intr, wl.R[0], wl.t[0])
+    v.integrate(kf, wl.intr, Rp[0], tp[0])
+    f = v.export()
+    ops = [(0, 1, wl.R[0], wl.t[0]), (0, -1, wl.R[0], wl.t[0]), (0, 1, Rp[0], tp[0])]
+    rng = np.random.default_rng(0)
+    for b in rng.choice(len(f["blocks"]), 20, replace=False):
+        for i in rng.choice(512, 8, replace=False):
+            n = 8 * f["blocks"][b] + np.array([i & 7, (i >> 3) & 7, i >> 6])
+            D, W, C, rc = v.voxel_sequence([kf], wl.intr, ops, n)
+            assert rc >= 0 and W == f["W"][b, i] and D == f["D"][b, i] and np.array_equal(C, f["C"][b, i])
