@@ -209,15 +209,23 @@ sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
                             sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
                             int32_t* selected_out, int32_t* n_selected, void* stream);
 
-/* Schedule of the batched voxel pass: voxels per lane (8, 4, 2 or 1; a
- * block is handled by 8 / vpl wavefronts), wavefronts per workgroup when a
- * block takes one wavefront, and persistent workgroups per compute unit.
- * sc_set_schedule validates and stores it in the volume; sc_get_schedule
- * reads it back. */
+/* Schedule of the batched voxel pass.
+ *   vpl          voxels per lane: 8, 4, 2 or 1; a block is handled by 8 / vpl
+ *                wavefronts.
+ *   waves_per_wg wavefronts per workgroup.  Derived (4 for vpl 8, else
+ *                8 / vpl) unless `compact` is set, where it may be 1, 2 or 4.
+ *   wgs_per_cu   persistent workgroups per compute unit, 1..32.
+ *   compact      0: each lane updates its own voxels, block state held in
+ *                registers.  1 (vpl 8 only): block state held in LDS, the
+ *                touched voxels of each operation are gathered into an LDS
+ *                queue and updated by all 64 lanes together.
+ * Every schedule gives identical bits.  sc_set_schedule validates and stores
+ * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back. */
 typedef struct {
     int32_t vpl;
     int32_t waves_per_wg;
     int32_t wgs_per_cu;
+    int32_t compact;
 } sc_schedule;
 sc_status sc_set_schedule(sc_volume* vol, const sc_schedule* sched);
 sc_status sc_get_schedule(sc_volume* vol, sc_schedule* sched);

@@ -57,11 +57,27 @@ __device__ inline int mask_count(const CandDev& cd, uint32_t h)
     return c;
 }
 
-__global__ void hist_kernel(CandDev cd)
+// Each workgroup takes a contiguous share of the candidate list, so the
+// histogram and the scatter below see the same elements per workgroup.
+__device__ inline void wg_share(uint32_t n, uint32_t& b0, uint32_t& b1)
 {
-    const uint32_t n = min(cd.counters[4], cd.cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        atomicAdd(cd.bins + mask_count(cd, cd.list[i]), 1u);
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    b0 = min(n, blockIdx.x * per);
+    b1 = min(n, b0 + per);
+}
+
+// Histogram of operation counts, privatised in LDS per workgroup.
+__global__ __launch_bounds__(256) void hist_kernel(CandDev cd, int n_bins)
+{
+    __shared__ uint32_t h[kMaxBatchOps + 1];
+    uint32_t b0, b1;
+    wg_share(min(cd.counters[4], cd.cap), b0, b1);
+    for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
+    __syncthreads();
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) atomicAdd(h + mask_count(cd, cd.list[i]), 1u);
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
+        if (h[c]) atomicAdd(cd.bins + c, h[c]);
 }
 
 // Exclusive scan in descending operation count: offset[c] = #blocks with more
@@ -97,13 +113,23 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
     }
 }
 
-__global__ void scatter_kernel(CandDev cd)
+// Scatter into operation-count order: each workgroup reserves one range per
+// count it holds, then places its elements inside those ranges.
+__global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, int n_bins)
 {
-    const uint32_t n = min(cd.counters[4], cd.cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t h = cd.list[i];
-        const uint32_t pos = atomicAdd(cd.bins + mask_count(cd, h), 1u);
-        cd.sorted[pos] = h;
+    __shared__ uint32_t h[kMaxBatchOps + 1];
+    uint32_t b0, b1;
+    wg_share(min(cd.counters[4], cd.cap), b0, b1);
+    for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
+    __syncthreads();
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) atomicAdd(h + mask_count(cd, cd.list[i]), 1u);
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
+        if (h[c]) h[c] = atomicAdd(cd.bins + c, h[c]);
+    __syncthreads();
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const uint32_t hh = cd.list[i];
+        cd.sorted[atomicAdd(h + mask_count(cd, hh), 1u)] = hh;
     }
 }
 
@@ -182,31 +208,27 @@ __device__ inline void apply_op(const OpDesc& op, const VolDev& v, int bx, int b
 #pragma unroll
     for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
     const double bz64 = (qz + (double)(lane & 7) * op.az[0]) + (double)(lane >> 3) * op.az[1];
+    VoxHits<CM, VPL> h;
+    test_voxels<CM, VPL>(op, v.mu, base, kz0, h);
+    if (h.hit == 0u) return;
+    if (op.sign < 0 && !allocated) {
+        e_notalloc = true;
+        return;
+    }
+    if (op.sign > 0) re_touch = true;
+    touched |= h.hit;
+    n_upd += __popc(h.hit);
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
-        const float fz = (float)(kz0 + j);
-        const float px = base[0] + fz * op.a[2][0];
-        const float py = base[1] + fz * op.a[2][1];
-        const float pz = base[2] + fz * op.a[2][2];
-        int pix;
-        float w, z;
-        if (!touch(op, v.mu, px, py, pz, pix, w, z)) continue;
-        const float d = distance(z, bz64 + (double)(kz0 + j) * op.az[2]);
-        if (op.sign < 0 && !allocated) {
-            e_notalloc = true;
-            continue;
-        }
-        if (op.sign > 0) re_touch = true;
-        touched |= 1u << j;
-        ++n_upd;
+        if (!((h.hit >> j) & 1u)) continue;
+        const float d = distance(h.z[j], bz64 + (double)(kz0 + j) * op.az[2]);
         if (CM == SC_COLOR_RGBA8) {
-            const uint32_t c = __ldg(reinterpret_cast<const uint32_t*>(op.color) + pix);
-            e_weight |= !update_rgba8(s.D[j], s.W[j], s.C[j], d, w, c, op.sign);
+            e_weight |= !update_rgba8(s.D[j], s.W[j], s.C[j], d, h.w[j], h.c[j], op.sign);
         } else {
-            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * pix;
+            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * h.pix[j];
             const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
             double C3[3] = {s.Cf[0][j], s.Cf[1][j], s.Cf[2][j]};
-            e_weight |= !update_f32(s.D[j], s.W[j], C3, d, w, c, op.sign);
+            e_weight |= !update_f32(s.D[j], s.W[j], C3, d, h.w[j], c, op.sign);
             s.Cf[0][j] = C3[0];
             s.Cf[1][j] = C3[1];
             s.Cf[2][j] = C3[2];
@@ -264,6 +286,175 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
         const bool wrote = __ballot(touched != 0) != 0;
         n_written += (slot >= 0 && wrote) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
+    }
+    atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
+    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
+    atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
+}
+
+// LDS bytes per wavefront of the compacting voxel pass: block state
+// (D, W f32; colour RGBA8 u32 or 3 x f64) and the queue of one operation's
+// touched voxels (pixel u32, voxel u16).
+template <int CM>
+constexpr int compact_wave_bytes()
+{
+    return 512 * (4 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24) + 4 + 2);
+}
+
+// Orders this wavefront's LDS accesses: the lanes that write a queue entry or
+// a voxel are not the lanes that read it next.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Persistent voxel pass, compacting: one wavefront per block with the block
+// state in LDS.  For each operation the lanes test their own eight voxels,
+// the touched ones are gathered into an LDS queue (ballot + mbcnt), and all
+// 64 lanes then update consecutive queue entries, so the update work follows
+// the number of touched voxels rather than the number of z-slices that hold
+// one.  Per voxel the operations still apply in bit order.
+template <int CM>
+__global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)bcast(threadIdx.x >> 6);
+    unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM>();
+    float* sD = reinterpret_cast<float*>(wb);
+    float* sW = sD + 512;
+    uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);  // RGBA8
+    double* sCf = reinterpret_cast<double*>(sW + 512);     // FP32 colour: [3][512]
+    uint32_t* qpix = reinterpret_cast<uint32_t*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    uint16_t* qvox = reinterpret_cast<uint16_t*>(qpix + 512);
+    const uint32_t n = min(cd.counters[4], cd.cap);
+    uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
+    for (;;) {
+        const uint32_t i = wave_fetch_add1(cd.counters + 5, lane);
+        if (i >= n) break;
+        const uint32_t h = bcast(cd.sorted[i]);
+        const uint64_t key = bcast64(cd.keys[h]);
+        int bx, by, bz;
+        unpack_key(key, bx, by, bz);
+        int slot = (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
+        {
+            const float* blk = v.pool + (size_t)max(slot, 0) * v.stride;
+            const bool have = slot >= 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                sD[x] = have ? blk[x] : 0.0f;
+                sW[x] = have ? blk[512 + x] : 0.0f;
+                if (CM == SC_COLOR_RGBA8) {
+                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk)[1024 + x] : 0u;
+                } else {
+                    const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+                    sCf[x] = have ? Cd[x] : 0.0;
+                    sCf[512 + x] = have ? Cd[512 + x] : 0.0;
+                    sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
+                }
+            }
+        }
+        wave_lds_sync();
+        uint32_t touched = 0;
+        bool re_touch = false, e_na = false, e_w = false;
+        for (int w = 0; w < cd.words; ++w) {
+            uint64_t m = bcast64(cd.mask[(size_t)h * cd.words + w]);
+            n_pairs += __popcll(m);
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const OpDesc& op = ops[w * 64 + b];
+                float q[3];
+                double qz;
+                block_origin(op, v.s, bx, by, bz, q, qz);
+                const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+                float base[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
+                VoxHits<CM, 8> hv;
+                test_voxels<CM, 8, false>(op, v.mu, base, 0, hv);
+                if (__ballot(hv.hit != 0u) == 0) continue;
+                if (op.sign < 0 && slot < 0) {
+                    e_na = true;
+                    continue;
+                }
+                if (op.sign > 0) re_touch = true;
+                touched |= hv.hit;
+                n_upd += __popc(hv.hit);
+                // gather the touched voxels, z-slice by z-slice
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool t = (hv.hit >> j) & 1u;
+                    const uint64_t bal = __ballot(t);
+                    if (t) {
+                        const uint32_t pos = cnt + lanes_below(bal);
+                        qvox[pos] = (uint16_t)(lane + 64 * j);
+                        qpix[pos] = (uint32_t)hv.pix[j];
+                    }
+                    cnt += (uint32_t)__popcll(bal);
+                }
+                wave_lds_sync();
+                // dense update of the queue, 64 entries per round
+                for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+                    const uint32_t e = r0 + (uint32_t)lane;
+                    if (e < cnt) {
+                        const int x = qvox[e];
+                        const int p = (int)qpix[e];
+                        const float wq = qweight(__ldg(op.weight + p));
+                        const float z = __ldg(op.depth + p);
+                        const double pz64 = ((qz + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
+                                            (double)(x >> 6) * op.az[2];
+                        const float d = distance(z, pz64);
+                        float D = sD[x], W = sW[x];
+                        if (CM == SC_COLOR_RGBA8) {
+                            uint32_t C = sC[x];
+                            const uint32_t c = __ldg(reinterpret_cast<const uint32_t*>(op.color) + p);
+                            e_w |= !update_rgba8(D, W, C, d, wq, c, op.sign);
+                            sC[x] = C;
+                        } else {
+                            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * p;
+                            const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
+                            double C3[3] = {sCf[x], sCf[512 + x], sCf[1024 + x]};
+                            e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
+                            sCf[x] = C3[0];
+                            sCf[512 + x] = C3[1];
+                            sCf[1024 + x] = C3[2];
+                        }
+                        sD[x] = D;
+                        sW[x] = W;
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        const int all = (__ballot(re_touch) ? 1 : 0) | (__ballot(e_na) ? 2 : 0) | (__ballot(e_w) ? 4 : 0);
+        if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, bx, by, bz, lane);
+        if (slot >= 0) {
+            float* blk = v.pool + (size_t)slot * v.stride;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (!((touched >> j) & 1u)) continue;
+                const int x = lane + 64 * j;
+                blk[x] = sD[x];
+                blk[512 + x] = sW[x];
+                if (CM == SC_COLOR_RGBA8) {
+                    reinterpret_cast<uint32_t*>(blk)[1024 + x] = sC[x];
+                } else {
+                    double* Cd = reinterpret_cast<double*>(blk + 1024);
+                    Cd[x] = sCf[x];
+                    Cd[512 + x] = sCf[512 + x];
+                    Cd[1024 + x] = sCf[1024 + x];
+                }
+            }
+        }
+        const bool wrote = __ballot(touched != 0) != 0;
+        n_written += (slot >= 0 && wrote) ? 1u : 0u;
+        retire_candidate(cd, v, h, all, lane);
+        wave_lds_sync();
     }
     atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
     atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
@@ -349,20 +540,39 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
 static bool schedule_ok(const sc_schedule& s)
 {
     if (s.vpl != 8 && s.vpl != 4 && s.vpl != 2 && s.vpl != 1) return false;
+    if (s.compact != 0 && s.compact != 1) return false;
+    if (s.compact && (s.vpl != 8 || (s.waves_per_wg != 1 && s.waves_per_wg != 2 && s.waves_per_wg != 4)))
+        return false;
     return s.wgs_per_cu >= 1 && s.wgs_per_cu <= 32;
 }
 
-static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t s, bool events)
+// Candidate stage: clears the per-batch counters, generates the candidate
+// blocks with their operation masks, and orders them by operation count.
+static void launch_candidates(sc_volume* vol, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     cand_batch_kernel<<<vol->n_cu * 16, 256, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
-    hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand);
+    hist_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand);
-    if (events) (void)hipEventRecordWithFlags(vol->tev[0], s, hipEventRecordExternal);
+    scatter_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
+}
+
+// The persistent voxel pass with schedule `sch`.
+static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_t s)
+{
     const bool rgba = vol->p.color_mode == SC_COLOR_RGBA8;
     const int grid = vol->n_cu * sch.wgs_per_cu;
+    if (sch.compact) {
+        const int threads = 64 * sch.waves_per_wg;
+        if (rgba)
+            batch_compact_kernel<SC_COLOR_RGBA8><<<grid, threads, sch.waves_per_wg * compact_wave_bytes<SC_COLOR_RGBA8>(),
+                                                   s>>>(vol->d_ops, vol->dev, vol->cand);
+        else
+            batch_compact_kernel<SC_COLOR_F32><<<grid, threads, sch.waves_per_wg * compact_wave_bytes<SC_COLOR_F32>(),
+                                                 s>>>(vol->d_ops, vol->dev, vol->cand);
+        return;
+    }
     const int threads = (sch.vpl == 8) ? 256 : 64 * (8 / sch.vpl);
     switch (sch.vpl) {
     case 8:
@@ -390,7 +600,6 @@ static void launch_sequence(sc_volume* vol, const sc_schedule& sch, hipStream_t 
             batch_main_group_kernel<SC_COLOR_F32, 1><<<grid, threads, 0, s>>>(vol->d_ops, vol->dev, vol->cand);
         break;
     }
-    if (events) (void)hipEventRecordWithFlags(vol->tev[1], s, hipEventRecordExternal);
 }
 
 static int sched_index(const sc_schedule& s)
@@ -399,54 +608,55 @@ static int sched_index(const sc_schedule& s)
     return v;
 }
 
-// Returns the graph for the current schedule, capturing it on first use.  The
-// capture records two events around the voxel pass; their nodes are kept so
-// that each launch can record per-launch timing events instead.
-static hipGraphExec_t graph_for(sc_volume* vol)
+// Captures the work that `launch` enqueues on the private capture stream and
+// instantiates it.  Returns null on failure (after clearing HIP's last error).
+template <class F>
+static hipGraphExec_t capture(sc_volume* vol, F&& launch)
 {
-    const int vi = sched_index(vol->sched);
-    const int key = vol->sched.waves_per_wg * 64 + vol->sched.wgs_per_cu;
-    if (vol->graph[vi][0] && vol->graph_keys[vi] == key) return vol->graph[vi][0];
-    if (vol->graph[vi][0]) {
-        (void)hipGraphExecDestroy(vol->graph[vi][0]);
-        vol->graph[vi][0] = nullptr;
-    }
-    if (vol->graph_src[vi]) {
-        (void)hipGraphDestroy(vol->graph_src[vi]);
-        vol->graph_src[vi] = nullptr;
-    }
     hipStream_t cs = vol->cap_stream;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    launch_sequence(vol, vol->sched, cs, true);
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    launch(cs);
     hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return nullptr;
-    // locate the two event-record nodes (in capture order)
-    size_t nn = 0;
-    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return nullptr;
-    std::vector<hipGraphNode_t> nodes(nn);
-    if (nn && hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return nullptr;
-    vol->ev_node[vi][0] = vol->ev_node[vi][1] = nullptr;
-    for (hipGraphNode_t nd : nodes) {
-        hipGraphNodeType ty;
-        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeEventRecord) continue;
-        hipEvent_t e = nullptr;
-        if (hipGraphEventRecordNodeGetEvent(nd, &e) != hipSuccess) continue;
-        if (e == vol->tev[0]) vol->ev_node[vi][0] = nd;
-        if (e == vol->tev[1]) vol->ev_node[vi][1] = nd;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return nullptr;
     }
     hipGraphExec_t ex = nullptr;
     const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
         return nullptr;
     }
-    vol->graph[vi][0] = ex;
-    vol->graph_src[vi] = g;
-    vol->graph_keys[vi] = key;
     return ex;
 }
 
-// Stages and runs one chunk of operations (ops already in vol->h_ops).
+// Returns the candidate-stage graph and the voxel-pass graph for the current
+// schedule, capturing each on first use.
+static bool graphs_for(sc_volume* vol, hipGraphExec_t& pre, hipGraphExec_t& main)
+{
+    if (!vol->graph_pre) vol->graph_pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, cs); });
+    const int vi = sched_index(vol->sched);
+    const int key = (vol->sched.compact * 8 + vol->sched.waves_per_wg) * 64 + vol->sched.wgs_per_cu;
+    if (vol->graph_main[vi] && vol->graph_keys[vi] != key) {
+        (void)hipGraphExecDestroy(vol->graph_main[vi]);
+        vol->graph_main[vi] = nullptr;
+    }
+    if (!vol->graph_main[vi]) {
+        const sc_schedule sch = vol->sched;
+        vol->graph_main[vi] = capture(vol, [&](hipStream_t cs) { launch_voxel_pass(vol, sch, cs); });
+        vol->graph_keys[vi] = key;
+    }
+    pre = vol->graph_pre;
+    main = vol->graph_main[vi];
+    return pre && main;
+}
+
+// Stages and runs one chunk of operations (ops already in vol->h_ops).  With
+// timing enabled, an event pair brackets the voxel pass on the stream.
 static sc_status run_chunk(sc_volume* vol, int n_ops, const sc_intrinsics* in, hipStream_t s)
 {
     vol->h_hdr->n_ops = n_ops;
@@ -455,21 +665,16 @@ static sc_status run_chunk(sc_volume* vol, int n_ops, const sc_intrinsics* in, h
     if (hipMemcpyAsync(vol->d_ops, vol->h_ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(vol->d_hdr, vol->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
-    hipGraphExec_t g = graph_for(vol);
-    if (!g) return SC_EDEVICE;
-    const int vi = sched_index(vol->sched);
-    if (vol->ev_node[vi][0] && vol->ev_node[vi][1]) {
-        hipEvent_t e0 = vol->tev[0], e1 = vol->tev[1];
-        if (vol->timing_n < vol->timing_cap) {
-            e0 = vol->timing_ev[2 * vol->timing_n];
-            e1 = vol->timing_ev[2 * vol->timing_n + 1];
-            vol->timing_n++;
-        }
-        if (hipGraphExecEventRecordNodeSetEvent(g, vol->ev_node[vi][0], e0) != hipSuccess ||
-            hipGraphExecEventRecordNodeSetEvent(g, vol->ev_node[vi][1], e1) != hipSuccess)
-            return SC_EDEVICE;
+    hipGraphExec_t pre = nullptr, main = nullptr;
+    if (!graphs_for(vol, pre, main)) return SC_EDEVICE;
+    if (hipGraphLaunch(pre, s) != hipSuccess) return SC_EDEVICE;
+    const bool timed = vol->timing_n < vol->timing_cap;
+    if (timed && hipEventRecord(vol->timing_ev[2 * vol->timing_n], s) != hipSuccess) return SC_EDEVICE;
+    if (hipGraphLaunch(main, s) != hipSuccess) return SC_EDEVICE;
+    if (timed) {
+        if (hipEventRecord(vol->timing_ev[2 * vol->timing_n + 1], s) != hipSuccess) return SC_EDEVICE;
+        vol->timing_n++;
     }
-    if (hipGraphLaunch(g, s) != hipSuccess) return SC_EDEVICE;
     // the staging buffers may be rewritten only after the copies have run
     if (hipEventRecord(vol->staged, s) != hipSuccess) return SC_EDEVICE;
     return SC_OK;
@@ -511,11 +716,22 @@ using namespace sc;
 
 extern "C" {
 
+// A schedule is usable on a volume if it is valid and its LDS fits in 64 KiB
+// per workgroup.
+static bool schedule_fits(const sc_volume* vol, const sc_schedule& s)
+{
+    if (!schedule_ok(s)) return false;
+    if (!s.compact) return true;
+    const int per = (vol->p.color_mode == SC_COLOR_RGBA8) ? compact_wave_bytes<SC_COLOR_RGBA8>()
+                                                          : compact_wave_bytes<SC_COLOR_F32>();
+    return s.waves_per_wg * per <= 65536;
+}
+
 sc_status sc_set_schedule(sc_volume* vol, const sc_schedule* sched)
 {
-    if (!vol || !sched || !schedule_ok(*sched)) return SC_EINVAL;
+    if (!vol || !sched || !schedule_fits(vol, *sched)) return SC_EINVAL;
     vol->sched = *sched;
-    vol->sched.waves_per_wg = (vol->sched.vpl == 8) ? 4 : 8 / vol->sched.vpl;
+    if (!sched->compact) vol->sched.waves_per_wg = (vol->sched.vpl == 8) ? 4 : 8 / vol->sched.vpl;
     return SC_OK;
 }
 
@@ -577,6 +793,7 @@ sc_status reintegrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
     if (ns < 0) return ns;
     const sc_status st = batch_update(vol, kfs, n_kf, intr, T_integrated, T_new, order.data(), ns, (hipStream_t)stream);
     if (st != SC_OK) return st;
+    if (hipGetLastError() != hipSuccess) return SC_EDEVICE;
     for (int j = 0; j < ns; ++j) T_integrated[order[j]] = T_new[order[j]];
     if (selected_out) memcpy(selected_out, order.data(), sizeof(int32_t) * ns);
     if (n_selected) *n_selected = ns;
@@ -619,8 +836,9 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     sc_volume* tmp = nullptr;
     sc_status st = sc_volume_create(&vol->p, &tmp);
     if (st != SC_OK) return st;
-    static const sc_schedule cands[] = {{8, 4, 2}, {8, 4, 4}, {8, 4, 8}, {4, 2, 8}, {4, 2, 16},
-                                        {2, 4, 4}, {2, 4, 8}, {1, 8, 2}, {1, 8, 4}};
+    static const sc_schedule cands[] = {{8, 4, 2, 0}, {8, 4, 4, 0}, {8, 4, 8, 0}, {4, 2, 8, 0}, {4, 2, 16, 0},
+                                        {2, 4, 4, 0}, {2, 4, 8, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {8, 4, 2, 1},
+                                        {8, 4, 4, 1}, {8, 2, 4, 1},  {8, 2, 8, 1},  {8, 1, 16, 1}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         sc_volume_destroy(tmp);
@@ -629,6 +847,7 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     float bms = 3.0e38f;
     sc_schedule bs = vol->sched;
     for (const sc_schedule& c : cands) {
+        if (!schedule_fits(vol, c)) continue;
         tmp->sched = c;
         float tbest = 3.0e38f;
         for (int rep = 0; rep < 3 && st == SC_OK; ++rep) {

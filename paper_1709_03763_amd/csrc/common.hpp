@@ -113,11 +113,9 @@ struct sc_volume {
     int parity;              // plain-path candidate counter parity
     hipStream_t cap_stream;  // private stream used for graph capture
     hipEvent_t staged;       // recorded after the batch descriptors were copied to the device
-    hipGraphExec_t graph[4][1]; // captured batched sequence per voxels-per-lane choice
-    hipGraph_t graph_src[4];    // the captured graphs (kept for their event-record nodes)
-    hipGraphNode_t ev_node[4][2]; // event-record nodes around the voxel pass
-    int graph_keys[4];       // schedule the graph of each slot was captured with
-    hipEvent_t tev[2];       // default events recorded around the voxel pass
+    hipGraphExec_t graph_pre;   // captured candidate stage (init, candidates, histogram, scan, scatter)
+    hipGraphExec_t graph_main[4]; // captured voxel pass per voxels-per-lane choice
+    int graph_keys[4];       // schedule the voxel-pass graph of each slot was captured with
     hipEvent_t* timing_ev;   // optional per-launch event pairs (2 * timing_cap)
     int timing_cap, timing_n;
     sc_schedule sched;

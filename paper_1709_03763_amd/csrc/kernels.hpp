@@ -36,6 +36,12 @@ __device__ inline uint64_t bcast64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Number of set bits of the wavefront mask m below this lane.
+__device__ inline uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Adds one to *ctr once per wavefront; every lane receives the old value.
 __device__ inline uint32_t wave_fetch_add1(uint32_t* ctr, int lane)
 {
@@ -66,14 +72,35 @@ __device__ inline void block_origin(const OpDesc& op, float s, int bx, int by, i
 
 // Nearest pixel of the pinhole projection; false if behind the camera or
 // outside the image.
+// Pixel coordinate floor(fl32(fl32(t + c) + 0.5)) of t = fl32(a / z) (a
+// correctly rounded division), given r = rcp(z) with at most one ulp of
+// error.  fl32(a * r) is within |a r| 2^-21 of t, so t lies in
+// [a r - e, a r + e] with e = |a r| 2^-20 (+2^-60 for tiny values); the map
+// t -> floor(fl32(fl32(t + c) + 0.5)) is monotone, so when both ends of the
+// interval give the same integer that is the exact result, and when both lie
+// beyond the same image border the pixel is outside either way.  Only the
+// remaining cases take the correctly rounded division.
+__device__ inline float pixel_coord(float a, float z, float r, float c, float limit)
+{
+    const float tq = a * r;
+    const float e = fabsf(tq) * 0x1p-20f + 0x1p-60f;
+    const float lo = floorf(((tq - e) + c) + 0.5f);
+    const float hi = floorf(((tq + e) + c) + 0.5f);
+    if (lo == hi) return lo;
+    if (hi < 0.0f || lo > limit) return -1.0f;
+    return floorf(((a / z) + c) + 0.5f);
+}
+
+// Nearest pixel of the FP32 camera point (px, py, pz); false if behind the
+// camera or outside the image.
 __device__ inline bool nearest_pixel(const OpDesc& op, float px, float py, float pz, int& pix)
 {
     if (!(pz > 0.0f)) return false;
-    const float u = (op.fx * px) / pz + op.cx;
-    const float v = (op.fy * py) / pz + op.cy;
-    const float fu = floorf(u + 0.5f);
-    const float fv = floorf(v + 0.5f);
-    if (!(fu >= 0.0f && fu <= (float)(op.width - 1) && fv >= 0.0f && fv <= (float)(op.height - 1))) return false;
+    const float r = __builtin_amdgcn_rcpf(pz);
+    const float wl = (float)(op.width - 1), hl = (float)(op.height - 1);
+    const float fu = pixel_coord(op.fx * px, pz, r, op.cx, wl);
+    const float fv = pixel_coord(op.fy * py, pz, r, op.cy, hl);
+    if (!(fu >= 0.0f && fu <= wl && fv >= 0.0f && fv <= hl)) return false;
     pix = (int)fv * op.width + (int)fu;
     return true;
 }
@@ -95,66 +122,99 @@ __device__ inline bool touch(const OpDesc& op, float mu, float px, float py, flo
 // Continuous projective distance d = Z*(pixel) - p_z with p_z in FP64.
 __device__ inline float distance(float z, double pz64) { return (float)((double)z - pz64); }
 
+// What one lane learns about its VPL voxels (z = kz0 .. kz0 + VPL - 1 of its
+// column) from one operation.
+template <int CM, int VPL>
+struct VoxHits {
+    uint32_t hit;   // bit j: voxel j is touched
+    int pix[VPL];
+    float w[VPL], z[VPL];
+    uint32_t c[VPL]; // RGBA8 colour at the pixel (RGBA8 mode)
+};
+
+// Touched tests of a lane's VPL voxels: every projection first, then every
+// keyframe load (voxels outside the image read pixel 0, so the loads need no
+// branch and are issued together), then the decisions.
+template <int CM, int VPL, bool kColor = true>
+__device__ inline void test_voxels(const OpDesc& op, float mu, const float base[3], int kz0, VoxHits<CM, VPL>& h)
+{
+    bool in[VPL];
+    float pzv[VPL];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        const float fz = (float)(kz0 + j);
+        const float px = base[0] + fz * op.a[2][0];
+        const float py = base[1] + fz * op.a[2][1];
+        const float pz = base[2] + fz * op.a[2][2];
+        int p = 0;
+        in[j] = nearest_pixel(op, px, py, pz, p);
+        h.pix[j] = in[j] ? p : 0;
+        pzv[j] = pz;
+    }
+    float wr[VPL];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        wr[j] = __ldg(op.weight + h.pix[j]);
+        h.z[j] = __ldg(op.depth + h.pix[j]);
+        if (kColor && CM == SC_COLOR_RGBA8) h.c[j] = __ldg(reinterpret_cast<const uint32_t*>(op.color) + h.pix[j]);
+    }
+    h.hit = 0u;
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        h.w[j] = qweight(wr[j]);
+        const bool t = in[j] && h.w[j] > 0.0f && fabsf(h.z[j] - pzv[j]) <= mu;
+        h.hit |= t ? (1u << j) : 0u;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // voxel updates
 // ---------------------------------------------------------------------------
 
-// Round-half-to-even of N / M (exact rational), clamped to 255.
-// N < 2^32, 0 < M < 2^24.  An FP32 estimate is corrected with the exact
-// integer residual, so the result is the exact rounding.
-__device__ inline uint32_t rne_div_255(uint32_t N, uint32_t M, float rcpM)
+// One RGBA8 channel: round-half-to-even of the exact rational N / M, clamped
+// to [0, 255].  N and M are integers below 2^53 held exactly in FP64 and rM
+// is 1/M to about 2^-52.  For a quotient below 256, N rM misses N / M by
+// less than 2^-43 while a quotient that is not a tie lies at least 1/(2M) >=
+// 2^-25 from every half-integer, so rint(N rM) is the correct rounding except
+// at exact ties, which the exact residual N - q M identifies.
+__device__ inline uint32_t mix_channel(double N, double M, double rM)
 {
-    const float qf = (float)N * rcpM;
-    if (qf >= 256.5f) return 255u;
-    int q = (int)rintf(qf);
-    int twice = 2 * (int)(N - (uint32_t)q * M);  // |residual| < 0.51 M, so no overflow
-    const int m = (int)M;
-    if (twice > m) {
-        q += 1;
-        twice -= 2 * m;
-    } else if (twice < -m) {
-        q -= 1;
-        twice += 2 * m;
-    }
-    if (twice == m && (q & 1)) q += 1;
-    else if (twice == -m && (q & 1)) q -= 1;
-    return (uint32_t)min(max(q, 0), 255);
-}
-
-// One RGBA8 colour channel after (de-)integration: the exact rational
-// (C Wq +- c wq) / W'q on the 2^-10 weight grid, rounded, clamped to [0,255].
-__device__ inline uint32_t mix_channel(uint32_t C, uint32_t c, uint32_t Wq, uint32_t wq, uint32_t W1q, float rcp,
-                                       int sign)
-{
-    int64_t N = (int64_t)C * Wq + (int64_t)sign * (int64_t)c * wq;
-    if (N <= 0) return 0u;
-    return rne_div_255((uint32_t)N, W1q, rcp);
+    const double Np = fmax(N, 0.0);
+    const double q = fmin(rint(Np * rM), 256.0);
+    const double two = 2.0 * fma(-q, M, Np);  // exact for q < 256: integers below 2^53
+    const int k = (int)q;
+    const bool tie = (two == M || two == -M) && (k & 1);
+    return (uint32_t)min(k + (tie ? ((two > 0.0) ? 1 : -1) : 0), 255);
 }
 
 // Integrate (sign +1) or de-integrate (sign -1, Eq. 2) one sample into an
-// RGBA8 voxel held in registers.  Returns false on a weight error.
+// RGBA8 voxel held in registers; on a weight error the voxel is left as it
+// was and false is returned.  The colour is the exact rational
+// (C Wq +- c wq) / W'q on the 2^-10 weight grid (every product below 2^32,
+// so exact in FP64), rounded half to even.  Branch-free.
 __device__ inline bool update_rgba8(float& D, float& W, uint32_t& C, float d, float w, uint32_t c, int sign)
 {
-    const float W1 = (sign > 0) ? W + w : W - w;  // exact on the 2^-10 grid
-    if (sign > 0 ? !(W1 < kWeightLimit) : (W1 < 0.0f)) return false;
-    if (W1 == 0.0f) {
-        D = 0.0f;
-        W = 0.0f;
-        C = 0u;
-        return true;
+    const float sw = (sign > 0) ? w : -w;
+    const float W1 = W + sw;  // exact on the 2^-10 grid
+    const bool bad = !(W1 < kWeightLimit) || W1 < 0.0f;
+    const bool zero = W1 == 0.0f;
+    const float D1 = (D * W + d * sw) * __builtin_amdgcn_rcpf(W1);
+    const double M = (double)W1 * (double)kWeightScale;
+    const double Wq = (double)W * (double)kWeightScale;
+    const double swq = (double)sw * (double)kWeightScale;
+    double rM = __builtin_amdgcn_rcp(M);
+    rM = fma(rM, fma(-M, rM, 1.0), rM);
+    rM = fma(rM, fma(-M, rM, 1.0), rM);
+    uint32_t C1 = 0u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double N = (double)((C >> (8 * k)) & 0xFFu) * Wq + (double)((c >> (8 * k)) & 0xFFu) * swq;
+        C1 |= mix_channel(N, M, rM) << (8 * k);
     }
-    const float rcp = __builtin_amdgcn_rcpf(W1);
-    D = (sign > 0 ? (D * W + d * w) : (D * W - d * w)) * rcp;
-    const uint32_t Wq = (uint32_t)(W * kWeightScale);
-    const uint32_t wq = (uint32_t)(w * kWeightScale);
-    const uint32_t W1q = (uint32_t)(W1 * kWeightScale);
-    const float rcpq = __builtin_amdgcn_rcpf((float)W1q);
-    const uint32_t r = mix_channel(C & 0xFFu, c & 0xFFu, Wq, wq, W1q, rcpq, sign);
-    const uint32_t g = mix_channel((C >> 8) & 0xFFu, (c >> 8) & 0xFFu, Wq, wq, W1q, rcpq, sign);
-    const uint32_t b = mix_channel((C >> 16) & 0xFFu, (c >> 16) & 0xFFu, Wq, wq, W1q, rcpq, sign);
-    C = r | (g << 8) | (b << 16);
-    W = W1;
-    return true;
+    D = bad ? D : (zero ? 0.0f : D1);
+    C = bad ? C : (zero ? 0u : C1);
+    W = bad ? W : (zero ? 0.0f : W1);
+    return !bad;
 }
 
 // FP32-colour mode: keyframe colour FP32 in [0,1]; the voxel colour is held
@@ -255,19 +315,22 @@ __device__ inline int vol_insert_wave(const VolDev& v, uint64_t key, int bx, int
 // candidate blocks
 // ---------------------------------------------------------------------------
 
-constexpr int kTile = 16;     // candidate generation works on 16 x 16 pixel tiles
-constexpr int kLdsSet = 1024; // LDS hash set per tile
+constexpr int kTile = 32;     // candidate generation works on 32 x 32 pixel tiles, 2 x 2 pixels per thread
+constexpr int kLdsSet = 2048; // LDS hash set per tile
 
 // Conservative world-space block range of one pixel's frustum cell
 // (u +- 0.55, v +- 0.55) between depths z - mu and z + mu, padded so that
 // FP32 rounding in the decision convention cannot escape it.
-__device__ inline bool pixel_block_range(const OpDesc& op, float s, float mu, int u, int v, float z, int lo[3],
-                                         int hi[3])
+// The reciprocals ifx = 1/fx, ify = 1/fy and is = 1/s may carry a few ulps of
+// error: the 0.05 px and metric paddings exceed their effect by orders of
+// magnitude.
+__device__ inline bool pixel_block_range(const OpDesc& op, float ifx, float ify, float is, float mu, int u, int v,
+                                         float z, int lo[3], int hi[3])
 {
     const float zl = fmaxf(z - mu - 1e-3f, 0.0f);
     const float zh = z + mu + 1e-3f;
-    const float xl = ((float)u - 0.55f - op.cx) / op.fx, xh = ((float)u + 0.55f - op.cx) / op.fx;
-    const float yl = ((float)v - 0.55f - op.cy) / op.fy, yh = ((float)v + 0.55f - op.cy) / op.fy;
+    const float xl = ((float)u - 0.55f - op.cx) * ifx, xh = ((float)u + 0.55f - op.cx) * ifx;
+    const float yl = ((float)v - 0.55f - op.cy) * ify, yh = ((float)v + 0.55f - op.cy) * ify;
     float mn[3], mx[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -292,8 +355,8 @@ __device__ inline bool pixel_block_range(const OpDesc& op, float s, float mu, in
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const float pad = 2e-3f + 2e-5f * fmaxf(fabsf(mn[r]), fabsf(mx[r]));
-        const float flo = ceilf((mn[r] - pad) / s);
-        const float fhi = floorf((mx[r] + pad) / s);
+        const float flo = ceilf((mn[r] - pad) * is);
+        const float fhi = floorf((mx[r] + pad) * is);
         // keys hold 21-bit block coordinates; a cell wider than 16 blocks means
         // a depth far beyond the voxel scale and is rejected
         ok = ok && (flo > -8.0e6f) && (fhi < 8.0e6f) && (fhi - flo < 128.0f);
@@ -303,24 +366,40 @@ __device__ inline bool pixel_block_range(const OpDesc& op, float s, float mu, in
     return ok;
 }
 
+// Sets operation bit `op_bit` of a candidate's mask.  Bits only go from 0 to
+// 1 within a kernel, so a read that shows the bit set is never stale-wrong;
+// a stale read only costs a redundant atomic.
+__device__ inline void cand_mark(const CandDev& cd, int gb, int op_bit)
+{
+    uint64_t* mw = cd.mask + (size_t)gb * cd.words + (op_bit >> 6);
+    const uint64_t bit = 1ull << (op_bit & 63);
+    if (!(*mw & bit)) atomicOr((unsigned long long*)mw, (unsigned long long)bit);
+}
+
 // Inserts a candidate block into the deduplicating candidate table; returns
-// its bucket, or -1 if the table is full (sticky error set).
+// its bucket, or -1 if the table is full (sticky error set).  Keys only go
+// from empty to a block within a kernel, so a plain read that finds the key
+// is reliable, and the CAS is issued only at an empty-looking bucket.
 __device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t key, int bx, int by, int bz,
                                   uint32_t* count)
 {
     uint32_t h = hash_block(bx, by, bz) & cd.mask_bits;
     for (uint32_t probe = 0; probe <= cd.mask_bits; ++probe) {
-        const uint64_t old = atomicCAS((unsigned long long*)(cd.keys + h), (unsigned long long)kKeyEmpty,
-                                       (unsigned long long)key);
-        if (old == key) return (int)h;
-        if (old == kKeyEmpty) {
-            const uint32_t idx = atomicAdd(count, 1u);
-            if (idx < cd.cap) {
-                cd.list[idx] = h;
-            } else {
-                set_error(v.err, SC_EHASHFULL);
+        const uint64_t seen = cd.keys[h];
+        if (seen == key) return (int)h;
+        if (seen == kKeyEmpty) {
+            const uint64_t old = atomicCAS((unsigned long long*)(cd.keys + h), (unsigned long long)kKeyEmpty,
+                                           (unsigned long long)key);
+            if (old == key) return (int)h;
+            if (old == kKeyEmpty) {
+                const uint32_t idx = atomicAdd(count, 1u);
+                if (idx < cd.cap) {
+                    cd.list[idx] = h;
+                } else {
+                    set_error(v.err, SC_EHASHFULL);
+                }
+                return (int)h;
             }
-            return (int)h;
         }
         h = (h + 1) & cd.mask_bits;
     }
@@ -328,47 +407,80 @@ __device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t k
     return -1;
 }
 
-// Candidate generation for one 16 x 16 tile of one keyframe operation
-// (256 threads): per-pixel conservative block ranges, deduplicated in an
-// LDS hash set, then inserted once per tile into the global candidate table.
-// With op_bit >= 0 the operation's bit is set in the block's mask.
+__device__ inline void lds_insert(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
+                                  int bx, int by, int bz)
+{
+    const uint64_t key = pack_key(bx, by, bz);
+    uint32_t h = hash_block(bx, by, bz) & (kLdsSet - 1);
+    for (int probe = 0; probe < 32; ++probe) {
+        const uint64_t old =
+            atomicCAS((unsigned long long*)(lds + h), (unsigned long long)kKeyEmpty, (unsigned long long)key);
+        if (old == kKeyEmpty || old == key) return;
+        h = (h + 1) & (kLdsSet - 1);
+    }
+    const int gb = cand_insert(cd, v, key, bx, by, bz, count);
+    if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
+}
+
+// Candidate generation for one 32 x 32 tile of one keyframe operation (256
+// threads, a 2 x 2 pixel quad each): per-pixel conservative block ranges —
+// merged into one box per quad when that does not enlarge the candidate
+// volume — deduplicated in an LDS hash set, then inserted once per tile into
+// the global candidate table.  With op_bit >= 0 the operation's bit is set
+// in the block's mask.
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
                                  int ty, int op_bit, uint64_t* lds)
 {
     const int tid = threadIdx.x;
     for (int i = tid; i < kLdsSet; i += blockDim.x) lds[i] = kKeyEmpty;
     __syncthreads();
-    const int u = tx * kTile + (tid & (kTile - 1));
-    const int vv = ty * kTile + (tid >> 4);
-    if (u < op.width && vv < op.height) {
-        const int pix = vv * op.width + u;
-        const float w = qweight(op.weight[pix]);
-        const float z = op.depth[pix];
-        if (w > 0.0f && z > 0.0f && z < 1.0e30f) {
-            int lo[3], hi[3];
-            if (!pixel_block_range(op, v.s, v.mu, u, vv, z, lo, hi)) set_error(v.err, SC_ERANGE);
-            for (int bx = lo[0]; bx <= hi[0]; ++bx)
-                for (int by = lo[1]; by <= hi[1]; ++by)
-                    for (int bz = lo[2]; bz <= hi[2]; ++bz) {
-                        const uint64_t key = pack_key(bx, by, bz);
-                        uint32_t h = hash_block(bx, by, bz) & (kLdsSet - 1);
-                        bool placed = false;
-                        for (int probe = 0; probe < 32; ++probe) {
-                            const uint64_t old = atomicCAS((unsigned long long*)(lds + h),
-                                                           (unsigned long long)kKeyEmpty, (unsigned long long)key);
-                            if (old == kKeyEmpty || old == key) {
-                                placed = true;
-                                break;
-                            }
-                            h = (h + 1) & (kLdsSet - 1);
-                        }
-                        if (!placed) {
-                            const int gb = cand_insert(cd, v, key, bx, by, bz, count);
-                            if (gb >= 0 && op_bit >= 0)
-                                atomicOr((unsigned long long*)(cd.mask + (size_t)gb * cd.words + (op_bit >> 6)),
-                                         1ull << (op_bit & 63));
-                        }
+    const int u0 = tx * kTile + 2 * (tid & 15);
+    const int v0 = ty * kTile + 2 * (tid >> 4);
+    int lo[4][3], hi[4][3];
+    bool have[4];
+    int sum_vol = 0;
+    int ulo[3] = {1 << 30, 1 << 30, 1 << 30}, uhi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    bool any = false;
+    const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int u = u0 + (q & 1), vv = v0 + (q >> 1);
+        have[q] = false;
+        if (u < op.width && vv < op.height) {
+            const int pix = vv * op.width + u;
+            const float w = qweight(op.weight[pix]);
+            const float z = op.depth[pix];
+            if (w > 0.0f && z > 0.0f && z < 1.0e30f) {
+                if (pixel_block_range(op, ifx, ify, is, v.mu, u, vv, z, lo[q], hi[q])) {
+                    have[q] = true;
+                    any = true;
+                    sum_vol += (hi[q][0] - lo[q][0] + 1) * (hi[q][1] - lo[q][1] + 1) * (hi[q][2] - lo[q][2] + 1);
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        ulo[r] = min(ulo[r], lo[q][r]);
+                        uhi[r] = max(uhi[r], hi[q][r]);
                     }
+                } else {
+                    set_error(v.err, SC_ERANGE);
+                }
+            }
+        }
+    }
+    if (any) {
+        const int uvol = (uhi[0] - ulo[0] + 1) * (uhi[1] - ulo[1] + 1) * (uhi[2] - ulo[2] + 1);
+        if (uvol <= sum_vol) {
+            for (int bx = ulo[0]; bx <= uhi[0]; ++bx)
+                for (int by = ulo[1]; by <= uhi[1]; ++by)
+                    for (int bz = ulo[2]; bz <= uhi[2]; ++bz) lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!have[q]) continue;
+                for (int bx = lo[q][0]; bx <= hi[q][0]; ++bx)
+                    for (int by = lo[q][1]; by <= hi[q][1]; ++by)
+                        for (int bz = lo[q][2]; bz <= hi[q][2]; ++bz)
+                            lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
+            }
         }
     }
     __syncthreads();
@@ -378,8 +490,7 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
         const int gb = cand_insert(cd, v, key, bx, by, bz, count);
-        if (gb >= 0 && op_bit >= 0)
-            atomicOr((unsigned long long*)(cd.mask + (size_t)gb * cd.words + (op_bit >> 6)), 1ull << (op_bit & 63));
+        if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
     }
 }
 

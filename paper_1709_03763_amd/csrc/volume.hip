@@ -142,21 +142,9 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
 #pragma unroll
     for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
     const double bz64 = (qz + (double)(lane & 7) * op.az[0]) + (double)(lane >> 3) * op.az[1];
-    uint32_t tmask = 0;
-    int pix[8];
-    float dd[8], ww[8];
-#pragma unroll
-    for (int kz = 0; kz < 8; ++kz) {
-        const float fz = (float)kz;
-        const float px = base[0] + fz * op.a[2][0];
-        const float py = base[1] + fz * op.a[2][1];
-        const float pz = base[2] + fz * op.a[2][2];
-        float z;
-        if (touch(op, v.mu, px, py, pz, pix[kz], ww[kz], z)) {
-            tmask |= 1u << kz;
-            dd[kz] = distance(z, bz64 + (double)kz * op.az[2]);
-        }
-    }
+    VoxHits<CM, 8> hv;
+    test_voxels<CM, 8>(op, v.mu, base, 0, hv);
+    const uint32_t tmask = hv.hit;
     if (__ballot(tmask != 0) == 0) return;
     const int slot = (op.sign > 0) ? vol_insert_wave(v, key, bx, by, bz, lane) : (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
     if (slot < 0) {
@@ -170,18 +158,18 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
         if (!((tmask >> kz) & 1u)) continue;
         const int i = lane + 64 * kz;
         float D = blk[i], W = blk[512 + i];
+        const float dd = distance(hv.z[kz], bz64 + (double)kz * op.az[2]);
         if (CM == SC_COLOR_RGBA8) {
             uint32_t* Cp = reinterpret_cast<uint32_t*>(blk) + 1024;
             uint32_t C = Cp[i];
-            const uint32_t c = reinterpret_cast<const uint32_t*>(op.color)[pix[kz]];
-            bad |= !update_rgba8(D, W, C, dd[kz], ww[kz], c, op.sign);
+            bad |= !update_rgba8(D, W, C, dd, hv.w[kz], hv.c[kz], op.sign);
             Cp[i] = C;
         } else {
             double* Cd = reinterpret_cast<double*>(blk + 1024);
             double C[3] = {Cd[i], Cd[512 + i], Cd[1024 + i]};
-            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * pix[kz];
+            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * hv.pix[kz];
             const float c[3] = {cp[0], cp[1], cp[2]};
-            bad |= !update_f32(D, W, C, dd[kz], ww[kz], c, op.sign);
+            bad |= !update_f32(D, W, C, dd, hv.w[kz], c, op.sign);
             Cd[i] = C[0];
             Cd[512 + i] = C[1];
             Cd[1024 + i] = C[2];
@@ -362,8 +350,6 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipHostMalloc((void**)&vol->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
     ok &= hipStreamCreateWithFlags(&vol->cap_stream, hipStreamNonBlocking) == hipSuccess;
     ok &= hipEventCreateWithFlags(&vol->staged, hipEventDisableTiming) == hipSuccess;
-    ok &= hipEventCreate(&vol->tev[0]) == hipSuccess;
-    ok &= hipEventCreate(&vol->tev[1]) == hipSuccess;
     if (!ok) {
         sc_volume_destroy(vol);
         return SC_ENOMEM;
@@ -383,13 +369,9 @@ void sc_volume_destroy(sc_volume* vol)
 {
     if (!vol) return;
     hipDeviceSynchronize();
-    for (auto& row : vol->graph)
-        for (auto& g : row)
-            if (g) hipGraphExecDestroy(g);
-    for (auto& g : vol->graph_src)
-        if (g) hipGraphDestroy(g);
-    if (vol->tev[0]) hipEventDestroy(vol->tev[0]);
-    if (vol->tev[1]) hipEventDestroy(vol->tev[1]);
+    if (vol->graph_pre) hipGraphExecDestroy(vol->graph_pre);
+    for (auto& g : vol->graph_main)
+        if (g) hipGraphExecDestroy(g);
     for (int i = 0; i < 2 * vol->timing_cap; ++i) hipEventDestroy(vol->timing_ev[i]);
     delete[] vol->timing_ev;
     hipFree(vol->cand.stats);

@@ -56,7 +56,8 @@ class sc_fuse_params(ctypes.Structure):
 
 
 class sc_schedule(ctypes.Structure):
-    _fields_ = [("vpl", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32)]
+    _fields_ = [("vpl", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("compact", ctypes.c_int32)]
 
 
 EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
@@ -300,14 +301,14 @@ class Volume:
     def reintegrate_plain(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
         return self._reint(lib().reintegrate_plain, kfs, intr, T_int, T_new, m, mode, stream)
 
-    def set_schedule(self, vpl, waves_per_wg, wgs_per_cu):
-        s = sc_schedule(vpl, waves_per_wg, wgs_per_cu)
+    def set_schedule(self, vpl, waves_per_wg, wgs_per_cu, compact=0):
+        s = sc_schedule(vpl, waves_per_wg, wgs_per_cu, compact)
         check(lib().sc_set_schedule(self._h, ctypes.byref(s)), "sc_set_schedule")
 
     def get_schedule(self):
         s = sc_schedule()
         check(lib().sc_get_schedule(self._h, ctypes.byref(s)), "sc_get_schedule")
-        return (s.vpl, s.waves_per_wg, s.wgs_per_cu)
+        return (s.vpl, s.waves_per_wg, s.wgs_per_cu, s.compact)
 
     def autotune(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
         karr = keyframes(kfs)
@@ -316,7 +317,7 @@ class Volume:
         check(lib().sc_autotune(self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), poses(*T_int),
                                 poses(*T_new), m, mode, ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)),
               "sc_autotune")
-        return (best.vpl, best.waves_per_wg, best.wgs_per_cu), float(ms.value)
+        return (best.vpl, best.waves_per_wg, best.wgs_per_cu, best.compact), float(ms.value)
 
     def batch_timing(self, capacity: int):
         """Record HIP events around the voxel pass of the next `capacity` batched launches."""

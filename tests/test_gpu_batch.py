@@ -83,7 +83,8 @@ def test_batch_matches_oracle_and_plain(scene, f32, mode):
     vol2.close()
 
 
-@pytest.mark.parametrize("sched", [(8, 4, 4), (8, 4, 1), (4, 2, 8), (2, 4, 4), (1, 8, 2)])
+@pytest.mark.parametrize("sched", [(8, 4, 4), (8, 4, 1), (4, 2, 8), (2, 4, 4), (1, 8, 2), (8, 4, 4, 1), (8, 2, 8, 1),
+                                   (8, 1, 3, 1)])
 def test_every_schedule_gives_identical_bits(scene, sched):
     wl, kfs, R, t = scene
     Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 5)
@@ -94,6 +95,34 @@ def test_every_schedule_gives_identical_bits(scene, sched):
     _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
     vol.check_error()
     compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
+@pytest.mark.parametrize("sched", [(8, 2, 4, 1), (4, 2, 8)])
+def test_fp32_colour_schedules(scene, sched):
+    """FP32-colour volumes under the compacting and the multi-wavefront
+    passes."""
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 6)
+    _say(f"f32 schedule {sched}")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t, f32=True)
+    vol.set_schedule(*sched)
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
+    vol.check_error()
+    compare_fields(vol.export_sorted(), ref.export(), exact_color=False)
+    vol.close()
+
+
+def test_schedule_validation(scene):
+    vol = scsurf.Volume(S, MU, 1 << 10, 1 << 8, color_mode=scsurf.COLOR_F32)
+    for bad in [(3, 4, 4), (8, 4, 0), (8, 4, 33), (4, 2, 8, 1), (8, 3, 4, 1), (8, 4, 4, 1), (8, 4, 4, 2)]:
+        with pytest.raises(scsurf.ScError):
+            vol.set_schedule(*bad)
+    vol.set_schedule(8, 2, 4, 1)
+    assert vol.get_schedule() == (8, 2, 4, 1)
+    vol.set_schedule(4, 1, 8)
+    assert vol.get_schedule() == (4, 2, 8, 0)
     vol.close()
 
 
