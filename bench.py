@@ -50,7 +50,7 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def build_workload(torch, scsurf, synth, n_kf, seed):
+def build_workload(torch, scsurf, synth, n_kf, seed, pack=True):
     wl = synth.workload(4)
     groups = synth.keyframe_groups(wl)[:n_kf]
     dev = torch.device("cuda")
@@ -86,7 +86,15 @@ def build_workload(torch, scsurf, synth, n_kf, seed):
         kf.color.mul_(keep[..., None].to(torch.uint8))
     R = np.array([wl.R[g[0]] for g in groups])
     t = np.array([wl.t[g[0]] for g in groups])
-    return wl, kfs, R, t, fuse_s, fracs
+    pack_s = None
+    if pack:
+        # the interleaved copy the voxel passes gather from, made once per keyframe
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kfs = [scsurf.keyframe_pack(k) for k in kfs]
+        torch.cuda.synchronize()
+        pack_s = time.perf_counter() - t0
+    return wl, kfs, R, t, fuse_s, fracs, pack_s
 
 
 def cpu_baseline(oracle, kfs_np, intr, A, B, sample):
@@ -159,7 +167,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time every voxel-pass schedule (stderr) before the timed steps")
+    ap.add_argument("--schedule", type=str, default="",
+                    help="fixed voxel-pass schedule vpl,waves_per_wg,wgs_per_cu,compact (skips the autotuner)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-pack", action="store_true",
+                    help="keyframes without the interleaved copy (three gathers per voxel test)")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a device copy of this size (for counter calibration)")
@@ -180,7 +194,7 @@ def main():
     torch.cuda.set_device(0)
     scsurf.lib()
     n_kf = args.keyframes
-    wl, kfs, R, t, fuse_s, fracs = build_workload(torch, scsurf, synth, n_kf, seed=4)
+    wl, kfs, R, t, fuse_s, fracs, pack_s = build_workload(torch, scsurf, synth, n_kf, seed=4, pack=not args.no_pack)
     H, Wd = wl.intr.height, wl.intr.width
     log(f"fused {n_kf} keyframes in {fuse_s * 1e3:.1f} ms")
     A = (R, t)
@@ -202,11 +216,27 @@ def main():
         state[0], state[1] = state[1], state[0]
         return order
 
-    sched = vol.get_schedule()
     tune_ms = None
-    if not args.no_autotune:
+    if args.schedule:
+        vol.set_schedule(*[int(x) for x in args.schedule.split(",")])
+    sched = vol.get_schedule()
+    if not args.no_autotune and not args.schedule:
         sched, tune_ms = vol.autotune(kfs, wl.intr, state[0], state[1], n_kf, mode)
         log(f"autotuned schedule {sched} ({tune_ms:.2f} ms)")
+    if args.sweep:
+        sweep = [(8, 4, 2, 0), (8, 4, 4, 0), (8, 4, 8, 0), (4, 2, 8, 0), (4, 2, 16, 0), (2, 4, 4, 0), (2, 4, 8, 0),
+                 (1, 8, 2, 0), (1, 8, 4, 0), (8, 4, 2, 1), (8, 4, 4, 1), (8, 2, 4, 1), (8, 2, 8, 1), (8, 1, 16, 1), (8, 4, 4, 2), (8, 2, 8, 2), (8, 1, 16, 2)]
+        keep = vol.get_schedule()
+        for sc in sweep:
+            vol.set_schedule(*sc)
+            step(vol.reintegrate_batch)
+            vol.batch_timing(4)
+            for _ in range(4):
+                step(vol.reintegrate_batch)
+            ms = vol.batch_timing_read()
+            vol.batch_timing(0)
+            log(f"sweep schedule {sc}: voxel pass {min(ms):.3f} ms (median {sorted(ms)[len(ms) // 2]:.3f})")
+        vol.set_schedule(*keep)
     order = []
     for _ in range(args.warmup):
         order = step(vol.reintegrate_batch)
@@ -316,6 +346,7 @@ def main():
         "plain": plain,
         "stages": {"kf_fuse_frames_per_s": round(n_kf * wl.kappa / fuse_s, 1),
                    "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
+                   "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),
                    "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms},
     }
     print(json.dumps(out), flush=True)

@@ -88,11 +88,19 @@ typedef struct {
     int32_t max_batch_ops; /* capacity of one batched update, in keyframe operations (<= 4096) */
 } sc_volume_params;
 
-/* A fused keyframe (Sec. 4.1): depth Z*, fusion weight W*, colour C*. */
+/* A fused keyframe (Sec. 4.1): depth Z*, fusion weight W*, colour C*.
+ * `packed` is optional (NULL: not used): a device copy of the same keyframe
+ * interleaved for the voxel passes, H x W records of 16 bytes
+ * {float depth, float weight, uint32 RGBA8 colour, uint32 0}, 16-byte
+ * aligned, as written by sc_keyframe_pack.  Volumes in RGBA8 mode then read
+ * every keyframe sample from it (one 16-byte gather per voxel instead of
+ * three); FP32-colour volumes ignore it.  It must hold the packing of this
+ * keyframe's depth, weight and colour, and is owned by the caller. */
 typedef struct {
     const float* depth;  /* device, H x W, metres */
     const float* weight; /* device, H x W; quantised to 2^-10 when used */
     const void* color;   /* device, per the volume's colour mode */
+    const void* packed;  /* device, optional, see above */
 } sc_keyframe;
 
 /* Keyframe fusion parameters (Sec. 3, "Keyframe Fusion"). */
@@ -103,6 +111,13 @@ typedef struct {
 } sc_fuse_params;
 
 typedef struct sc_volume sc_volume;
+
+/* Writes the interleaved copy of an RGBA8 keyframe used by the voxel passes:
+ * packed[i] = {depth[i], weight[i], color[i], 0} for the width * height
+ * pixels.  `packed` is a caller-owned device buffer of width * height * 16
+ * bytes, 16-byte aligned.  SC_EINVAL on a null pointer, a misaligned buffer
+ * or a non-positive size; asynchronous on `stream`. */
+sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream);
 
 /* ---- volume lifecycle --------------------------------------------------- */
 
@@ -216,9 +231,10 @@ sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
  *                8 / vpl) unless `compact` is set, where it may be 1, 2 or 4.
  *   wgs_per_cu   persistent workgroups per compute unit, 1..32.
  *   compact      0: each lane updates its own voxels, block state held in
- *                registers.  1 (vpl 8 only): block state held in LDS, the
- *                touched voxels of each operation are gathered into an LDS
- *                queue and updated by all 64 lanes together.
+ *                registers.  1 or 2 (vpl 8 only): block state held in LDS,
+ *                the touched voxels of each operation are gathered into an
+ *                LDS queue and updated by all 64 lanes together; 2 tests a
+ *                lane's voxels four at a time (fewer registers).
  * Every schedule gives identical bits.  sc_set_schedule validates and stores
  * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back. */
 typedef struct {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
-    if (tid == 0) cd.stats[0] += min(cd.counters[4], cd.cap);
+    if (tid == 0) cd.stats[0] += min(cd.counters[4], cd.cap);  // slot 0 of counter 0
     const int per = (n_bins + 1023) / 1024;
     // thread tid owns bins (descending) [n_bins-1 - tid*per, ...]
     uint32_t sum = 0;
@@ -254,9 +254,13 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
     constexpr int VPL = 8;
     const int lane = threadIdx.x & 63;
     const uint32_t n = min(cd.counters[4], cd.cap);
+    const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + bcast(threadIdx.x >> 6);
+    const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
+    WorkCursor cur;
+    cursor_init(cur, worker);
     uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
-        const uint32_t i = wave_fetch_add1(cd.counters + 5, lane);
+        const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
         const uint64_t key = bcast64(cd.keys[h]);
@@ -287,9 +291,9 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
         n_written += (slot >= 0 && wrote) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
     }
-    atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
-    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
-    atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
+    stat_add(cd, 1, worker, n_pairs, lane);
+    stat_add(cd, 2, worker, wave_sum(n_upd), lane);
+    stat_add(cd, 3, worker, n_written, lane);
 }
 
 // LDS bytes per wavefront of the compacting voxel pass: block state
@@ -315,8 +319,9 @@ __device__ inline void wave_lds_sync()
 // the touched ones are gathered into an LDS queue (ballot + mbcnt), and all
 // 64 lanes then update consecutive queue entries, so the update work follows
 // the number of touched voxels rather than the number of z-slices that hold
-// one.  Per voxel the operations still apply in bit order.
-template <int CM>
+// one.  Per voxel the operations still apply in bit order.  TV voxels per
+// lane are tested at a time (8, or 4 to keep fewer values live).
+template <int CM, int TV>
 __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -330,9 +335,13 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     uint32_t* qpix = reinterpret_cast<uint32_t*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
     uint16_t* qvox = reinterpret_cast<uint16_t*>(qpix + 512);
     const uint32_t n = min(cd.counters[4], cd.cap);
+    const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
+    const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
+    WorkCursor cur;
+    cursor_init(cur, worker);
     uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
-        const uint32_t i = wave_fetch_add1(cd.counters + 5, lane);
+        const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
         const uint64_t key = bcast64(cd.keys[h]);
@@ -374,29 +383,34 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
                 float base[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
-                VoxHits<CM, 8> hv;
-                test_voxels<CM, 8, false>(op, v.mu, base, 0, hv);
-                if (__ballot(hv.hit != 0u) == 0) continue;
+                // test the lane's voxels TV at a time and gather the touched
+                // ones, z-slice by z-slice
+                uint32_t hit = 0u, cnt = 0u;
+#pragma unroll
+                for (int part = 0; part < 8 / TV; ++part) {
+                    VoxHits<CM, TV> hv;
+                    test_voxels<CM, TV, false>(op, v.mu, base, part * TV, hv);
+#pragma unroll
+                    for (int j = 0; j < TV; ++j) {
+                        const bool t = (hv.hit >> j) & 1u;
+                        const uint64_t bal = __ballot(t);
+                        if (t) {
+                            const uint32_t pos = cnt + lanes_below(bal);
+                            qvox[pos] = (uint16_t)(lane + 64 * (part * TV + j));
+                            qpix[pos] = (uint32_t)hv.pix[j];
+                        }
+                        cnt += (uint32_t)__popcll(bal);
+                    }
+                    hit |= hv.hit << (part * TV);
+                }
+                if (cnt == 0u) continue;
                 if (op.sign < 0 && slot < 0) {
                     e_na = true;
                     continue;
                 }
                 if (op.sign > 0) re_touch = true;
-                touched |= hv.hit;
-                n_upd += __popc(hv.hit);
-                // gather the touched voxels, z-slice by z-slice
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool t = (hv.hit >> j) & 1u;
-                    const uint64_t bal = __ballot(t);
-                    if (t) {
-                        const uint32_t pos = cnt + lanes_below(bal);
-                        qvox[pos] = (uint16_t)(lane + 64 * j);
-                        qpix[pos] = (uint32_t)hv.pix[j];
-                    }
-                    cnt += (uint32_t)__popcll(bal);
-                }
+                touched |= hit;
+                n_upd += __popc(hit);
                 wave_lds_sync();
                 // dense update of the queue, 64 entries per round
                 for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
@@ -404,16 +418,26 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
                     if (e < cnt) {
                         const int x = qvox[e];
                         const int p = (int)qpix[e];
-                        const float wq = qweight(__ldg(op.weight + p));
-                        const float z = __ldg(op.depth + p);
+                        float wraw, z;
+                        uint32_t c8 = 0u;
+                        if (CM == SC_COLOR_RGBA8 && op.packed) {
+                            const uint4 rec = __ldg(op.packed + p);
+                            z = __uint_as_float(rec.x);
+                            wraw = __uint_as_float(rec.y);
+                            c8 = rec.z;
+                        } else {
+                            wraw = __ldg(op.weight + p);
+                            z = __ldg(op.depth + p);
+                            if (CM == SC_COLOR_RGBA8) c8 = __ldg(reinterpret_cast<const uint32_t*>(op.color) + p);
+                        }
+                        const float wq = qweight(wraw);
                         const double pz64 = ((qz + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
                                             (double)(x >> 6) * op.az[2];
                         const float d = distance(z, pz64);
                         float D = sD[x], W = sW[x];
                         if (CM == SC_COLOR_RGBA8) {
                             uint32_t C = sC[x];
-                            const uint32_t c = __ldg(reinterpret_cast<const uint32_t*>(op.color) + p);
-                            e_w |= !update_rgba8(D, W, C, d, wq, c, op.sign);
+                            e_w |= !update_rgba8(D, W, C, d, wq, c8, op.sign);
                             sC[x] = C;
                         } else {
                             const float* cp = reinterpret_cast<const float*>(op.color) + 3 * p;
@@ -456,9 +480,9 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
         retire_candidate(cd, v, h, all, lane);
         wave_lds_sync();
     }
-    atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
-    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
-    atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
+    stat_add(cd, 1, worker, n_pairs, lane);
+    stat_add(cd, 2, worker, wave_sum(n_upd), lane);
+    stat_add(cd, 3, worker, n_written, lane);
 }
 
 // Persistent voxel pass, one workgroup of G = 8 / VPL wavefronts per block
@@ -476,10 +500,12 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
     const int wave = (int)bcast(threadIdx.x >> 6);
     const int kz0 = wave * VPL;
     const uint32_t n = min(cd.counters[4], cd.cap);
+    WorkCursor cur;  // used by wavefront 0
+    cursor_init(cur, blockIdx.x);
     uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
         if (wave == 0) {
-            const uint32_t it = wave_fetch_add1(cd.counters + 5, lane);
+            const uint32_t it = cursor_pop(cur, cd.counters + 5, gridDim.x, lane);
             s_item = it;
             s_flags = 0;
         }
@@ -526,10 +552,10 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
         if (wave == 0) retire_candidate(cd, v, h, all, lane);
         __syncthreads();
     }
-    atomicAdd(cd.stats + 2, (unsigned long long)n_upd);
+    stat_add(cd, 2, blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave, wave_sum(n_upd), lane);
     if (wave == 0) {
-        atomicAdd(cd.stats + 1, (unsigned long long)(lane == 0 ? n_pairs : 0u));
-        atomicAdd(cd.stats + 3, (unsigned long long)(lane == 0 ? n_written : 0u));
+        stat_add(cd, 1, blockIdx.x, n_pairs, lane);
+        stat_add(cd, 3, blockIdx.x, n_written, lane);
     }
 }
 
@@ -540,7 +566,7 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
 static bool schedule_ok(const sc_schedule& s)
 {
     if (s.vpl != 8 && s.vpl != 4 && s.vpl != 2 && s.vpl != 1) return false;
-    if (s.compact != 0 && s.compact != 1) return false;
+    if (s.compact < 0 || s.compact > 2) return false;
     if (s.compact && (s.vpl != 8 || (s.waves_per_wg != 1 && s.waves_per_wg != 2 && s.waves_per_wg != 4)))
         return false;
     return s.wgs_per_cu >= 1 && s.wgs_per_cu <= 32;
@@ -552,7 +578,7 @@ static void launch_candidates(sc_volume* vol, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    cand_batch_kernel<<<vol->n_cu * 16, 256, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
+    cand_batch_kernel<<<vol->n_cu * 8, 256, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     scatter_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
@@ -565,12 +591,19 @@ static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_
     const int grid = vol->n_cu * sch.wgs_per_cu;
     if (sch.compact) {
         const int threads = 64 * sch.waves_per_wg;
-        if (rgba)
-            batch_compact_kernel<SC_COLOR_RGBA8><<<grid, threads, sch.waves_per_wg * compact_wave_bytes<SC_COLOR_RGBA8>(),
-                                                   s>>>(vol->d_ops, vol->dev, vol->cand);
-        else
-            batch_compact_kernel<SC_COLOR_F32><<<grid, threads, sch.waves_per_wg * compact_wave_bytes<SC_COLOR_F32>(),
-                                                 s>>>(vol->d_ops, vol->dev, vol->cand);
+        const size_t l8 = sch.waves_per_wg * compact_wave_bytes<SC_COLOR_RGBA8>();
+        const size_t lf = sch.waves_per_wg * compact_wave_bytes<SC_COLOR_F32>();
+        if (sch.compact == 1) {
+            if (rgba)
+                batch_compact_kernel<SC_COLOR_RGBA8, 8><<<grid, threads, l8, s>>>(vol->d_ops, vol->dev, vol->cand);
+            else
+                batch_compact_kernel<SC_COLOR_F32, 8><<<grid, threads, lf, s>>>(vol->d_ops, vol->dev, vol->cand);
+        } else {
+            if (rgba)
+                batch_compact_kernel<SC_COLOR_RGBA8, 4><<<grid, threads, l8, s>>>(vol->d_ops, vol->dev, vol->cand);
+            else
+                batch_compact_kernel<SC_COLOR_F32, 4><<<grid, threads, lf, s>>>(vol->d_ops, vol->dev, vol->cand);
+        }
         return;
     }
     const int threads = (sch.vpl == 8) ? 256 : 64 * (8 / sch.vpl);
@@ -768,9 +801,14 @@ sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats)
 {
     if (!vol || !stats) return SC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(stats, vol->cand.stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    int64_t slots[4 * kStatSlots];
+    if (hipMemcpyAsync(slots, vol->cand.stats, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return SC_EDEVICE;
+    for (int k = 0; k < 4; ++k) {
+        stats[k] = 0;
+        for (int j = 0; j < kStatSlots; ++j) stats[k] += slots[k * kStatSlots + j];
+    }
     return SC_OK;
 }
 
@@ -838,7 +876,8 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     if (st != SC_OK) return st;
     static const sc_schedule cands[] = {{8, 4, 2, 0}, {8, 4, 4, 0}, {8, 4, 8, 0}, {4, 2, 8, 0}, {4, 2, 16, 0},
                                         {2, 4, 4, 0}, {2, 4, 8, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {8, 4, 2, 1},
-                                        {8, 4, 4, 1}, {8, 2, 4, 1},  {8, 2, 8, 1},  {8, 1, 16, 1}};
+                                        {8, 4, 4, 1}, {8, 2, 4, 1},  {8, 2, 8, 1},  {8, 1, 16, 1}, {8, 4, 4, 2},
+                                        {8, 2, 8, 2}, {8, 1, 16, 2}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         sc_volume_destroy(tmp);

@@ -46,6 +46,7 @@ struct OpDesc {
     const float* depth;   // Z*, H x W
     const float* weight;  // W*, H x W
     const void* color;    // RGBA8 (uint32 per pixel) or float x 3
+    const uint4* packed;  // optional interleaved {depth, weight, RGBA8, 0} per pixel (RGBA8 volumes)
     int32_t width, height;
     float fx, fy, cx, cy;
     double R[9];          // camera -> world rotation, row-major

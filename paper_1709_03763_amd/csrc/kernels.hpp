@@ -42,11 +42,58 @@ __device__ inline uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Adds one to *ctr once per wavefront; every lane receives the old value.
-__device__ inline uint32_t wave_fetch_add1(uint32_t* ctr, int lane)
+// Adds k to *ctr once per wavefront; every lane receives the old value.
+__device__ inline uint32_t wave_fetch_add(uint32_t* ctr, uint32_t k, int lane)
 {
-    const uint32_t r = atomicAdd(ctr, lane == 0 ? 1u : 0u);
+    const uint32_t r = atomicAdd(ctr, lane == 0 ? k : 0u);
     return bcast(r);
+}
+
+__device__ inline uint32_t wave_fetch_add1(uint32_t* ctr, int lane) { return wave_fetch_add(ctr, 1u, lane); }
+
+// Sum over the wavefront.
+__device__ inline uint32_t wave_sum(uint32_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Work distribution of the persistent passes.  A device-wide atomic on one
+// address is serviced one at a time, so a queue that pops one item per
+// atomic is bounded by that service rate.  Instead each worker (wavefront or
+// workgroup) takes item `id` first, without an atomic (the queue is ordered
+// heaviest first, so the heaviest items spread over all workers), then
+// claims kPopBatch consecutive items per atomic.  Used in uniform control
+// flow only.
+constexpr uint32_t kPopBatch = 4;
+
+struct WorkCursor {
+    uint32_t next, end;
+};
+
+__device__ inline void cursor_init(WorkCursor& c, uint32_t id)
+{
+    c.next = id;
+    c.end = id + 1u;
+}
+
+__device__ inline uint32_t cursor_pop(WorkCursor& c, uint32_t* ctr, uint32_t n_workers, int lane)
+{
+    if (c.next >= c.end) {
+        c.next = n_workers + wave_fetch_add(ctr, kPopBatch, lane);
+        c.end = c.next + kPopBatch;
+    }
+    return c.next++;
+}
+
+// Per-pass statistics are added into kStatSlots slots per counter so that the
+// workers' final atomics do not all meet on one address.
+constexpr int kStatSlots = 64;
+
+__device__ inline void stat_add(const CandDev& cd, int counter, uint32_t worker, uint64_t x, int lane)
+{
+    atomicAdd(cd.stats + counter * kStatSlots + (worker % kStatSlots), (unsigned long long)(lane == 0 ? x : 0ull));
 }
 
 // ---------------------------------------------------------------------------
@@ -152,11 +199,22 @@ __device__ inline void test_voxels(const OpDesc& op, float mu, const float base[
         pzv[j] = pz;
     }
     float wr[VPL];
+    if (CM == SC_COLOR_RGBA8 && op.packed) {
 #pragma unroll
-    for (int j = 0; j < VPL; ++j) {
-        wr[j] = __ldg(op.weight + h.pix[j]);
-        h.z[j] = __ldg(op.depth + h.pix[j]);
-        if (kColor && CM == SC_COLOR_RGBA8) h.c[j] = __ldg(reinterpret_cast<const uint32_t*>(op.color) + h.pix[j]);
+        for (int j = 0; j < VPL; ++j) {
+            const uint4 r = __ldg(op.packed + h.pix[j]);
+            h.z[j] = __uint_as_float(r.x);
+            wr[j] = __uint_as_float(r.y);
+            h.c[j] = r.z;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+            wr[j] = __ldg(op.weight + h.pix[j]);
+            h.z[j] = __ldg(op.depth + h.pix[j]);
+            if (kColor && CM == SC_COLOR_RGBA8)
+                h.c[j] = __ldg(reinterpret_cast<const uint32_t*>(op.color) + h.pix[j]);
+        }
     }
     h.hit = 0u;
 #pragma unroll
@@ -317,20 +375,21 @@ __device__ inline int vol_insert_wave(const VolDev& v, uint64_t key, int bx, int
 
 constexpr int kTile = 32;     // candidate generation works on 32 x 32 pixel tiles, 2 x 2 pixels per thread
 constexpr int kLdsSet = 2048; // LDS hash set per tile
+constexpr int kCandThreads = 256;  // threads of a candidate-generation workgroup
 
-// Conservative world-space block range of one pixel's frustum cell
-// (u +- 0.55, v +- 0.55) between depths z - mu and z + mu, padded so that
-// FP32 rounding in the decision convention cannot escape it.
-// The reciprocals ifx = 1/fx, ify = 1/fy and is = 1/s may carry a few ulps of
-// error: the 0.05 px and metric paddings exceed their effect by orders of
-// magnitude.
-__device__ inline bool pixel_block_range(const OpDesc& op, float ifx, float ify, float is, float mu, int u, int v,
-                                         float z, int lo[3], int hi[3])
+// Conservative world-space block range of the frustum cell of the pixel
+// rectangle [u0, u1] x [v0, v1] (widened by 0.55 px on every side) between
+// depths zlo - mu and zhi + mu, padded so that FP32 rounding in the decision
+// convention cannot escape it.  The reciprocals ifx = 1/fx, ify = 1/fy and
+// is = 1/s may carry a few ulps of error: the 0.05 px and metric paddings
+// exceed their effect by orders of magnitude.
+__device__ inline bool cell_block_range(const OpDesc& op, float ifx, float ify, float is, float mu, int u0, int u1,
+                                        int v0, int v1, float zlo, float zhi, int lo[3], int hi[3])
 {
-    const float zl = fmaxf(z - mu - 1e-3f, 0.0f);
-    const float zh = z + mu + 1e-3f;
-    const float xl = ((float)u - 0.55f - op.cx) * ifx, xh = ((float)u + 0.55f - op.cx) * ifx;
-    const float yl = ((float)v - 0.55f - op.cy) * ify, yh = ((float)v + 0.55f - op.cy) * ify;
+    const float zl = fmaxf(zlo - mu - 1e-3f, 0.0f);
+    const float zh = zhi + mu + 1e-3f;
+    const float xl = ((float)u0 - 0.55f - op.cx) * ifx, xh = ((float)u1 + 0.55f - op.cx) * ifx;
+    const float yl = ((float)v0 - 0.55f - op.cy) * ify, yh = ((float)v1 + 0.55f - op.cy) * ify;
     float mn[3], mx[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -376,13 +435,15 @@ __device__ inline void cand_mark(const CandDev& cd, int gb, int op_bit)
     if (!(*mw & bit)) atomicOr((unsigned long long*)mw, (unsigned long long)bit);
 }
 
-// Inserts a candidate block into the deduplicating candidate table; returns
-// its bucket, or -1 if the table is full (sticky error set).  Keys only go
-// from empty to a block within a kernel, so a plain read that finds the key
-// is reliable, and the CAS is issued only at an empty-looking bucket.
-__device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t key, int bx, int by, int bz,
-                                  uint32_t* count)
+// Finds or inserts a candidate block in the deduplicating candidate table;
+// returns its bucket, or -1 if the table is full (sticky error set).  `fresh`
+// is set when this call inserted the key (the caller then appends the bucket
+// to the candidate list).  Keys only go from empty to a block within a
+// kernel, so a plain read that finds the key is reliable, and the CAS is
+// issued only at an empty-looking bucket.
+__device__ inline int cand_claim(const CandDev& cd, const VolDev& v, uint64_t key, int bx, int by, int bz, bool& fresh)
 {
+    fresh = false;
     uint32_t h = hash_block(bx, by, bz) & cd.mask_bits;
     for (uint32_t probe = 0; probe <= cd.mask_bits; ++probe) {
         const uint64_t seen = cd.keys[h];
@@ -392,12 +453,7 @@ __device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t k
                                            (unsigned long long)key);
             if (old == key) return (int)h;
             if (old == kKeyEmpty) {
-                const uint32_t idx = atomicAdd(count, 1u);
-                if (idx < cd.cap) {
-                    cd.list[idx] = h;
-                } else {
-                    set_error(v.err, SC_EHASHFULL);
-                }
+                fresh = true;
                 return (int)h;
             }
         }
@@ -407,27 +463,68 @@ __device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t k
     return -1;
 }
 
+__device__ inline void cand_append(const CandDev& cd, const VolDev& v, uint32_t idx, int gb)
+{
+    if (idx < cd.cap)
+        cd.list[idx] = (uint32_t)gb;
+    else
+        set_error(v.err, SC_EHASHFULL);
+}
+
+// Per-lane insertion with its own list append (the rare LDS-overflow path).
+__device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t key, int bx, int by, int bz,
+                                  uint32_t* count)
+{
+    bool fresh;
+    const int gb = cand_claim(cd, v, key, bx, by, bz, fresh);
+    if (fresh) cand_append(cd, v, atomicAdd(count, 1u), gb);
+    return gb;
+}
+
+// LDS slot of a block: low coordinate bits, no multiplies (a tile's blocks
+// form a small box, so the low bits spread them).
+__device__ inline uint32_t lds_slot(int bx, int by, int bz)
+{
+    return ((uint32_t)bx & 15u) | (((uint32_t)by & 15u) << 4) | (((uint32_t)bz & 7u) << 8);
+}
+
 __device__ inline void lds_insert(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
                                   int bx, int by, int bz)
 {
     const uint64_t key = pack_key(bx, by, bz);
-    uint32_t h = hash_block(bx, by, bz) & (kLdsSet - 1);
+    uint32_t h = lds_slot(bx, by, bz);
     for (int probe = 0; probe < 32; ++probe) {
-        const uint64_t old =
-            atomicCAS((unsigned long long*)(lds + h), (unsigned long long)kKeyEmpty, (unsigned long long)key);
-        if (old == kKeyEmpty || old == key) return;
+        // most inserts repeat a key already present: a plain read settles
+        // them without a serialising atomic (entries only go from empty to a
+        // key while the set is filled)
+        const uint64_t seen = lds[h];
+        if (seen == key) return;
+        if (seen == kKeyEmpty) {
+            const uint64_t old =
+                atomicCAS((unsigned long long*)(lds + h), (unsigned long long)kKeyEmpty, (unsigned long long)key);
+            if (old == kKeyEmpty || old == key) return;
+        }
         h = (h + 1) & (kLdsSet - 1);
     }
     const int gb = cand_insert(cd, v, key, bx, by, bz, count);
     if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
 }
 
+__device__ inline void lds_insert_box(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
+                                      const int lo[3], const int hi[3])
+{
+    for (int bx = lo[0]; bx <= hi[0]; ++bx)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+            for (int bz = lo[2]; bz <= hi[2]; ++bz) lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
+}
+
 // Candidate generation for one 32 x 32 tile of one keyframe operation (256
-// threads, a 2 x 2 pixel quad each): per-pixel conservative block ranges —
-// merged into one box per quad when that does not enlarge the candidate
-// volume — deduplicated in an LDS hash set, then inserted once per tile into
-// the global candidate table.  With op_bit >= 0 the operation's bit is set
-// in the block's mask.
+// threads, a 2 x 2 pixel quad each).  A quad whose valid depths lie within
+// 2 mu of each other takes one conservative box for its whole frustum cell;
+// otherwise each valid pixel takes its own.  The boxes' blocks are
+// deduplicated in an LDS hash set, then inserted once per tile into the
+// global candidate table; with op_bit >= 0 the operation's bit is set in
+// the block's mask.
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
                                  int ty, int op_bit, uint64_t* lds)
 {
@@ -436,61 +533,64 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
     __syncthreads();
     const int u0 = tx * kTile + 2 * (tid & 15);
     const int v0 = ty * kTile + 2 * (tid >> 4);
-    int lo[4][3], hi[4][3];
-    bool have[4];
-    int sum_vol = 0;
-    int ulo[3] = {1 << 30, 1 << 30, 1 << 30}, uhi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    bool any = false;
     const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
+    float zq[4];
+    uint32_t valid = 0u;
+    float zmin = 3.0e38f, zmax = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int u = u0 + (q & 1), vv = v0 + (q >> 1);
-        have[q] = false;
+        zq[q] = 0.0f;
         if (u < op.width && vv < op.height) {
             const int pix = vv * op.width + u;
             const float w = qweight(op.weight[pix]);
             const float z = op.depth[pix];
             if (w > 0.0f && z > 0.0f && z < 1.0e30f) {
-                if (pixel_block_range(op, ifx, ify, is, v.mu, u, vv, z, lo[q], hi[q])) {
-                    have[q] = true;
-                    any = true;
-                    sum_vol += (hi[q][0] - lo[q][0] + 1) * (hi[q][1] - lo[q][1] + 1) * (hi[q][2] - lo[q][2] + 1);
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        ulo[r] = min(ulo[r], lo[q][r]);
-                        uhi[r] = max(uhi[r], hi[q][r]);
-                    }
-                } else {
-                    set_error(v.err, SC_ERANGE);
-                }
+                valid |= 1u << q;
+                zq[q] = z;
+                zmin = fminf(zmin, z);
+                zmax = fmaxf(zmax, z);
             }
         }
     }
-    if (any) {
-        const int uvol = (uhi[0] - ulo[0] + 1) * (uhi[1] - ulo[1] + 1) * (uhi[2] - ulo[2] + 1);
-        if (uvol <= sum_vol) {
-            for (int bx = ulo[0]; bx <= uhi[0]; ++bx)
-                for (int by = ulo[1]; by <= uhi[1]; ++by)
-                    for (int bz = ulo[2]; bz <= uhi[2]; ++bz) lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
-        } else {
+    if (valid) {
+        int lo[3], hi[3];
+        bool done = false;
+        if (zmax - zmin <= 2.0f * v.mu) {
+            done = cell_block_range(op, ifx, ify, is, v.mu, u0, u0 + 1, v0, v0 + 1, zmin, zmax, lo, hi);
+            if (done) lds_insert_box(lds, cd, v, count, op_bit, lo, hi);
+        }
+        if (!done) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (!have[q]) continue;
-                for (int bx = lo[q][0]; bx <= hi[q][0]; ++bx)
-                    for (int by = lo[q][1]; by <= hi[q][1]; ++by)
-                        for (int bz = lo[q][2]; bz <= hi[q][2]; ++bz)
-                            lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
+                if (!((valid >> q) & 1u)) continue;
+                const int u = u0 + (q & 1), vv = v0 + (q >> 1);
+                if (cell_block_range(op, ifx, ify, is, v.mu, u, u, vv, vv, zq[q], zq[q], lo, hi))
+                    lds_insert_box(lds, cd, v, count, op_bit, lo, hi);
+                else
+                    set_error(v.err, SC_ERANGE);
             }
         }
     }
     __syncthreads();
-    for (int i = tid; i < kLdsSet; i += blockDim.x) {
-        const uint64_t key = lds[i];
-        if (key == kKeyEmpty) continue;
-        int bx, by, bz;
-        unpack_key(key, bx, by, bz);
-        const int gb = cand_insert(cd, v, key, bx, by, bz, count);
-        if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
+    // insert the tile's blocks; new candidates are appended with one atomic
+    // per wavefront (every lane runs the same kLdsSet / 256 iterations)
+    const int lane = tid & 63;
+    for (int it = 0; it < kLdsSet / kCandThreads; ++it) {
+        const uint64_t key = lds[tid + it * kCandThreads];
+        bool fresh = false;
+        int gb = -1;
+        if (key != kKeyEmpty) {
+            int bx, by, bz;
+            unpack_key(key, bx, by, bz);
+            gb = cand_claim(cd, v, key, bx, by, bz, fresh);
+            if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
+        }
+        const uint64_t bal = __ballot(fresh);
+        if (bal) {
+            const uint32_t base = wave_fetch_add(count, (uint32_t)__popcll(bal), lane);
+            if (fresh) cand_append(cd, v, base + lanes_below(bal), gb);
+        }
     }
 }
 

@@ -187,8 +187,11 @@ __global__ __launch_bounds__(256) void update_plain_kernel(OpDesc op, VolDev v, 
 {
     const int lane = threadIdx.x & 63;
     const uint32_t n = min(cd.counters[parity], cd.cap);
+    WorkCursor cur;
+    cursor_init(cur, blockIdx.x * (blockDim.x >> 6) + bcast(threadIdx.x >> 6));
+    const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
     for (;;) {
-        const uint32_t i = wave_fetch_add1(cd.counters + 2 + parity, lane);
+        const uint32_t i = cursor_pop(cur, cd.counters + 2 + parity, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.list[i]);
         const uint64_t key = bcast64(cd.keys[h]);
@@ -226,6 +229,12 @@ __global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float
     }
 }
 
+__global__ void pack_kernel(const float* depth, const float* weight, const uint32_t* color, uint4* out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_uint4(__float_as_uint(depth[i]), __float_as_uint(weight[i]), color[i], 0u);
+}
+
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
@@ -237,6 +246,7 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     op->depth = kf->depth;
     op->weight = kf->weight;
     op->color = kf->color;
+    op->packed = (vol->p.color_mode == SC_COLOR_RGBA8) ? reinterpret_cast<const uint4*>(kf->packed) : nullptr;
     op->width = in->width;
     op->height = in->height;
     op->fx = in->fx;
@@ -260,7 +270,10 @@ static bool intr_ok(const sc_intrinsics* in)
            in->height <= 16384;
 }
 
-bool keyframe_ok(const sc_keyframe* kf) { return kf && kf->depth && kf->weight && kf->color; }
+bool keyframe_ok(const sc_keyframe* kf)
+{
+    return kf && kf->depth && kf->weight && kf->color && ((uintptr_t)kf->packed & 15u) == 0u;
+}
 
 sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
                    hipStream_t s)
@@ -343,7 +356,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * c.cap) == hipSuccess;
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
-    ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 8) == hipSuccess;
+    ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
     ok &= hipHostMalloc((void**)&vol->h_ops, sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) == hipSuccess;
     ok &= hipMalloc(&vol->d_hdr, sizeof(BatchHdr)) == hipSuccess;
@@ -410,7 +423,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u64(c.mask, 0ull, (size_t)vol->cand_buckets * c.words, s);
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
-    fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 8, s);
+    fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
     vol->parity = 0;
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
@@ -443,6 +456,19 @@ sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, flo
     HIP_TRY(hipStreamSynchronize(s));
     if (n_out) *n_out = nb;
     return SC_OK;
+}
+
+sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream)
+{
+    if (!kf || !kf->depth || !kf->weight || !kf->color || !packed || ((uintptr_t)packed & 15u) || width <= 0 ||
+        height <= 0 || width > 16384 || height > 16384)
+        return SC_EINVAL;
+    const int64_t n = (int64_t)width * height;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    pack_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(kf->depth, kf->weight,
+                                                        reinterpret_cast<const uint32_t*>(kf->color),
+                                                        reinterpret_cast<uint4*>(packed), n);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
 sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_t* slots_out, void* stream)

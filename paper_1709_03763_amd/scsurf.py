@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 import torch
@@ -47,7 +48,8 @@ class sc_volume_params(ctypes.Structure):
 
 
 class sc_keyframe(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("color", ctypes.c_void_p)]
+    _fields_ = [("depth", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("color", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p)]
 
 
 class sc_fuse_params(ctypes.Structure):
@@ -64,7 +66,7 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
-           "sc_volume_stats", "tsdf_integrate_backward"]
+           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack"]
 
 _lib = None
 
@@ -105,6 +107,7 @@ def lib():
     L.sc_batch_timing.argtypes = [P, i32]
     L.sc_batch_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
     L.sc_volume_stats.argtypes = [P, P, P]
+    L.sc_keyframe_pack.argtypes = [ctypes.POINTER(sc_keyframe), i32, i32, P, P]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:
@@ -173,10 +176,12 @@ class Keyframe:
     depth: torch.Tensor
     weight: torch.Tensor
     color: torch.Tensor
+    packed: Optional[torch.Tensor] = None  # (H,W,4) int32 interleaved copy from keyframe_pack
 
     def c(self) -> sc_keyframe:
+        packed = None if self.packed is None else dptr(self.packed, torch.int32, "packed")
         return sc_keyframe(dptr(self.depth, torch.float32, "depth"), dptr(self.weight, torch.float32, "weight"),
-                           dptr(self.color, None, "color"))
+                           dptr(self.color, None, "color"), packed)
 
 
 def keyframes(kfs):
@@ -368,6 +373,18 @@ def select_dist(dist, m, mode=SEL_EQ3):
     if n < 0:
         raise ScError(n, "sc_select_dist")
     return list(out[:n])
+
+
+def keyframe_pack(kf: Keyframe, stream=None) -> Keyframe:
+    """The keyframe with its interleaved {depth, weight, RGBA8, 0} copy
+    attached (RGBA8 keyframes; the voxel passes then gather from it)."""
+    H, W = kf.depth.shape
+    if kf.color.dtype != torch.uint8 or tuple(kf.color.shape) != (H, W, 4):
+        raise ValueError("keyframe_pack needs an RGBA8 keyframe")
+    packed = torch.empty((H, W, 4), dtype=torch.int32, device=kf.depth.device)
+    check(lib().sc_keyframe_pack(ctypes.byref(kf.c()), W, H, packed.data_ptr(), stream_handle(stream)),
+          "sc_keyframe_pack")
+    return Keyframe(kf.depth, kf.weight, kf.color, packed)
 
 
 def depth_weight(depth: torch.Tensor, intr, params=None, stream=None) -> torch.Tensor:
