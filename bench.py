@@ -209,10 +209,11 @@ def main():
     n_blocks = vol.check_error()
     log(f"integrated {n_kf} keyframes in {integrate_s * 1e3:.1f} ms; {n_blocks} blocks")
     mode = scsurf.SEL_ALL_ORDERED
+    kset = scsurf.KeyframeSet(kfs)  # marshalled once, reused by every update
     state = [A, B]  # state[0] = current integration poses, state[1] = the other set
 
     def step(fn):
-        order, _ = fn(kfs, wl.intr, state[0], state[1], n_kf, mode)
+        order, _ = fn(kset, wl.intr, state[0], state[1], n_kf, mode)
         state[0], state[1] = state[1], state[0]
         return order
 
@@ -221,7 +222,7 @@ def main():
         vol.set_schedule(*[int(x) for x in args.schedule.split(",")])
     sched = vol.get_schedule()
     if not args.no_autotune and not args.schedule:
-        sched, tune_ms = vol.autotune(kfs, wl.intr, state[0], state[1], n_kf, mode)
+        sched, tune_ms = vol.autotune(kset, wl.intr, state[0], state[1], n_kf, mode)
         log(f"autotuned schedule {sched} ({tune_ms:.2f} ms)")
     if args.sweep:
         sweep = [(8, 4, 2, 0), (8, 4, 4, 0), (8, 4, 8, 0), (4, 2, 8, 0), (4, 2, 16, 0), (2, 4, 4, 0), (2, 4, 8, 0),

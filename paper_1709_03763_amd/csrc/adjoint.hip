@@ -110,11 +110,13 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
     int64_t nb = 0;
     sc_status st = sc_volume_query(vol, s, &nb, nullptr);
     if (st != SC_OK) return st;
-    if (hipEventSynchronize(vol->staged) != hipSuccess) return SC_EDEVICE;
-    for (int k = 0; k < n_kf; ++k) make_op(vol, &kfs[k], intr, &T[k], +1, k, &vol->h_ops[k]);
-    if (hipMemcpyAsync(vol->d_ops, vol->h_ops, sizeof(OpDesc) * n_kf, hipMemcpyHostToDevice, s) != hipSuccess)
+    OpDesc* ops = stage_begin(vol);
+    if (!ops) return SC_EDEVICE;
+    for (int k = 0; k < n_kf; ++k) make_op(vol, &kfs[k], intr, &T[k], +1, k, &ops[k]);
+    if (hipMemcpyAsync(vol->d_ops, ops, sizeof(OpDesc) * n_kf, hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
-    if (hipEventRecord(vol->staged, s) != hipSuccess) return SC_EDEVICE;
+    st = stage_end(vol, s);
+    if (st != SC_OK) return st;
     // FP64 pose accumulators live in the batch histogram scratch (>= 6 doubles per keyframe)
     double* acc = reinterpret_cast<double*>(vol->cand.sorted);
     zero_f64_kernel<<<(6 * n_kf + 255) / 256, 256, 0, s>>>(acc, 6 * n_kf);

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
         const int tile = it - o * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
-        cand_tile(ops[o], v, cd, cd.counters + 4, tx, ty, o, lds);
+        cand_tile(ops[o], v, cd, nullptr, tx, ty, o, lds);
         __syncthreads();
     }
 }
@@ -57,8 +57,8 @@ __device__ inline int mask_count(const CandDev& cd, uint32_t h)
     return c;
 }
 
-// Each workgroup takes a contiguous share of the candidate list, so the
-// histogram and the scatter below see the same elements per workgroup.
+// Each workgroup takes a contiguous share of the candidate table's buckets,
+// so the histogram and the scatter below see the same buckets per workgroup.
 __device__ inline void wg_share(uint32_t n, uint32_t& b0, uint32_t& b1)
 {
     const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -66,27 +66,29 @@ __device__ inline void wg_share(uint32_t n, uint32_t& b0, uint32_t& b1)
     b1 = min(n, b0 + per);
 }
 
-// Histogram of operation counts, privatised in LDS per workgroup.
+// Histogram of operation counts over the occupied buckets, privatised in LDS
+// per workgroup.
 __global__ __launch_bounds__(256) void hist_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t h[kMaxBatchOps + 1];
     uint32_t b0, b1;
-    wg_share(min(cd.counters[4], cd.cap), b0, b1);
+    wg_share(cd.mask_bits + 1u, b0, b1);
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) atomicAdd(h + mask_count(cd, cd.list[i]), 1u);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
+        if (cd.keys[i] != kKeyEmpty) atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
     __syncthreads();
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
         if (h[c]) atomicAdd(cd.bins + c, h[c]);
 }
 
 // Exclusive scan in descending operation count: offset[c] = #blocks with more
-// than c operations.  One workgroup; n_bins <= 4097.
+// than c operations; the total is the number of candidate blocks.  One
+// workgroup; n_bins <= 4097.
 __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
-    if (tid == 0) cd.stats[0] += min(cd.counters[4], cd.cap);  // slot 0 of counter 0
     const int per = (n_bins + 1023) / 1024;
     // thread tid owns bins (descending) [n_bins-1 - tid*per, ...]
     uint32_t sum = 0;
@@ -111,26 +113,29 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
             run += b;
         }
     }
+    if (tid == 1023) {
+        cd.counters[4] = part[1023];
+        cd.stats[0] += part[1023];  // slot 0 of counter 0
+    }
 }
 
 // Scatter into operation-count order: each workgroup reserves one range per
-// count it holds, then places its elements inside those ranges.
+// count it holds, then places its buckets inside those ranges.
 __global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t h[kMaxBatchOps + 1];
     uint32_t b0, b1;
-    wg_share(min(cd.counters[4], cd.cap), b0, b1);
+    wg_share(cd.mask_bits + 1u, b0, b1);
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) atomicAdd(h + mask_count(cd, cd.list[i]), 1u);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
+        if (cd.keys[i] != kKeyEmpty) atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
     __syncthreads();
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
         if (h[c]) h[c] = atomicAdd(cd.bins + c, h[c]);
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const uint32_t hh = cd.list[i];
-        cd.sorted[atomicAdd(h + mask_count(cd, hh), 1u)] = hh;
-    }
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
+        if (cd.keys[i] != kKeyEmpty) cd.sorted[atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u)] = i;
 }
 
 // Voxel state of one lane: VPL voxels along z of the lane's (x, y) column.
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
 {
     constexpr int VPL = 8;
     const int lane = threadIdx.x & 63;
-    const uint32_t n = min(cd.counters[4], cd.cap);
+    const uint32_t n = cd.counters[4];
     const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + bcast(threadIdx.x >> 6);
     const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
     WorkCursor cur;
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     double* sCf = reinterpret_cast<double*>(sW + 512);     // FP32 colour: [3][512]
     uint32_t* qpix = reinterpret_cast<uint32_t*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
     uint16_t* qvox = reinterpret_cast<uint16_t*>(qpix + 512);
-    const uint32_t n = min(cd.counters[4], cd.cap);
+    const uint32_t n = cd.counters[4];
     const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
     const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
     WorkCursor cur;
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
     const int lane = threadIdx.x & 63;
     const int wave = (int)bcast(threadIdx.x >> 6);
     const int kz0 = wave * VPL;
-    const uint32_t n = min(cd.counters[4], cd.cap);
+    const uint32_t n = cd.counters[4];
     WorkCursor cur;  // used by wavefront 0
     cursor_init(cur, blockIdx.x);
     uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
@@ -579,9 +584,9 @@ static void launch_candidates(sc_volume* vol, hipStream_t s)
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     cand_batch_kernel<<<vol->n_cu * 8, 256, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
-    hist_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
+    hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    scatter_kernel<<<vol->n_cu, 256, 0, s>>>(vol->cand, n_bins);
+    scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
 }
 
 // The persistent voxel pass with schedule `sch`.
@@ -688,16 +693,20 @@ static bool graphs_for(sc_volume* vol, hipGraphExec_t& pre, hipGraphExec_t& main
     return pre && main;
 }
 
-// Stages and runs one chunk of operations (ops already in vol->h_ops).  With
+// Copies one chunk of staged operations to the device and runs it.  With
 // timing enabled, an event pair brackets the voxel pass on the stream.
-static sc_status run_chunk(sc_volume* vol, int n_ops, const sc_intrinsics* in, hipStream_t s)
+static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s)
 {
-    vol->h_hdr->n_ops = n_ops;
-    vol->h_hdr->tiles_x = (in->width + kTile - 1) / kTile;
-    vol->h_hdr->tiles_y = (in->height + kTile - 1) / kTile;
-    if (hipMemcpyAsync(vol->d_ops, vol->h_ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(vol->d_hdr, vol->h_hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s) != hipSuccess)
+    BatchHdr* hdr = stage_hdr(vol);
+    hdr->n_ops = n_ops;
+    hdr->tiles_x = (in->width + kTile - 1) / kTile;
+    hdr->tiles_y = (in->height + kTile - 1) / kTile;
+    if (hipMemcpyAsync(vol->d_ops, ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(vol->d_hdr, hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
+    // the staging buffer may be refilled once these copies have run
+    const sc_status st = stage_end(vol, s);
+    if (st != SC_OK) return st;
     hipGraphExec_t pre = nullptr, main = nullptr;
     if (!graphs_for(vol, pre, main)) return SC_EDEVICE;
     if (hipGraphLaunch(pre, s) != hipSuccess) return SC_EDEVICE;
@@ -708,8 +717,6 @@ static sc_status run_chunk(sc_volume* vol, int n_ops, const sc_intrinsics* in, h
         if (hipEventRecord(vol->timing_ev[2 * vol->timing_n + 1], s) != hipSuccess) return SC_EDEVICE;
         vol->timing_n++;
     }
-    // the staging buffers may be rewritten only after the copies have run
-    if (hipEventRecord(vol->staged, s) != hipSuccess) return SC_EDEVICE;
     return SC_OK;
 }
 
@@ -727,16 +734,17 @@ sc_status batch_update(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, con
     int total = 2 * ns, done = 0;
     while (done < total) {
         const int cnt = std::min(cap, total - done);
-        if (hipEventSynchronize(vol->staged) != hipSuccess) return SC_EDEVICE;
+        OpDesc* ops = stage_begin(vol);
+        if (!ops) return SC_EDEVICE;
         for (int j = 0; j < cnt; ++j) {
             const int g = done + j;
             const int k = order[g < ns ? g : g - ns];
             if (g < ns)
-                make_op(vol, &kfs[k], in, &T_int[k], -1, k, &vol->h_ops[j]);
+                make_op(vol, &kfs[k], in, &T_int[k], -1, k, &ops[j]);
             else
-                make_op(vol, &kfs[k], in, &T_new[k], +1, k, &vol->h_ops[j]);
+                make_op(vol, &kfs[k], in, &T_new[k], +1, k, &ops[j]);
         }
-        const sc_status st = run_chunk(vol, cnt, in, s);
+        const sc_status st = run_chunk(vol, ops, cnt, in, s);
         if (st != SC_OK) return st;
         done += cnt;
     }

@@ -78,13 +78,14 @@ struct VolDev {
 struct CandDev {
     uint64_t* keys;       // cand buckets
     uint64_t* mask;       // cand buckets x words: bit o set if operation o proposed the block
-    uint32_t* list;       // occupied buckets in insertion order
-    uint32_t* sorted;     // occupied buckets ordered by operation count (batched path)
-    uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity), [4] batch work cursor
+    uint32_t* list;       // occupied buckets in insertion order (plain path)
+    uint32_t* sorted;     // occupied buckets ordered by operation count (batched path), one per bucket
+    uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity),
+                          // [4] batch candidates, [5] batch work cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
     unsigned long long* stats;  // cumulative: candidate blocks, (block, op) pairs, voxel updates, blocks written
     uint32_t mask_bits;   // cand buckets - 1
-    uint32_t cap;         // list capacity
+    uint32_t cap;         // list capacity (plain path)
     int32_t words;        // 64-bit mask words per bucket
 };
 
@@ -107,13 +108,14 @@ struct sc_volume {
     sc::VolDev dev;
     sc::CandDev cand;
     sc::OpDesc* d_ops;       // device, max_batch_ops (+ one for the plain path)
-    sc::OpDesc* h_ops;       // pinned host staging
+    sc::OpDesc* h_ops;       // pinned host staging, two buffers of max_batch_ops
     sc::BatchHdr* d_hdr;     // device
-    sc::BatchHdr* h_hdr;     // pinned host staging
+    sc::BatchHdr* h_hdr;     // pinned host staging, two buffers
     uint32_t cand_buckets;
     int parity;              // plain-path candidate counter parity
     hipStream_t cap_stream;  // private stream used for graph capture
-    hipEvent_t staged;       // recorded after the batch descriptors were copied to the device
+    hipEvent_t staged[2];    // recorded after each staging buffer's descriptors were copied to the device
+    int stage;               // staging buffer the next chunk fills
     hipGraphExec_t graph_pre;   // captured candidate stage (init, candidates, histogram, scan, scatter)
     hipGraphExec_t graph_main[4]; // captured voxel pass per voxels-per-lane choice
     int graph_keys[4];       // schedule the voxel-pass graph of each slot was captured with

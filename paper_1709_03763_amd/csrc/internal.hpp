@@ -10,6 +10,9 @@ void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
              int kf_index, OpDesc* op);
 bool keyframe_ok(const sc_keyframe* kf);
+OpDesc* stage_begin(sc_volume* vol);
+BatchHdr* stage_hdr(sc_volume* vol);
+sc_status stage_end(sc_volume* vol, hipStream_t s);
 sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
                    hipStream_t s);
 

@@ -425,14 +425,12 @@ __device__ inline bool cell_block_range(const OpDesc& op, float ifx, float ify, 
     return ok;
 }
 
-// Sets operation bit `op_bit` of a candidate's mask.  Bits only go from 0 to
-// 1 within a kernel, so a read that shows the bit set is never stale-wrong;
-// a stale read only costs a redundant atomic.
+// Sets operation bit `op_bit` of a candidate's mask: a non-returning atomic,
+// so the wavefront does not wait for it.
 __device__ inline void cand_mark(const CandDev& cd, int gb, int op_bit)
 {
     uint64_t* mw = cd.mask + (size_t)gb * cd.words + (op_bit >> 6);
-    const uint64_t bit = 1ull << (op_bit & 63);
-    if (!(*mw & bit)) atomicOr((unsigned long long*)mw, (unsigned long long)bit);
+    atomicOr((unsigned long long*)mw, (unsigned long long)(1ull << (op_bit & 63)));
 }
 
 // Finds or inserts a candidate block in the deduplicating candidate table;
@@ -471,13 +469,14 @@ __device__ inline void cand_append(const CandDev& cd, const VolDev& v, uint32_t 
         set_error(v.err, SC_EHASHFULL);
 }
 
-// Per-lane insertion with its own list append (the rare LDS-overflow path).
+// Per-lane insertion with its own list append (the rare LDS-overflow path;
+// no list when count is null).
 __device__ inline int cand_insert(const CandDev& cd, const VolDev& v, uint64_t key, int bx, int by, int bz,
                                   uint32_t* count)
 {
     bool fresh;
     const int gb = cand_claim(cd, v, key, bx, by, bz, fresh);
-    if (fresh) cand_append(cd, v, atomicAdd(count, 1u), gb);
+    if (fresh && count) cand_append(cd, v, atomicAdd(count, 1u), gb);
     return gb;
 }
 
@@ -524,7 +523,9 @@ __device__ inline void lds_insert_box(uint64_t* lds, const CandDev& cd, const Vo
 // otherwise each valid pixel takes its own.  The boxes' blocks are
 // deduplicated in an LDS hash set, then inserted once per tile into the
 // global candidate table; with op_bit >= 0 the operation's bit is set in
-// the block's mask.
+// the block's mask.  With count non-null, new candidates are also appended
+// to the candidate list (the plain path); the batched path finds them by
+// scanning the table instead.
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
                                  int ty, int op_bit, uint64_t* lds)
 {
@@ -574,7 +575,8 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
     }
     __syncthreads();
     // insert the tile's blocks; new candidates are appended with one atomic
-    // per wavefront (every lane runs the same kLdsSet / 256 iterations)
+    // per wavefront (every lane runs the same kLdsSet / kCandThreads
+    // iterations)
     const int lane = tid & 63;
     for (int it = 0; it < kLdsSet / kCandThreads; ++it) {
         const uint64_t key = lds[tid + it * kCandThreads];
@@ -586,10 +588,12 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
             gb = cand_claim(cd, v, key, bx, by, bz, fresh);
             if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
         }
-        const uint64_t bal = __ballot(fresh);
-        if (bal) {
-            const uint32_t base = wave_fetch_add(count, (uint32_t)__popcll(bal), lane);
-            if (fresh) cand_append(cd, v, base + lanes_below(bal), gb);
+        if (count) {
+            const uint64_t bal = __ballot(fresh);
+            if (bal) {
+                const uint32_t base = wave_fetch_add(count, (uint32_t)__popcll(bal), lane);
+                if (fresh) cand_append(cd, v, base + lanes_below(bal), gb);
+            }
         }
     }
 }

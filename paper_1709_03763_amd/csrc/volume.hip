@@ -264,6 +264,25 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     op->kf = kf_index;
 }
 
+// Host staging of operation descriptors, double-buffered: a buffer is
+// refilled only after the copy that last read it has run, so the host can
+// prepare the next chunk while the device still works on the previous one.
+OpDesc* stage_begin(sc_volume* vol)
+{
+    if (hipEventSynchronize(vol->staged[vol->stage]) != hipSuccess) return nullptr;
+    return vol->h_ops + (size_t)vol->stage * vol->p.max_batch_ops;
+}
+
+BatchHdr* stage_hdr(sc_volume* vol) { return vol->h_hdr + vol->stage; }
+
+// Records the current buffer's copies on `s` and switches buffers.
+sc_status stage_end(sc_volume* vol, hipStream_t s)
+{
+    if (hipEventRecord(vol->staged[vol->stage], s) != hipSuccess) return SC_EDEVICE;
+    vol->stage ^= 1;
+    return SC_OK;
+}
+
 static bool intr_ok(const sc_intrinsics* in)
 {
     return in && in->width > 0 && in->height > 0 && in->fx > 0.0f && in->fy > 0.0f && in->width <= 16384 &&
@@ -353,23 +372,26 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.keys, sizeof(uint64_t) * cb) == hipSuccess;
     ok &= hipMalloc(&c.mask, sizeof(uint64_t) * cb * c.words) == hipSuccess;
     ok &= hipMalloc(&c.list, sizeof(uint32_t) * c.cap) == hipSuccess;
-    ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * c.cap) == hipSuccess;
+    ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * cb) == hipSuccess;  // every bucket may be a candidate
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
-    ok &= hipHostMalloc((void**)&vol->h_ops, sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) == hipSuccess;
+    ok &= hipHostMalloc((void**)&vol->h_ops, 2 * sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) ==
+          hipSuccess;
     ok &= hipMalloc(&vol->d_hdr, sizeof(BatchHdr)) == hipSuccess;
-    ok &= hipHostMalloc((void**)&vol->h_hdr, sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
+    ok &= hipHostMalloc((void**)&vol->h_hdr, 2 * sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
     ok &= hipStreamCreateWithFlags(&vol->cap_stream, hipStreamNonBlocking) == hipSuccess;
-    ok &= hipEventCreateWithFlags(&vol->staged, hipEventDisableTiming) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&vol->staged[0], hipEventDisableTiming) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&vol->staged[1], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         sc_volume_destroy(vol);
         return SC_ENOMEM;
     }
     hipStream_t s = 0;
     sc_status st = sc_volume_reset(vol, s);
-    if (st == SC_OK && hipEventRecord(vol->staged, s) != hipSuccess) st = SC_EDEVICE;
+    for (int b = 0; b < 2; ++b)
+        if (st == SC_OK && hipEventRecord(vol->staged[b], s) != hipSuccess) st = SC_EDEVICE;
     if (st != SC_OK || hipStreamSynchronize(s) != hipSuccess) {
         sc_volume_destroy(vol);
         return SC_EDEVICE;
@@ -405,7 +427,8 @@ void sc_volume_destroy(sc_volume* vol)
     if (vol->h_ops) hipHostFree(vol->h_ops);
     if (vol->h_hdr) hipHostFree(vol->h_hdr);
     if (vol->cap_stream) hipStreamDestroy(vol->cap_stream);
-    if (vol->staged) hipEventDestroy(vol->staged);
+    for (hipEvent_t e : vol->staged)
+        if (e) hipEventDestroy(e);
     delete vol;
 }
 

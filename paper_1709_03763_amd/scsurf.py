@@ -155,18 +155,18 @@ def pose(R, t) -> sc_pose:
 
 
 def poses(R, t):
-    R = np.asarray(R, np.float64).reshape(-1, 3, 3)
+    """(N,3,3) rotations and (N,3) translations -> ctypes sc_pose array (one
+    copy through a contiguous (N,12) buffer)."""
+    R = np.asarray(R, np.float64).reshape(-1, 9)
     t = np.asarray(t, np.float64).reshape(-1, 3)
-    arr = (sc_pose * len(R))()
-    for i in range(len(R)):
-        arr[i] = pose(R[i], t[i])
+    buf = np.ascontiguousarray(np.concatenate([R, t], axis=1))
+    arr = (sc_pose * len(buf)).from_buffer_copy(buf.tobytes())
     return arr
 
 
 def poses_to_numpy(arr):
-    R = np.array([np.array(p.R[:]).reshape(3, 3) for p in arr])
-    t = np.array([np.array(p.t[:]) for p in arr])
-    return R, t
+    buf = np.frombuffer(arr, dtype=np.float64).reshape(len(arr), 12)
+    return buf[:, :9].reshape(-1, 3, 3).copy(), buf[:, 9:].copy()
 
 
 @dataclass
@@ -184,11 +184,25 @@ class Keyframe:
                            dptr(self.color, None, "color"), packed)
 
 
+class KeyframeSet:
+    """A fixed list of keyframes marshalled once for repeated updates: holds
+    the ctypes array of their device pointers and references to the tensors
+    (so they stay alive).  Rebuild it if a keyframe's tensors are replaced."""
+
+    def __init__(self, kfs):
+        self.kfs = list(kfs)
+        self.arr = (sc_keyframe * len(self.kfs))()
+        for i, k in enumerate(self.kfs):
+            self.arr[i] = k.c()
+
+    def __len__(self):
+        return len(self.kfs)
+
+
 def keyframes(kfs):
-    arr = (sc_keyframe * len(kfs))()
-    for i, k in enumerate(kfs):
-        arr[i] = k.c()
-    return arr
+    if isinstance(kfs, KeyframeSet):
+        return kfs.arr
+    return KeyframeSet(kfs).arr
 
 
 def fuse_params(z_min=0.3, z_max=4.0, disc_rel=0.05, occ_rel=0.05) -> sc_fuse_params:

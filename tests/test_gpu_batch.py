@@ -169,11 +169,12 @@ def test_graph_replays_across_successive_updates(scene):
     state must match the oracle (replays after the first included)."""
     wl, kfs, R, t = scene
     vol, ref, dks, okf = _integrated(wl, kfs, R, t)
+    kset = scsurf.KeyframeSet(dks)
     Rc, tc = R.copy(), t.copy()
     for u in range(4):
         Rn, tn = synth.perturb_all(Rc, tc, 0.01, 0.5, 100 + u)
         _say(f"update {u}")
-        order, (Rc2, tc2) = vol.reintegrate_batch(dks, wl.intr, (Rc, tc), (Rn, tn), 3, scsurf.SEL_EQ3)
+        order, (Rc2, tc2) = vol.reintegrate_batch(kset, wl.intr, (Rc, tc), (Rn, tn), 3, scsurf.SEL_EQ3)
         exp = osel.select(osel.distances(Rc, tc, Rn, tn), 3, scsurf.SEL_EQ3)
         assert order == exp
         _oracle_update(ref, okf, wl, Rc, tc, Rn, tn, exp)
