@@ -144,15 +144,25 @@ def adjoint_stage(torch, scsurf, synth):
     return float(np.median(times[1:]) * 1e3)
 
 
-def traffic_from_profile(digest, launches_bytes):
+def kernel_variant(sched):
+    """Name of the voxel-pass kernel a schedule (vpl, waves_per_wg, wgs_per_cu,
+    compact) launches."""
+    vpl, _, _, compact = sched
+    if compact:
+        return f"batch_compact_kernel<RGBA8,{8 if compact == 1 else 4}>"
+    return "batch_main_wave_kernel<RGBA8>" if vpl == 8 else f"batch_main_group_kernel<RGBA8,{vpl}>"
+
+
+def traffic_from_profile(digest, variant):
     """HBM bytes per launch of the voxel pass from the committed rocprofv3
-    counter summary, if it was taken from the current kernel sources."""
+    counter summary, if it was taken from the current kernel sources and the
+    same kernel variant."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_digest") != digest:
+    if rec.get("source_digest") != digest or rec.get("kernel") != variant:
         return None
     return rec.get("bytes_per_launch")
 
@@ -160,8 +170,8 @@ def traffic_from_profile(digest, launches_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--keyframes", type=int, default=200)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
@@ -174,7 +184,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-pack", action="store_true",
                     help="keyframes without the interleaved copy (three gathers per voxel test)")
-    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=200,
+                    help="keyframes the oracle re-integrates for the CPU baseline (all 200 by default)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -250,8 +261,11 @@ def main():
     s0 = vol.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    host_s = 0.0
     for _ in range(args.steps):
+        th = time.perf_counter()
         order = step(vol.reintegrate_batch)
+        host_s += time.perf_counter() - th
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -264,6 +278,8 @@ def main():
     n_sel = len(order)
     n_ops = 2 * n_sel
     cand, pairs, upd, written = [(b - a) / args.steps for a, b in zip(s0, s1)]
+    log(f"voxel pass per launch: min {min(main_ms):.3f} median {float(np.median(main_ms)):.3f} "
+        f"max {max(main_ms):.3f} ms; host time in the update calls {host_s * 1e3 / args.steps:.3f} ms/step")
     log(f"batched: {ms_per_step:.3f} ms/step, voxel pass {np.mean(main_ms):.3f} ms, "
         f"{cand:.0f} candidate blocks, {written:.0f} written, {upd / 1e6:.1f} M voxel updates, "
         f"{n_blocks_after} blocks allocated")
@@ -272,7 +288,8 @@ def main():
     alg_bytes = written * 512 * 2 * VOXEL_BYTES + n_ops * H * Wd * KF_PIXEL_BYTES
     achieved = alg_bytes / (pass_ms / 1e3) / 1e9
     digest = source_digest()
-    traffic = traffic_from_profile(digest, alg_bytes)
+    variant = kernel_variant(sched)
+    traffic = traffic_from_profile(digest, variant)
 
     plain = None
     if not args.no_plain and args.plain_steps > 0:
@@ -294,7 +311,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        sample = list(np.random.default_rng(0).choice(n_kf, args.cpu_sample, replace=False))
+        sample = sorted(np.random.default_rng(0).choice(n_kf, min(args.cpu_sample, n_kf), replace=False).tolist())
         kfs_np = [{"depth": kfs[k].depth.cpu().numpy(), "weight": kfs[k].weight.cpu().numpy(),
                    "color": kfs[k].color.cpu().numpy()} for k in range(n_kf)]
         rate, dt = cpu_baseline(oracle, kfs_np, wl.intr, A, B, sample)
@@ -339,7 +356,7 @@ def main():
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "batch_main_wave_kernel" if sched[0] == 8 else "batch_main_group_kernel",
+                     "kernel": variant,
                      "kernel_ms": round(pass_ms, 4), "algorithmic_bytes": int(alg_bytes),
                      "blocks_written": int(written), "candidate_blocks": int(cand), "block_op_pairs": int(pairs),
                      "source_digest": digest},

@@ -37,7 +37,7 @@ __global__ void batch_init_kernel(CandDev cd, int n_bins)
 __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr,
                                                          VolDev v, CandDev cd)
 {
-    __shared__ uint64_t lds[kLdsSet];
+    __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
     const int tiles = hdr->tiles_x * hdr->tiles_y;
     const int items = hdr->n_ops * tiles;
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
         const int tile = it - o * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
-        cand_tile(ops[o], v, cd, nullptr, tx, ty, o, lds);
+        cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds);
         __syncthreads();
     }
 }
@@ -120,8 +120,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
 }
 
 // Scatter into operation-count order: each workgroup reserves one range per
-// count it holds, then places its buckets inside those ranges.
-__global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, int n_bins)
+// count it holds, then places its buckets inside those ranges, with each
+// block's key and current pool slot (looked up here, in parallel, so the
+// voxel pass starts a block with one round of independent loads).
+__global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, VolDev v, int n_bins)
 {
     __shared__ uint32_t h[kMaxBatchOps + 1];
     uint32_t b0, b1;
@@ -134,8 +136,16 @@ __global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, int n_bins)
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
         if (h[c]) h[c] = atomicAdd(cd.bins + c, h[c]);
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
-        if (cd.keys[i] != kKeyEmpty) cd.sorted[atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u)] = i;
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const uint64_t key = cd.keys[i];
+        if (key == kKeyEmpty) continue;
+        const uint32_t pos = atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
+        int bx, by, bz;
+        unpack_key(key, bx, by, bz);
+        cd.sorted[pos] = i;
+        cd.skey[pos] = key;
+        cd.sslot[pos] = vol_find(v, key, bx, by, bz);
+    }
 }
 
 // Voxel state of one lane: VPL voxels along z of the lane's (x, y) column.
@@ -268,10 +278,10 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
         const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
-        const uint64_t key = bcast64(cd.keys[h]);
+        const uint64_t key = bcast64(cd.skey[i]);
+        int slot = (int)bcast((uint32_t)cd.sslot[i]);
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
-        int slot = (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
         LaneVox<CM, VPL> st;
         if (slot >= 0)
             load_vox<CM, VPL>(st, v.pool + (size_t)slot * v.stride, lane, 0);
@@ -302,12 +312,13 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
 }
 
 // LDS bytes per wavefront of the compacting voxel pass: block state
-// (D, W f32; colour RGBA8 u32 or 3 x f64) and the queue of one operation's
-// touched voxels (pixel u32, voxel u16).
-template <int CM>
+// (D, W f32; colour RGBA8 u32 or 3 x f64) and the queue of one part's
+// touched voxels (voxel u16; quantised weight, keyframe depth, and RGBA8
+// colour or pixel index, 4 bytes each).
+template <int CM, int TV>
 constexpr int compact_wave_bytes()
 {
-    return 512 * (4 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24) + 4 + 2);
+    return 512 * (4 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 64 * TV * (2 + 4 + 4 + 4);
 }
 
 // Orders this wavefront's LDS accesses: the lanes that write a queue entry or
@@ -320,25 +331,29 @@ __device__ inline void wave_lds_sync()
 }
 
 // Persistent voxel pass, compacting: one wavefront per block with the block
-// state in LDS.  For each operation the lanes test their own eight voxels,
-// the touched ones are gathered into an LDS queue (ballot + mbcnt), and all
-// 64 lanes then update consecutive queue entries, so the update work follows
-// the number of touched voxels rather than the number of z-slices that hold
-// one.  Per voxel the operations still apply in bit order.  TV voxels per
-// lane are tested at a time (8, or 4 to keep fewer values live).
+// state in LDS.  For each operation the lanes test their own voxels TV at a
+// time (a part); the touched ones of a part are gathered into an LDS queue
+// (ballot + mbcnt) together with the keyframe samples already loaded for the
+// test, and all 64 lanes then update consecutive queue entries.  The update
+// work follows the number of touched voxels rather than the number of
+// z-slices that hold one, and no keyframe sample is loaded twice.  Per voxel
+// the operations still apply in bit order.
 template <int CM, int TV>
 __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
 {
+    constexpr int Q = 64 * TV;  // queue entries
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = (int)bcast(threadIdx.x >> 6);
-    unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM>();
+    unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM, TV>();
     float* sD = reinterpret_cast<float*>(wb);
     float* sW = sD + 512;
     uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);  // RGBA8
     double* sCf = reinterpret_cast<double*>(sW + 512);     // FP32 colour: [3][512]
-    uint32_t* qpix = reinterpret_cast<uint32_t*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
-    uint16_t* qvox = reinterpret_cast<uint16_t*>(qpix + 512);
+    float* qw = reinterpret_cast<float*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    float* qz = qw + Q;
+    uint32_t* qc = reinterpret_cast<uint32_t*>(qz + Q);  // RGBA8 colour, or pixel index (FP32 colour)
+    uint16_t* qvox = reinterpret_cast<uint16_t*>(qc + Q);
     const uint32_t n = cd.counters[4];
     const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
     const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
@@ -349,10 +364,10 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
         const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
-        const uint64_t key = bcast64(cd.keys[h]);
+        const uint64_t key = bcast64(cd.skey[i]);
+        int slot = (int)bcast((uint32_t)cd.sslot[i]);
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
-        int slot = (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
         {
             const float* blk = v.pool + (size_t)max(slot, 0) * v.stride;
             const bool have = slot >= 0;
@@ -382,19 +397,18 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
                 m &= m - 1;
                 const OpDesc& op = ops[w * 64 + b];
                 float q[3];
-                double qz;
-                block_origin(op, v.s, bx, by, bz, q, qz);
+                double qz0;
+                block_origin(op, v.s, bx, by, bz, q, qz0);
                 const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
                 float base[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * op.a[0][r]) + ky * op.a[1][r];
-                // test the lane's voxels TV at a time and gather the touched
-                // ones, z-slice by z-slice
-                uint32_t hit = 0u, cnt = 0u;
 #pragma unroll
                 for (int part = 0; part < 8 / TV; ++part) {
                     VoxHits<CM, TV> hv;
-                    test_voxels<CM, TV, false>(op, v.mu, base, part * TV, hv);
+                    test_voxels<CM, TV, true>(op, v.mu, base, part * TV, hv);
+                    // gather this part's touched voxels, z-slice by z-slice
+                    uint32_t cnt = 0u;
 #pragma unroll
                     for (int j = 0; j < TV; ++j) {
                         const bool t = (hv.hit >> j) & 1u;
@@ -402,62 +416,51 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
                         if (t) {
                             const uint32_t pos = cnt + lanes_below(bal);
                             qvox[pos] = (uint16_t)(lane + 64 * (part * TV + j));
-                            qpix[pos] = (uint32_t)hv.pix[j];
+                            qw[pos] = hv.w[j];
+                            qz[pos] = hv.z[j];
+                            qc[pos] = (CM == SC_COLOR_RGBA8) ? hv.c[j] : (uint32_t)hv.pix[j];
                         }
                         cnt += (uint32_t)__popcll(bal);
                     }
-                    hit |= hv.hit << (part * TV);
-                }
-                if (cnt == 0u) continue;
-                if (op.sign < 0 && slot < 0) {
-                    e_na = true;
-                    continue;
-                }
-                if (op.sign > 0) re_touch = true;
-                touched |= hit;
-                n_upd += __popc(hit);
-                wave_lds_sync();
-                // dense update of the queue, 64 entries per round
-                for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
-                    const uint32_t e = r0 + (uint32_t)lane;
-                    if (e < cnt) {
-                        const int x = qvox[e];
-                        const int p = (int)qpix[e];
-                        float wraw, z;
-                        uint32_t c8 = 0u;
-                        if (CM == SC_COLOR_RGBA8 && op.packed) {
-                            const uint4 rec = __ldg(op.packed + p);
-                            z = __uint_as_float(rec.x);
-                            wraw = __uint_as_float(rec.y);
-                            c8 = rec.z;
-                        } else {
-                            wraw = __ldg(op.weight + p);
-                            z = __ldg(op.depth + p);
-                            if (CM == SC_COLOR_RGBA8) c8 = __ldg(reinterpret_cast<const uint32_t*>(op.color) + p);
-                        }
-                        const float wq = qweight(wraw);
-                        const double pz64 = ((qz + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
-                                            (double)(x >> 6) * op.az[2];
-                        const float d = distance(z, pz64);
-                        float D = sD[x], W = sW[x];
-                        if (CM == SC_COLOR_RGBA8) {
-                            uint32_t C = sC[x];
-                            e_w |= !update_rgba8(D, W, C, d, wq, c8, op.sign);
-                            sC[x] = C;
-                        } else {
-                            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * p;
-                            const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
-                            double C3[3] = {sCf[x], sCf[512 + x], sCf[1024 + x]};
-                            e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
-                            sCf[x] = C3[0];
-                            sCf[512 + x] = C3[1];
-                            sCf[1024 + x] = C3[2];
-                        }
-                        sD[x] = D;
-                        sW[x] = W;
+                    if (cnt == 0u) continue;
+                    if (op.sign < 0 && slot < 0) {
+                        e_na = true;
+                        break;
                     }
+                    if (op.sign > 0) re_touch = true;
+                    touched |= hv.hit << (part * TV);
+                    n_upd += __popc(hv.hit);
+                    wave_lds_sync();
+                    // dense update of the queue, 64 entries per round
+                    for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+                        const uint32_t e = r0 + (uint32_t)lane;
+                        if (e < cnt) {
+                            const int x = qvox[e];
+                            const double pz64 =
+                                ((qz0 + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
+                                (double)(x >> 6) * op.az[2];
+                            const float d = distance(qz[e], pz64);
+                            const float wq = qw[e];
+                            float D = sD[x], W = sW[x];
+                            if (CM == SC_COLOR_RGBA8) {
+                                uint32_t C = sC[x];
+                                e_w |= !update_rgba8(D, W, C, d, wq, qc[e], op.sign);
+                                sC[x] = C;
+                            } else {
+                                const float* cp = reinterpret_cast<const float*>(op.color) + 3 * (size_t)qc[e];
+                                const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
+                                double C3[3] = {sCf[x], sCf[512 + x], sCf[1024 + x]};
+                                e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
+                                sCf[x] = C3[0];
+                                sCf[512 + x] = C3[1];
+                                sCf[1024 + x] = C3[2];
+                            }
+                            sD[x] = D;
+                            sW[x] = W;
+                        }
+                    }
+                    wave_lds_sync();
                 }
-                wave_lds_sync();
             }
         }
         const int all = (__ballot(re_touch) ? 1 : 0) | (__ballot(e_na) ? 2 : 0) | (__ballot(e_w) ? 4 : 0);
@@ -518,10 +521,10 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
         const uint32_t i = bcast(s_item);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
-        const uint64_t key = bcast64(cd.keys[h]);
+        const uint64_t key = bcast64(cd.skey[i]);
+        int slot = (int)bcast((uint32_t)cd.sslot[i]);
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
-        int slot = (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
         LaneVox<CM, VPL> st;
         if (slot >= 0)
             load_vox<CM, VPL>(st, v.pool + (size_t)slot * v.stride, lane, kz0);
@@ -583,10 +586,11 @@ static void launch_candidates(sc_volume* vol, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    cand_batch_kernel<<<vol->n_cu * 8, 256, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
+    cand_batch_kernel<<<vol->n_cu * 8, CandCfg<kTileBatch, kCellBatch>::threads, 0, s>>>(vol->d_ops, vol->d_hdr,
+                                                                                       vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
+    scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, vol->dev, n_bins);
 }
 
 // The persistent voxel pass with schedule `sch`.
@@ -596,18 +600,21 @@ static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_
     const int grid = vol->n_cu * sch.wgs_per_cu;
     if (sch.compact) {
         const int threads = 64 * sch.waves_per_wg;
-        const size_t l8 = sch.waves_per_wg * compact_wave_bytes<SC_COLOR_RGBA8>();
-        const size_t lf = sch.waves_per_wg * compact_wave_bytes<SC_COLOR_F32>();
+        const size_t w = sch.waves_per_wg;
         if (sch.compact == 1) {
             if (rgba)
-                batch_compact_kernel<SC_COLOR_RGBA8, 8><<<grid, threads, l8, s>>>(vol->d_ops, vol->dev, vol->cand);
+                batch_compact_kernel<SC_COLOR_RGBA8, 8><<<grid, threads, w * compact_wave_bytes<SC_COLOR_RGBA8, 8>(),
+                                                          s>>>(vol->d_ops, vol->dev, vol->cand);
             else
-                batch_compact_kernel<SC_COLOR_F32, 8><<<grid, threads, lf, s>>>(vol->d_ops, vol->dev, vol->cand);
+                batch_compact_kernel<SC_COLOR_F32, 8><<<grid, threads, w * compact_wave_bytes<SC_COLOR_F32, 8>(),
+                                                        s>>>(vol->d_ops, vol->dev, vol->cand);
         } else {
             if (rgba)
-                batch_compact_kernel<SC_COLOR_RGBA8, 4><<<grid, threads, l8, s>>>(vol->d_ops, vol->dev, vol->cand);
+                batch_compact_kernel<SC_COLOR_RGBA8, 4><<<grid, threads, w * compact_wave_bytes<SC_COLOR_RGBA8, 4>(),
+                                                          s>>>(vol->d_ops, vol->dev, vol->cand);
             else
-                batch_compact_kernel<SC_COLOR_F32, 4><<<grid, threads, lf, s>>>(vol->d_ops, vol->dev, vol->cand);
+                batch_compact_kernel<SC_COLOR_F32, 4><<<grid, threads, w * compact_wave_bytes<SC_COLOR_F32, 4>(),
+                                                        s>>>(vol->d_ops, vol->dev, vol->cand);
         }
         return;
     }
@@ -699,8 +706,8 @@ static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const s
 {
     BatchHdr* hdr = stage_hdr(vol);
     hdr->n_ops = n_ops;
-    hdr->tiles_x = (in->width + kTile - 1) / kTile;
-    hdr->tiles_y = (in->height + kTile - 1) / kTile;
+    hdr->tiles_x = (in->width + kTileBatch - 1) / kTileBatch;
+    hdr->tiles_y = (in->height + kTileBatch - 1) / kTileBatch;
     if (hipMemcpyAsync(vol->d_ops, ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(vol->d_hdr, hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
@@ -763,8 +770,9 @@ static bool schedule_fits(const sc_volume* vol, const sc_schedule& s)
 {
     if (!schedule_ok(s)) return false;
     if (!s.compact) return true;
-    const int per = (vol->p.color_mode == SC_COLOR_RGBA8) ? compact_wave_bytes<SC_COLOR_RGBA8>()
-                                                          : compact_wave_bytes<SC_COLOR_F32>();
+    const bool rgba = vol->p.color_mode == SC_COLOR_RGBA8;
+    const int per = (s.compact == 1) ? (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 8>() : compact_wave_bytes<SC_COLOR_F32, 8>())
+                                     : (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 4>() : compact_wave_bytes<SC_COLOR_F32, 4>());
     return s.waves_per_wg * per <= 65536;
 }
 

@@ -80,6 +80,8 @@ struct CandDev {
     uint64_t* mask;       // cand buckets x words: bit o set if operation o proposed the block
     uint32_t* list;       // occupied buckets in insertion order (plain path)
     uint32_t* sorted;     // occupied buckets ordered by operation count (batched path), one per bucket
+    uint64_t* skey;       // block key of each sorted entry
+    int32_t* sslot;       // pool slot of each sorted entry's block before the pass (-1: not allocated)
     uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity),
                           // [4] batch candidates, [5] batch work cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)

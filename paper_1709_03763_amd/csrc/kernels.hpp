@@ -81,8 +81,11 @@ __device__ inline void cursor_init(WorkCursor& c, uint32_t id)
 __device__ inline uint32_t cursor_pop(WorkCursor& c, uint32_t* ctr, uint32_t n_workers, int lane)
 {
     if (c.next >= c.end) {
-        c.next = n_workers + wave_fetch_add(ctr, kPopBatch, lane);
-        c.end = c.next + kPopBatch;
+        // single items through the heavy front of the queue, so that no
+        // worker holds several heavy items at once; batches after it
+        const uint32_t k = (c.next < 2u * n_workers) ? 1u : kPopBatch;
+        c.next = n_workers + wave_fetch_add(ctr, k, lane);
+        c.end = c.next + k;
     }
     return c.next++;
 }
@@ -373,23 +376,53 @@ __device__ inline int vol_insert_wave(const VolDev& v, uint64_t key, int bx, int
 // candidate blocks
 // ---------------------------------------------------------------------------
 
-constexpr int kTile = 32;     // candidate generation works on 32 x 32 pixel tiles, 2 x 2 pixels per thread
-constexpr int kLdsSet = 2048; // LDS hash set per tile
-constexpr int kCandThreads = 256;  // threads of a candidate-generation workgroup
+// Candidate generation works on square pixel tiles with one CELL x CELL pixel
+// cell per thread: 64 x 64 tiles of 4 x 4 cells for the batched path, where
+// many operations fill the GPU, and 32 x 32 tiles of 2 x 2 quads for the one
+// operation of a plain-path call (256 threads either way).
+constexpr int kTileBatch = 64, kCellBatch = 4;
+constexpr int kTilePlain = 32, kCellPlain = 2;
+// A merged cell widens the depth band of each of its pixels by the cell's
+// depth spread; these bounds (in units of mu) keep the extra candidates few.
+constexpr float kCellSpread = 1.0f, kQuadSpread = 2.0f;
 
-// Conservative world-space block range of the frustum cell of the pixel
-// rectangle [u0, u1] x [v0, v1] (widened by 0.55 px on every side) between
-// depths zlo - mu and zhi + mu, padded so that FP32 rounding in the decision
-// convention cannot escape it.  The reciprocals ifx = 1/fx, ify = 1/fy and
-// is = 1/s may carry a few ulps of error: the 0.05 px and metric paddings
-// exceed their effect by orders of magnitude.
-__device__ inline bool cell_block_range(const OpDesc& op, float ifx, float ify, float is, float mu, int u0, int u1,
-                                        int v0, int v1, float zlo, float zhi, int lo[3], int hi[3])
+template <int TILE, int CELL>
+struct CandCfg {
+    static constexpr int threads = (TILE / CELL) * (TILE / CELL);
+    static constexpr int lds_set = 2048;  // LDS hash set entries per tile
+};
+
+// Frustum cell of a pixel rectangle [u0, u1] x [v0, v1], widened by 0.55 px
+// on every side: normalised image coordinates x in [xm - hx, xm + hx] and
+// y in [ym - hy, ym + hy], camera depth in [zl, zh] (the band
+// [zlo - mu, zhi + mu], padded so that FP32 rounding in the decision
+// convention cannot escape it).  The reciprocals ifx = 1/fx and ify = 1/fy
+// may carry a few ulps of error: the 0.05 px padding exceeds their effect by
+// orders of magnitude.
+struct CellGeom {
+    float xm, ym, hx, hy, zl, zh;
+};
+
+__device__ inline CellGeom cell_geom(const OpDesc& op, float ifx, float ify, float mu, int u0, int u1, int v0, int v1,
+                                     float zlo, float zhi)
 {
-    const float zl = fmaxf(zlo - mu - 1e-3f, 0.0f);
-    const float zh = zhi + mu + 1e-3f;
+    CellGeom c;
     const float xl = ((float)u0 - 0.55f - op.cx) * ifx, xh = ((float)u1 + 0.55f - op.cx) * ifx;
     const float yl = ((float)v0 - 0.55f - op.cy) * ify, yh = ((float)v1 + 0.55f - op.cy) * ify;
+    c.xm = 0.5f * (xl + xh);
+    c.hx = 0.5f * (xh - xl);
+    c.ym = 0.5f * (yl + yh);
+    c.hy = 0.5f * (yh - yl);
+    c.zl = fmaxf(zlo - mu - 1e-3f, 0.0f);
+    c.zh = zhi + mu + 1e-3f;
+    return c;
+}
+
+// Conservative world-space block range of a cell's frustum (the box of its
+// eight corners, padded); false if the cell spans 16 blocks or more along an
+// axis (a depth far beyond the voxel scale) or leaves the key range.
+__device__ inline bool cell_block_range(const OpDesc& op, float is, const CellGeom& c, int lo[3], int hi[3])
+{
     float mn[3], mx[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -398,16 +431,16 @@ __device__ inline bool cell_block_range(const OpDesc& op, float ifx, float ify, 
     }
 #pragma unroll
     for (int iz = 0; iz < 2; ++iz) {
-        const float zz = iz ? zh : zl;
-        const float cxm = 0.5f * (xl + xh) * zz, hx = 0.5f * (xh - xl) * zz;
-        const float cym = 0.5f * (yl + yh) * zz, hy = 0.5f * (yh - yl) * zz;
+        const float zz = iz ? c.zh : c.zl;
+        const float cxm = c.xm * zz, hx = c.hx * zz;
+        const float cym = c.ym * zz, hy = c.hy * zz;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const float r0 = (float)op.R[3 * r + 0], r1 = (float)op.R[3 * r + 1], r2 = (float)op.R[3 * r + 2];
-            const float c = r0 * cxm + r1 * cym + r2 * zz + (float)op.t[r];
+            const float cc = r0 * cxm + r1 * cym + r2 * zz + (float)op.t[r];
             const float e = fabsf(r0) * hx + fabsf(r1) * hy;
-            mn[r] = fminf(mn[r], c - e);
-            mx[r] = fmaxf(mx[r], c + e);
+            mn[r] = fminf(mn[r], cc - e);
+            mx[r] = fmaxf(mx[r], cc + e);
         }
     }
     bool ok = true;
@@ -416,8 +449,6 @@ __device__ inline bool cell_block_range(const OpDesc& op, float ifx, float ify, 
         const float pad = 2e-3f + 2e-5f * fmaxf(fabsf(mn[r]), fabsf(mx[r]));
         const float flo = ceilf((mn[r] - pad) * is);
         const float fhi = floorf((mx[r] + pad) * is);
-        // keys hold 21-bit block coordinates; a cell wider than 16 blocks means
-        // a depth far beyond the voxel scale and is rejected
         ok = ok && (flo > -8.0e6f) && (fhi < 8.0e6f) && (fhi - flo < 128.0f);
         lo[r] = ok ? ((int)flo >> 3) : 0;  // arithmetic shift: floor division by 8
         hi[r] = ok ? ((int)fhi >> 3) : -1;
@@ -487,11 +518,12 @@ __device__ inline uint32_t lds_slot(int bx, int by, int bz)
     return ((uint32_t)bx & 15u) | (((uint32_t)by & 15u) << 4) | (((uint32_t)bz & 7u) << 8);
 }
 
+template <int SET>
 __device__ inline void lds_insert(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
                                   int bx, int by, int bz)
 {
     const uint64_t key = pack_key(bx, by, bz);
-    uint32_t h = lds_slot(bx, by, bz);
+    uint32_t h = lds_slot(bx, by, bz) & (SET - 1);
     for (int probe = 0; probe < 32; ++probe) {
         // most inserts repeat a key already present: a plain read settles
         // them without a serialising atomic (entries only go from empty to a
@@ -503,83 +535,124 @@ __device__ inline void lds_insert(uint64_t* lds, const CandDev& cd, const VolDev
                 atomicCAS((unsigned long long*)(lds + h), (unsigned long long)kKeyEmpty, (unsigned long long)key);
             if (old == kKeyEmpty || old == key) return;
         }
-        h = (h + 1) & (kLdsSet - 1);
+        h = (h + 1) & (SET - 1);
     }
     const int gb = cand_insert(cd, v, key, bx, by, bz, count);
     if (gb >= 0 && op_bit >= 0) cand_mark(cd, gb, op_bit);
 }
 
-__device__ inline void lds_insert_box(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
-                                      const int lo[3], const int hi[3])
+// Inserts the blocks that can meet the frustum cell of pixels [u0, u1] x
+// [v0, v1] with valid depths in [zlo, zhi]; false if the cell's range is out
+// of bounds (nothing inserted).
+template <int SET>
+__device__ inline bool insert_cell(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
+                                   const OpDesc& op, float ifx, float ify, float is, int u0,
+                                   int u1, int v0, int v1, float zlo, float zhi)
 {
+    const CellGeom c = cell_geom(op, ifx, ify, v.mu, u0, u1, v0, v1, zlo, zhi);
+    int lo[3], hi[3];
+    if (!cell_block_range(op, is, c, lo, hi)) return false;
     for (int bx = lo[0]; bx <= hi[0]; ++bx)
         for (int by = lo[1]; by <= hi[1]; ++by)
-            for (int bz = lo[2]; bz <= hi[2]; ++bz) lds_insert(lds, cd, v, count, op_bit, bx, by, bz);
+            for (int bz = lo[2]; bz <= hi[2]; ++bz) lds_insert<SET>(lds, cd, v, count, op_bit, bx, by, bz);
+    return true;
 }
 
-// Candidate generation for one 32 x 32 tile of one keyframe operation (256
-// threads, a 2 x 2 pixel quad each).  A quad whose valid depths lie within
-// 2 mu of each other takes one conservative box for its whole frustum cell;
-// otherwise each valid pixel takes its own.  The boxes' blocks are
-// deduplicated in an LDS hash set, then inserted once per tile into the
-// global candidate table; with op_bit >= 0 the operation's bit is set in
-// the block's mask.  With count non-null, new candidates are also appended
-// to the candidate list (the plain path); the batched path finds them by
-// scanning the table instead.
+// Per-pixel fallback of a cell spanning a depth discontinuity.
+template <int SET>
+__device__ inline void insert_pixels(uint64_t* lds, const CandDev& cd, const VolDev& v, uint32_t* count, int op_bit,
+                                     const OpDesc& op, float ifx, float ify, float is, int u,
+                                     int vv, float z)
+{
+    if (!insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, u, u, vv, vv, z, z))
+        set_error(v.err, SC_ERANGE);
+}
+
+// Candidate generation for one TILE x TILE tile of one keyframe operation,
+// one CELL x CELL pixel cell per thread (CELL 2 or 4).  A cell whose valid
+// depths lie within kCellSpread mu of each other is treated as one frustum
+// cell; otherwise (CELL 4) each of its 2 x 2 quads is (within kQuadSpread mu),
+// and what still spans a depth difference falls back to single pixels.  The
+// blocks of the frustum cells' boxes are deduplicated in an LDS hash set, then
+// inserted once per
+// tile into the global candidate table; with op_bit >= 0 the operation's bit
+// is set in the block's mask.  With count non-null, new candidates are also
+// appended to the candidate list (the plain path); the batched path finds
+// them by scanning the table instead.
+template <int TILE, int CELL>
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
                                  int ty, int op_bit, uint64_t* lds)
 {
+    constexpr int kCells = TILE / CELL;
+    constexpr int kThreads = CandCfg<TILE, CELL>::threads;
+    constexpr int kSet = CandCfg<TILE, CELL>::lds_set;
+    constexpr int kPix = CELL * CELL;
     const int tid = threadIdx.x;
-    for (int i = tid; i < kLdsSet; i += blockDim.x) lds[i] = kKeyEmpty;
+    for (int i = tid; i < kSet; i += kThreads) lds[i] = kKeyEmpty;
     __syncthreads();
-    const int u0 = tx * kTile + 2 * (tid & 15);
-    const int v0 = ty * kTile + 2 * (tid >> 4);
+    const int u0 = tx * TILE + CELL * (tid % kCells);
+    const int v0 = ty * TILE + CELL * (tid / kCells);
     const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
-    float zq[4];
+    float zc[kPix];
     uint32_t valid = 0u;
     float zmin = 3.0e38f, zmax = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int u = u0 + (q & 1), vv = v0 + (q >> 1);
-        zq[q] = 0.0f;
+    for (int q = 0; q < kPix; ++q) {
+        const int u = u0 + (q % CELL), vv = v0 + (q / CELL);
+        zc[q] = 0.0f;
         if (u < op.width && vv < op.height) {
             const int pix = vv * op.width + u;
             const float w = qweight(op.weight[pix]);
             const float z = op.depth[pix];
             if (w > 0.0f && z > 0.0f && z < 1.0e30f) {
                 valid |= 1u << q;
-                zq[q] = z;
+                zc[q] = z;
                 zmin = fminf(zmin, z);
                 zmax = fmaxf(zmax, z);
             }
         }
     }
     if (valid) {
-        int lo[3], hi[3];
         bool done = false;
-        if (zmax - zmin <= 2.0f * v.mu) {
-            done = cell_block_range(op, ifx, ify, is, v.mu, u0, u0 + 1, v0, v0 + 1, zmin, zmax, lo, hi);
-            if (done) lds_insert_box(lds, cd, v, count, op_bit, lo, hi);
-        }
-        if (!done) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!((valid >> q) & 1u)) continue;
-                const int u = u0 + (q & 1), vv = v0 + (q >> 1);
-                if (cell_block_range(op, ifx, ify, is, v.mu, u, u, vv, vv, zq[q], zq[q], lo, hi))
-                    lds_insert_box(lds, cd, v, count, op_bit, lo, hi);
-                else
-                    set_error(v.err, SC_ERANGE);
+        if (zmax - zmin <= (CELL == 4 ? kCellSpread : kQuadSpread) * v.mu)
+            done = insert_cell<kSet>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0, u0 + CELL - 1, v0,
+                                     v0 + CELL - 1, zmin, zmax);
+        if (!done && CELL == 4) {
+            for (int qd = 0; qd < 4; ++qd) {
+                const int qu = u0 + 2 * (qd & 1), qv = v0 + 2 * (qd >> 1);
+                const int q0 = 2 * (qd & 1) + 2 * CELL * (qd >> 1);  // first pixel of the quad in zc
+                const int idx[4] = {q0, q0 + 1, q0 + CELL, q0 + CELL + 1};
+                float qmin = 3.0e38f, qmax = 0.0f;
+                uint32_t qvalid = 0u;
+                for (int k = 0; k < 4; ++k)
+                    if ((valid >> idx[k]) & 1u) {
+                        qvalid |= 1u << k;
+                        qmin = fminf(qmin, zc[idx[k]]);
+                        qmax = fmaxf(qmax, zc[idx[k]]);
+                    }
+                if (!qvalid) continue;
+                if (qmax - qmin <= kQuadSpread * v.mu &&
+                    insert_cell<kSet>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu, qu + 1, qv, qv + 1, qmin,
+                                      qmax))
+                    continue;
+                for (int k = 0; k < 4; ++k)
+                    if ((qvalid >> k) & 1u)
+                        insert_pixels<kSet>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu + (k & 1),
+                                            qv + (k >> 1), zc[idx[k]]);
             }
+        } else if (!done) {
+            for (int q = 0; q < kPix; ++q)
+                if ((valid >> q) & 1u)
+                    insert_pixels<kSet>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0 + (q % CELL),
+                                        v0 + (q / CELL), zc[q]);
         }
     }
     __syncthreads();
     // insert the tile's blocks; new candidates are appended with one atomic
-    // per wavefront (every lane runs the same kLdsSet / kCandThreads
-    // iterations)
+    // per wavefront (every lane runs the same kSet / kThreads iterations)
     const int lane = tid & 63;
-    for (int it = 0; it < kLdsSet / kCandThreads; ++it) {
-        const uint64_t key = lds[tid + it * kCandThreads];
+    for (int it = 0; it < kSet / kThreads; ++it) {
+        const uint64_t key = lds[tid + it * kThreads];
         bool fresh = false;
         int gb = -1;
         if (key != kKeyEmpty) {

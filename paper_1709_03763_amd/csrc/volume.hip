@@ -119,12 +119,12 @@ __global__ void hash_lookup_kernel(VolDev v, const int32_t* xyz, int64_t n, int3
 
 __global__ __launch_bounds__(256) void cand_plain_kernel(OpDesc op, VolDev v, CandDev cd, int parity)
 {
-    __shared__ uint64_t lds[kLdsSet];
+    __shared__ uint64_t lds[CandCfg<kTilePlain, kCellPlain>::lds_set];
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         cd.counters[1 - parity] = 0u;
         cd.counters[2 + (1 - parity)] = 0u;
     }
-    cand_tile(op, v, cd, cd.counters + parity, blockIdx.x, blockIdx.y, -1, lds);
+    cand_tile<kTilePlain, kCellPlain>(op, v, cd, cd.counters + parity, blockIdx.x, blockIdx.y, -1, lds);
 }
 
 // Applies one operation to one candidate block with one wavefront, eight
@@ -302,8 +302,8 @@ sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     make_op(vol, kf, in, T, sign, 0, &op);
     const int p = vol->parity;
     vol->parity ^= 1;
-    dim3 tiles((in->width + kTile - 1) / kTile, (in->height + kTile - 1) / kTile);
-    cand_plain_kernel<<<tiles, 256, 0, s>>>(op, vol->dev, vol->cand, p);
+    dim3 tiles((in->width + kTilePlain - 1) / kTilePlain, (in->height + kTilePlain - 1) / kTilePlain);
+    cand_plain_kernel<<<tiles, CandCfg<kTilePlain, kCellPlain>::threads, 0, s>>>(op, vol->dev, vol->cand, p);
     const int grid = vol->n_cu * 4;
     if (vol->p.color_mode == SC_COLOR_RGBA8)
         update_plain_kernel<SC_COLOR_RGBA8><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
@@ -373,6 +373,8 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.mask, sizeof(uint64_t) * cb * c.words) == hipSuccess;
     ok &= hipMalloc(&c.list, sizeof(uint32_t) * c.cap) == hipSuccess;
     ok &= hipMalloc(&c.sorted, sizeof(uint32_t) * cb) == hipSuccess;  // every bucket may be a candidate
+    ok &= hipMalloc(&c.skey, sizeof(uint64_t) * cb) == hipSuccess;
+    ok &= hipMalloc(&c.sslot, sizeof(int32_t) * cb) == hipSuccess;
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
@@ -410,6 +412,8 @@ void sc_volume_destroy(sc_volume* vol)
     for (int i = 0; i < 2 * vol->timing_cap; ++i) hipEventDestroy(vol->timing_ev[i]);
     delete[] vol->timing_ev;
     hipFree(vol->cand.stats);
+    hipFree(vol->cand.skey);
+    hipFree(vol->cand.sslot);
     hipFree(vol->dev.keys);
     hipFree(vol->dev.vals);
     hipFree(vol->dev.slot_keys);
