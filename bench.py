@@ -148,6 +148,8 @@ def kernel_variant(sched):
     """Name of the voxel-pass kernel a schedule (vpl, waves_per_wg, wgs_per_cu,
     compact) launches."""
     vpl, _, _, compact = sched
+    if compact == 3:
+        return "batch_pipe_kernel<RGBA8>"
     if compact:
         return f"batch_compact_kernel<RGBA8,{8 if compact == 1 else 4}>"
     return "batch_main_wave_kernel<RGBA8>" if vpl == 8 else f"batch_main_group_kernel<RGBA8,{vpl}>"
@@ -237,7 +239,7 @@ def main():
         log(f"autotuned schedule {sched} ({tune_ms:.2f} ms)")
     if args.sweep:
         sweep = [(8, 4, 2, 0), (8, 4, 4, 0), (8, 4, 8, 0), (4, 2, 8, 0), (4, 2, 16, 0), (2, 4, 4, 0), (2, 4, 8, 0),
-                 (1, 8, 2, 0), (1, 8, 4, 0), (8, 4, 2, 1), (8, 4, 4, 1), (8, 2, 4, 1), (8, 2, 8, 1), (8, 1, 16, 1), (8, 4, 4, 2), (8, 2, 8, 2), (8, 1, 16, 2)]
+                 (1, 8, 2, 0), (1, 8, 4, 0), (8, 4, 2, 1), (8, 4, 4, 1), (8, 2, 4, 1), (8, 2, 8, 1), (8, 1, 16, 1), (8, 4, 4, 2), (8, 2, 8, 2), (8, 1, 16, 2), (8, 4, 4, 3), (8, 2, 8, 3), (8, 1, 16, 3)]
         keep = vol.get_schedule()
         for sc in sweep:
             vol.set_schedule(*sc)

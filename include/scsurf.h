@@ -231,10 +231,12 @@ sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
  *                8 / vpl) unless `compact` is set, where it may be 1, 2 or 4.
  *   wgs_per_cu   persistent workgroups per compute unit, 1..32.
  *   compact      0: each lane updates its own voxels, block state held in
- *                registers.  1 or 2 (vpl 8 only): block state held in LDS,
- *                the touched voxels of each operation are gathered into an
- *                LDS queue and updated by all 64 lanes together; 2 tests a
- *                lane's voxels four at a time (fewer registers).
+ *                registers.  1, 2 or 3 (vpl 8 only): block state held in
+ *                LDS, the touched voxels of each operation are gathered into
+ *                an LDS queue and updated by all 64 lanes together; 2 tests
+ *                a lane's voxels four at a time (fewer registers); 3 does as
+ *                2 and issues the keyframe gathers of the next four voxels
+ *                (or the next operation) before updating the current ones.
  * Every schedule gives identical bits.  sc_set_schedule validates and stores
  * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back. */
 typedef struct {

@@ -493,6 +493,251 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     stat_add(cd, 3, worker, n_written, lane);
 }
 
+// Per-block operation walk of the pipelined pass: the operations of a block
+// in bit order, read word by word from its mask.
+struct OpWalk {
+    const uint64_t* mask;
+    int words, w;
+    uint64_t m;
+    uint32_t pairs;
+};
+
+__device__ inline int walk_next(OpWalk& k)
+{
+    while (k.m == 0ull) {
+        if (++k.w >= k.words) return -1;
+        k.m = bcast64(k.mask[k.w]);
+        k.pairs += (uint32_t)__popcll(k.m);
+    }
+    const int b = __ffsll((unsigned long long)k.m) - 1;
+    k.m &= k.m - 1;
+    return k.w * 64 + b;
+}
+
+// State of the pipelined pass within one block.
+struct PipeBlock {
+    int bx, by, bz, slot, skip_op;
+    uint32_t touched, n_upd;
+    bool re_touch, e_na, e_w;
+};
+
+// One step of the pipelined pass: issue the keyframe gathers of the next
+// (operation, part) into `nxt`, then decide, gather into the queue and update
+// the current one from `cur`.  The dense phase reads only LDS, so the loads
+// of `nxt` stay in flight while the current part is processed.  Returns
+// false when the block has no further step.
+template <int CM>
+__device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v, OpWalk& walk, PipeBlock& pb,
+                                 VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, int& op_c, int& part_c, double& qz_c,
+                                 float base_f[3], double& qz_f, int lane, float* sD, float* sW, uint32_t* sC,
+                                 double* sCf, float* qw, float* qz, uint32_t* qc, uint16_t* qvox)
+{
+    constexpr int TV = 4;
+    int op_n, part_n;
+    if (part_c == 0) {
+        op_n = op_c;
+        part_n = 1;
+    } else {
+        op_n = walk_next(walk);
+        part_n = 0;
+    }
+    if (op_n >= 0) {
+        const OpDesc& on = ops[op_n];
+        if (part_n == 0) {
+            float q[3];
+            block_origin(on, v.s, pb.bx, pb.by, pb.bz, q, qz_f);
+            const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) base_f[r] = (q[r] + kx * on.a[0][r]) + ky * on.a[1][r];
+        }
+        fetch_voxels<CM, TV, true>(on, base_f, part_n * TV, nxt);
+    }
+    const OpDesc& op = ops[op_c];
+    if (op_c != pb.skip_op) {
+        VoxHits<CM, TV> hv;
+        decide_voxels<CM, TV>(cur, v.mu, hv);
+        uint32_t cnt = 0u;
+#pragma unroll
+        for (int j = 0; j < TV; ++j) {
+            const bool t = (hv.hit >> j) & 1u;
+            const uint64_t bal = __ballot(t);
+            if (t) {
+                const uint32_t pos = cnt + lanes_below(bal);
+                qvox[pos] = (uint16_t)(lane + 64 * (part_c * TV + j));
+                qw[pos] = hv.w[j];
+                qz[pos] = hv.z[j];
+                qc[pos] = (CM == SC_COLOR_RGBA8) ? hv.c[j] : (uint32_t)hv.pix[j];
+            }
+            cnt += (uint32_t)__popcll(bal);
+        }
+        if (cnt != 0u) {
+            if (op.sign < 0 && pb.slot < 0) {
+                pb.e_na = true;
+                pb.skip_op = op_c;
+            } else {
+                if (op.sign > 0) pb.re_touch = true;
+                pb.touched |= hv.hit << (part_c * TV);
+                pb.n_upd += __popc(hv.hit);
+                wave_lds_sync();
+                for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+                    const uint32_t e = r0 + (uint32_t)lane;
+                    if (e < cnt) {
+                        const int x = qvox[e];
+                        const double pz64 = ((qz_c + (double)(x & 7) * op.az[0]) +
+                                             (double)((x >> 3) & 7) * op.az[1]) +
+                                            (double)(x >> 6) * op.az[2];
+                        const float d = distance(qz[e], pz64);
+                        const float wq = qw[e];
+                        float D = sD[x], W = sW[x];
+                        if (CM == SC_COLOR_RGBA8) {
+                            uint32_t C = sC[x];
+                            pb.e_w |= !update_rgba8(D, W, C, d, wq, qc[e], op.sign);
+                            sC[x] = C;
+                        } else {
+                            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * (size_t)qc[e];
+                            const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
+                            double C3[3] = {sCf[x], sCf[512 + x], sCf[1024 + x]};
+                            pb.e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
+                            sCf[x] = C3[0];
+                            sCf[512 + x] = C3[1];
+                            sCf[1024 + x] = C3[2];
+                        }
+                        sD[x] = D;
+                        sW[x] = W;
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+    if (op_n < 0) return false;
+    if (part_n == 0) qz_c = qz_f;
+    op_c = op_n;
+    part_c = part_n;
+    return true;
+}
+
+// Persistent voxel pass, compacting and pipelined: the compacting pass (four
+// voxels per lane per part, LDS queue carrying the keyframe samples) with the
+// gathers of each (operation, part) issued one step ahead, through two
+// fetch buffers used alternately.
+template <int CM>
+__global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
+{
+    constexpr int TV = 4, Q = 64 * TV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)bcast(threadIdx.x >> 6);
+    unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM, TV>();
+    float* sD = reinterpret_cast<float*>(wb);
+    float* sW = sD + 512;
+    uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);
+    double* sCf = reinterpret_cast<double*>(sW + 512);
+    float* qw = reinterpret_cast<float*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    float* qz = qw + Q;
+    uint32_t* qc = reinterpret_cast<uint32_t*>(qz + Q);
+    uint16_t* qvox = reinterpret_cast<uint16_t*>(qc + Q);
+    const uint32_t n = cd.counters[4];
+    const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
+    const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
+    WorkCursor cur;
+    cursor_init(cur, worker);
+    uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
+    for (;;) {
+        const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
+        if (i >= n) break;
+        const uint32_t h = bcast(cd.sorted[i]);
+        const uint64_t key = bcast64(cd.skey[i]);
+        PipeBlock pb;
+        pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
+        unpack_key(key, pb.bx, pb.by, pb.bz);
+        pb.skip_op = -1;
+        pb.touched = 0u;
+        pb.n_upd = 0u;
+        pb.re_touch = pb.e_na = pb.e_w = false;
+        {
+            const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
+            const bool have = pb.slot >= 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                sD[x] = have ? blk[x] : 0.0f;
+                sW[x] = have ? blk[512 + x] : 0.0f;
+                if (CM == SC_COLOR_RGBA8) {
+                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk)[1024 + x] : 0u;
+                } else {
+                    const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+                    sCf[x] = have ? Cd[x] : 0.0;
+                    sCf[512 + x] = have ? Cd[512 + x] : 0.0;
+                    sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
+                }
+            }
+        }
+        wave_lds_sync();
+        OpWalk walk;
+        walk.mask = cd.mask + (size_t)h * cd.words;
+        walk.words = cd.words;
+        walk.w = 0;
+        walk.m = bcast64(walk.mask[0]);
+        walk.pairs = (uint32_t)__popcll(walk.m);
+        int op_c = walk_next(walk);
+        if (op_c >= 0) {
+            VoxFetch<CM, TV> f0, f1;
+            int part_c = 0;
+            double qz_c, qz_f;
+            float base_f[3];
+            {
+                const OpDesc& o0 = ops[op_c];
+                float q[3];
+                block_origin(o0, v.s, pb.bx, pb.by, pb.bz, q, qz_f);
+                const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) base_f[r] = (q[r] + kx * o0.a[0][r]) + ky * o0.a[1][r];
+                fetch_voxels<CM, TV, true>(o0, base_f, 0, f0);
+                qz_c = qz_f;
+            }
+            for (;;) {
+                if (!pipe_step<CM>(ops, v, walk, pb, f0, f1, op_c, part_c, qz_c, base_f, qz_f, lane, sD, sW, sC, sCf,
+                                   qw, qz, qc, qvox))
+                    break;
+                if (!pipe_step<CM>(ops, v, walk, pb, f1, f0, op_c, part_c, qz_c, base_f, qz_f, lane, sD, sW, sC, sCf,
+                                   qw, qz, qc, qvox))
+                    break;
+            }
+        }
+        n_pairs += walk.pairs;
+        n_upd += pb.n_upd;
+        const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
+        int slot = pb.slot;
+        if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
+        if (slot >= 0) {
+            float* blk = v.pool + (size_t)slot * v.stride;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (!((pb.touched >> j) & 1u)) continue;
+                const int x = lane + 64 * j;
+                blk[x] = sD[x];
+                blk[512 + x] = sW[x];
+                if (CM == SC_COLOR_RGBA8) {
+                    reinterpret_cast<uint32_t*>(blk)[1024 + x] = sC[x];
+                } else {
+                    double* Cd = reinterpret_cast<double*>(blk + 1024);
+                    Cd[x] = sCf[x];
+                    Cd[512 + x] = sCf[512 + x];
+                    Cd[1024 + x] = sCf[1024 + x];
+                }
+            }
+        }
+        const bool wrote = __ballot(pb.touched != 0) != 0;
+        n_written += (slot >= 0 && wrote) ? 1u : 0u;
+        retire_candidate(cd, v, h, all, lane);
+        wave_lds_sync();
+    }
+    stat_add(cd, 1, worker, n_pairs, lane);
+    stat_add(cd, 2, worker, wave_sum(n_upd), lane);
+    stat_add(cd, 3, worker, n_written, lane);
+}
+
 // Persistent voxel pass, one workgroup of G = 8 / VPL wavefronts per block
 // (wavefront w owns z in [w VPL, (w+1) VPL)).  Wavefront 0 pops and
 // allocates; the others learn the results through LDS after a barrier.  The
@@ -574,7 +819,7 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
 static bool schedule_ok(const sc_schedule& s)
 {
     if (s.vpl != 8 && s.vpl != 4 && s.vpl != 2 && s.vpl != 1) return false;
-    if (s.compact < 0 || s.compact > 2) return false;
+    if (s.compact < 0 || s.compact > 3) return false;
     if (s.compact && (s.vpl != 8 || (s.waves_per_wg != 1 && s.waves_per_wg != 2 && s.waves_per_wg != 4)))
         return false;
     return s.wgs_per_cu >= 1 && s.wgs_per_cu <= 32;
@@ -601,7 +846,14 @@ static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_
     if (sch.compact) {
         const int threads = 64 * sch.waves_per_wg;
         const size_t w = sch.waves_per_wg;
-        if (sch.compact == 1) {
+        if (sch.compact == 3) {
+            if (rgba)
+                batch_pipe_kernel<SC_COLOR_RGBA8><<<grid, threads, w * compact_wave_bytes<SC_COLOR_RGBA8, 4>(), s>>>(
+                    vol->d_ops, vol->dev, vol->cand);
+            else
+                batch_pipe_kernel<SC_COLOR_F32><<<grid, threads, w * compact_wave_bytes<SC_COLOR_F32, 4>(), s>>>(
+                    vol->d_ops, vol->dev, vol->cand);
+        } else if (sch.compact == 1) {
             if (rgba)
                 batch_compact_kernel<SC_COLOR_RGBA8, 8><<<grid, threads, w * compact_wave_bytes<SC_COLOR_RGBA8, 8>(),
                                                           s>>>(vol->d_ops, vol->dev, vol->cand);
@@ -893,7 +1145,7 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     static const sc_schedule cands[] = {{8, 4, 2, 0}, {8, 4, 4, 0}, {8, 4, 8, 0}, {4, 2, 8, 0}, {4, 2, 16, 0},
                                         {2, 4, 4, 0}, {2, 4, 8, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {8, 4, 2, 1},
                                         {8, 4, 4, 1}, {8, 2, 4, 1},  {8, 2, 8, 1},  {8, 1, 16, 1}, {8, 4, 4, 2},
-                                        {8, 2, 8, 2}, {8, 1, 16, 2}};
+                                        {8, 2, 8, 2}, {8, 1, 16, 2}, {8, 4, 4, 3},  {8, 2, 8, 3},  {8, 1, 16, 3}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         sc_volume_destroy(tmp);

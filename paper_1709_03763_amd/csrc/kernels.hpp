@@ -182,14 +182,20 @@ struct VoxHits {
     uint32_t c[VPL]; // RGBA8 colour at the pixel (RGBA8 mode)
 };
 
-// Touched tests of a lane's VPL voxels: every projection first, then every
-// keyframe load (voxels outside the image read pixel 0, so the loads need no
-// branch and are issued together), then the decisions.
-template <int CM, int VPL, bool kColor = true>
-__device__ inline void test_voxels(const OpDesc& op, float mu, const float base[3], int kz0, VoxHits<CM, VPL>& h)
+// Projections and keyframe samples of a lane's VPL voxels for one operation
+// (the loads are issued, not waited for: the caller decides later).
+template <int CM, int VPL>
+struct VoxFetch {
+    uint32_t in;  // bit j: voxel j projects into the image
+    int pix[VPL];
+    float pz[VPL], wr[VPL], z[VPL];
+    uint32_t c[VPL];  // RGBA8 colour at the pixel (RGBA8 mode)
+};
+
+template <int CM, int VPL, bool kColor>
+__device__ inline void fetch_voxels(const OpDesc& op, const float base[3], int kz0, VoxFetch<CM, VPL>& f)
 {
-    bool in[VPL];
-    float pzv[VPL];
+    f.in = 0u;
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
         const float fz = (float)(kz0 + j);
@@ -197,35 +203,56 @@ __device__ inline void test_voxels(const OpDesc& op, float mu, const float base[
         const float py = base[1] + fz * op.a[2][1];
         const float pz = base[2] + fz * op.a[2][2];
         int p = 0;
-        in[j] = nearest_pixel(op, px, py, pz, p);
-        h.pix[j] = in[j] ? p : 0;
-        pzv[j] = pz;
+        const bool in = nearest_pixel(op, px, py, pz, p);
+        f.in |= in ? (1u << j) : 0u;
+        f.pix[j] = in ? p : 0;
+        f.pz[j] = pz;
     }
-    float wr[VPL];
     if (CM == SC_COLOR_RGBA8 && op.packed) {
 #pragma unroll
         for (int j = 0; j < VPL; ++j) {
-            const uint4 r = __ldg(op.packed + h.pix[j]);
-            h.z[j] = __uint_as_float(r.x);
-            wr[j] = __uint_as_float(r.y);
-            h.c[j] = r.z;
+            const uint4 r = __ldg(op.packed + f.pix[j]);
+            f.z[j] = __uint_as_float(r.x);
+            f.wr[j] = __uint_as_float(r.y);
+            f.c[j] = r.z;
         }
     } else {
 #pragma unroll
         for (int j = 0; j < VPL; ++j) {
-            wr[j] = __ldg(op.weight + h.pix[j]);
-            h.z[j] = __ldg(op.depth + h.pix[j]);
-            if (kColor && CM == SC_COLOR_RGBA8)
-                h.c[j] = __ldg(reinterpret_cast<const uint32_t*>(op.color) + h.pix[j]);
+            f.wr[j] = __ldg(op.weight + f.pix[j]);
+            f.z[j] = __ldg(op.depth + f.pix[j]);
+            f.c[j] = (kColor && CM == SC_COLOR_RGBA8)
+                         ? __ldg(reinterpret_cast<const uint32_t*>(op.color) + f.pix[j])
+                         : 0u;
         }
     }
+}
+
+// The touched decisions of fetched voxels.
+template <int CM, int VPL>
+__device__ inline void decide_voxels(const VoxFetch<CM, VPL>& f, float mu, VoxHits<CM, VPL>& h)
+{
     h.hit = 0u;
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
-        h.w[j] = qweight(wr[j]);
-        const bool t = in[j] && h.w[j] > 0.0f && fabsf(h.z[j] - pzv[j]) <= mu;
+        h.pix[j] = f.pix[j];
+        h.z[j] = f.z[j];
+        h.c[j] = f.c[j];
+        h.w[j] = qweight(f.wr[j]);
+        const bool t = ((f.in >> j) & 1u) && h.w[j] > 0.0f && fabsf(h.z[j] - f.pz[j]) <= mu;
         h.hit |= t ? (1u << j) : 0u;
     }
+}
+
+// Touched tests of a lane's VPL voxels: every projection first, then every
+// keyframe load (voxels outside the image read pixel 0, so the loads need no
+// branch and are issued together), then the decisions.
+template <int CM, int VPL, bool kColor = true>
+__device__ inline void test_voxels(const OpDesc& op, float mu, const float base[3], int kz0, VoxHits<CM, VPL>& h)
+{
+    VoxFetch<CM, VPL> f;
+    fetch_voxels<CM, VPL, kColor>(op, base, kz0, f);
+    decide_voxels<CM, VPL>(f, mu, h);
 }
 
 // ---------------------------------------------------------------------------
