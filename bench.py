@@ -155,6 +155,53 @@ def kernel_variant(sched):
     return "batch_main_wave_kernel<RGBA8>" if vpl == 8 else f"batch_main_group_kernel<RGBA8,{vpl}>"
 
 
+def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20):
+    """The online loop on the corridor workload: frames fused into keyframes of
+    five, each keyframe integrated at its drifting estimate, a pose-graph
+    update every `every` keyframes re-integrating the Eq. 3 window of m,
+    then the final pass.  Frames are rendered to the device first; the loop
+    is timed."""
+    from paper_1709_03763_amd import online
+
+    wl = synth.workload(5)
+    kappa = wl.kappa
+    groups = synth.keyframe_groups(wl)[: n_frames // kappa]
+    first = np.array([g[0] for g in groups])
+    Rk, tk = wl.R[first], wl.t[first]
+    drift = online.drifting_estimates(Rk, tk, seed=55)
+    Re, te = online.corrected(Rk, tk, drift, 1.0)
+    idx = np.concatenate(groups)
+    zs, cs = [], []
+    for s0 in range(0, len(idx), 100):
+        z, rgb = synth.frames(wl, idx[s0:s0 + 100], device="cuda")
+        zs.append(torch.from_numpy(z).cuda())
+        cs.append(torch.from_numpy(rgb).cuda())
+    Z, C = torch.cat(zs), torch.cat(cs)
+    poses = []
+    for k, g in enumerate(groups):
+        A = Re[k] @ Rk[k].T
+        poses += [(A @ wl.R[f], A @ (wl.t[f] - tk[k]) + te[k]) for f in g]
+    updates = {n: online.corrected(Rk[:n], tk[:n], drift[:n], 0.5 ** (n // every))
+               for n in range(every, len(groups) + 1, every)}
+    vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, 1 << 21, scsurf.COLOR_RGBA8,
+                        max_batch_ops=512)
+    sess = online.OnlineSession(vol, wl.intr, kappa, m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(len(idx)):
+        k = sess.add_frame(Z[f], C[f], *poses[f])
+        if k is not None and (k + 1) in updates:
+            sess.pose_update(*updates[k + 1])
+    final = sess.final_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_blocks = vol.check_error()
+    vol.close()
+    return {"frames": len(idx), "keyframes": len(groups), "updates": len(updates), "m": m,
+            "final_pass_keyframes": len(final), "reintegrated_keyframes": sess.reintegrated, "blocks": n_blocks,
+            "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1)}
+
+
 def traffic_from_profile(digest, variant):
     """HBM bytes per launch of the voxel pass from the committed rocprofv3
     counter summary, if it was taken from the current kernel sources and the
@@ -184,6 +231,7 @@ def main():
     ap.add_argument("--schedule", type=str, default="",
                     help="fixed voxel-pass schedule vpl,waves_per_wg,wgs_per_cu,compact (skips the autotuner)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-online", action="store_true")
     ap.add_argument("--no-pack", action="store_true",
                     help="keyframes without the interleaved copy (three gathers per voxel test)")
     ap.add_argument("--cpu-sample", type=int, default=200,
@@ -306,6 +354,13 @@ def main():
                  "batched_speedup": round(pms / ms_per_step, 2)}
         log(f"plain: {pms:.3f} ms/step ({plain['batched_speedup']}x slower than batched)")
 
+    online_res = None
+    if not args.no_online:
+        online_res = online_stage(torch, scsurf, synth)
+        log(f"online loop (corridor, {online_res['frames']} frames): {online_res['frames_per_s']} frames/s, "
+            f"{online_res['reintegrated_keyframes']} keyframe re-integrations incl. a final pass of "
+            f"{online_res['final_pass_keyframes']}")
+
     adj_ms = None
     if not args.no_adjoint:
         adj_ms = adjoint_stage(torch, scsurf, synth)
@@ -365,9 +420,16 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "stages": {"kf_fuse_frames_per_s": round(n_kf * wl.kappa / fuse_s, 1),
+                   # algorithmic bytes of fusing one keyframe: kappa frames of depth (4 B) and RGB (3 B)
+                   # read, one keyframe of depth, weight and RGBA8 (12 B) written, per pixel
+                   "kf_fuse_hbm_frac": round(n_kf * H * Wd * (wl.kappa * 7 + 12) / fuse_s / 1e9 / HBM_PEAK_GBS, 5),
                    "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
+                   # plain integration of the 200 keyframes into the empty volume: blocks written once
+                   # (read and write, 24 B per voxel) plus each keyframe read once
+                   "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)
+                                               / integrate_s / 1e9 / HBM_PEAK_GBS, 5),
                    "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),
-                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms},
+                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms, "online_loop": online_res},
     }
     print(json.dumps(out), flush=True)
     vol.close()

@@ -1,0 +1,124 @@
+"""Online surface correction session (Sec. 4.1 "System Pipeline" and Sec. 4.3
+"Re-integration strategy"): host-side control over the library's calls.
+
+Frames arrive with pose estimates and are collected into the current
+keyframe (the constant-size strategy, kappa frames per keyframe).  A complete
+keyframe is fused (Eq. 1 and the colour median, `kf_fuse`), packed, and
+integrated into the volume at its current pose estimate, which becomes its
+integration pose.  A pose-graph update supplies new estimates for every
+keyframe so far; the update re-integrates the selected keyframes (by default
+the m most-moved consecutive keyframes, Eq. 3) in one batched pass, and
+only those take the new pose as their integration pose.  The final pass
+re-integrates every keyframe whose integration pose differs from its latest
+estimate.  Every step runs in the library's kernels; this module only
+decides which call to make.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import scsurf
+
+
+class OnlineSession:
+    def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None):
+        if kappa < 1 or m < 1:
+            raise ValueError("kappa and m must be positive")
+        self.vol, self.intr, self.kappa, self.m, self.mode, self.stream = vol, intr, kappa, m, mode, stream
+        self._depth, self._rgb, self._R, self._t = [], [], [], []
+        self.keyframes: list[scsurf.Keyframe] = []
+        self.R_int = np.zeros((0, 3, 3))  # integration poses
+        self.t_int = np.zeros((0, 3))
+        self.R_new = np.zeros((0, 3, 3))  # latest estimates
+        self.t_new = np.zeros((0, 3))
+        self._kset = None
+        self.reintegrated = 0  # keyframe re-integrations performed (de + re counted once)
+
+    @property
+    def n_keyframes(self) -> int:
+        return len(self.keyframes)
+
+    def add_frame(self, depth: torch.Tensor, rgb: torch.Tensor, R, t):
+        """One RGB-D frame (device tensors, depth (H,W) f32, rgb (H,W,3) u8)
+        with its pose estimate (camera to world).  Returns the index of the
+        keyframe integrated by this frame, or None."""
+        self._depth.append(depth)
+        self._rgb.append(rgb)
+        self._R.append(np.asarray(R, np.float64))
+        self._t.append(np.asarray(t, np.float64))
+        if len(self._depth) < self.kappa:
+            return None
+        return self._finish_keyframe()
+
+    def _finish_keyframe(self):
+        z = torch.stack(self._depth)
+        c = torch.stack(self._rgb)
+        R, t = np.array(self._R), np.array(self._t)
+        kf = scsurf.kf_fuse(z, c, R, t, self.intr, stream=self.stream)
+        kf = scsurf.keyframe_pack(kf, stream=self.stream)
+        self._depth, self._rgb, self._R, self._t = [], [], [], []
+        self.vol.integrate(kf, self.intr, R[0], t[0], stream=self.stream)
+        self.keyframes.append(kf)
+        self._kset = None
+        self.R_int = np.concatenate([self.R_int, R[:1]])
+        self.t_int = np.concatenate([self.t_int, t[:1]])
+        self.R_new = np.concatenate([self.R_new, R[:1]])
+        self.t_new = np.concatenate([self.t_new, t[:1]])
+        return self.n_keyframes - 1
+
+    def _keyframe_set(self):
+        if self._kset is None or len(self._kset) != self.n_keyframes:
+            self._kset = scsurf.KeyframeSet(self.keyframes)
+        return self._kset
+
+    def pose_update(self, R, t):
+        """New pose estimates for the keyframes so far ((K,3,3), (K,3)).
+        Re-integrates the selected keyframes; returns their indices in
+        processing order."""
+        R = np.asarray(R, np.float64).reshape(-1, 3, 3)
+        t = np.asarray(t, np.float64).reshape(-1, 3)
+        if len(R) != self.n_keyframes:
+            raise ValueError(f"{len(R)} poses for {self.n_keyframes} keyframes")
+        self.R_new, self.t_new = R.copy(), t.copy()
+        if self.n_keyframes == 0:
+            return []
+        order, (Ri, ti) = self.vol.reintegrate_batch(self._keyframe_set(), self.intr, (self.R_int, self.t_int),
+                                                      (self.R_new, self.t_new), self.m, self.mode, self.stream)
+        self.R_int, self.t_int = Ri, ti
+        self.reintegrated += len(order)
+        return order
+
+    def final_pass(self):
+        """Re-integrates every keyframe whose integration pose differs from its
+        latest estimate, most-moved first.  Returns their indices."""
+        if self.n_keyframes == 0:
+            return []
+        order, (Ri, ti) = self.vol.reintegrate_batch(self._keyframe_set(), self.intr, (self.R_int, self.t_int),
+                                                      (self.R_new, self.t_new), self.n_keyframes,
+                                                      scsurf.SEL_ALL_ORDERED, self.stream)
+        self.R_int, self.t_int = Ri, ti
+        self.reintegrated += len(order)
+        return order
+
+
+def drifting_estimates(R, t, seed, rho_step=0.002, phi_step_deg=0.1):
+    """Synthetic tracking: pose estimates of keyframes whose error grows as a
+    seeded random walk in se(3) (rho_step m and phi_step_deg per keyframe),
+    applied as T_est = T_true Exp(drift)."""
+    rng = np.random.default_rng(seed)
+    K = len(R)
+    steps = np.concatenate([rng.normal(0, rho_step, (K, 3)), rng.normal(0, np.radians(phi_step_deg), (K, 3))], 1)
+    drift = np.cumsum(steps, axis=0)
+    return drift
+
+
+def corrected(R, t, drift, frac):
+    """Poses T_true Exp(frac * drift): a pose-graph update that removes
+    (1 - frac) of each keyframe's drift."""
+    from .synth import compose, se3_exp
+    Rn, tn = np.empty_like(R), np.empty_like(t)
+    for k in range(len(R)):
+        dR, dt = se3_exp(frac * drift[k])
+        Rn[k], tn[k] = compose(R[k], t[k], dR, dt)
+    return Rn, tn
