@@ -146,6 +146,19 @@ sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, flo
 
 /* ---- keyframe fusion (Sec. 3 "Keyframe Fusion", Eq. 1) ------------------- */
 
+/* Overlap of a frame with a keyframe's reference view (Sec. 4.2, the
+ * overlap strategy for starting a new keyframe).  A pixel of `depth` is
+ * valid if z_min <= Z <= z_max; it is visible if its back-projected point,
+ * moved into the reference camera (T_ref^-1 T_frame), lies in front of it
+ * and its nearest pixel there is inside the image.  Computed in FP64 in the
+ * written order (camera point ((u - cx) / fx) Z, ((v - cy) / fy) Z, Z; world
+ * point R p + t row by row; reference point R_ref^T (w - t_ref) column by
+ * column; pixel floor(fx x / z + cx + 1/2)).  counts: device, 2 x uint32
+ * {valid, visible}, overwritten.  depth: device H x W.  SC_EINVAL on a null
+ * pointer or bad intrinsics; asynchronous on `stream`. */
+sc_status sc_overlap(const float* depth, const sc_intrinsics* intr, const sc_pose* T_frame, const sc_pose* T_ref,
+                     float z_min, float z_max, uint32_t* counts, void* stream);
+
 /* Per-pixel depth weight w_z = cos(theta) Z^-2, theta the angle between the
  * depth normal and the camera axis, quantised to 2^-10; 0 marks pixels that
  * are invalid or near a depth discontinuity.  depth: device n x H x W;

@@ -408,7 +408,64 @@ static bool intr_valid(const sc_intrinsics* in)
            in->height <= 16384;
 }
 
-// relative pose A^-1 B in FP64 with the written order, rounded to FP32
+// Overlap counts (valid, visible) of one frame with a reference view, FP64
+// in the written order; one thread per pixel, a wavefront reduction, then one
+// atomic per wavefront and counter.
+struct OverlapArgs {
+    double R[9], t[3], Rr[9], tr[3];
+    double fx, fy, cx, cy;
+    float z_min, z_max;
+    int32_t width, height;
+};
+
+__device__ inline uint32_t overlap_wave_sum(uint32_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__global__ void overlap_clear_kernel(uint32_t* counts)
+{
+    if (threadIdx.x < 2) counts[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void overlap_kernel(const float* __restrict__ depth, OverlapArgs a,
+                                                      uint32_t* counts)
+{
+    const int64_t n = (int64_t)a.width * a.height;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t valid = 0u, visible = 0u;
+    if (i < n) {
+        const float zf = depth[i];
+        if (zf >= a.z_min && zf <= a.z_max) {
+            valid = 1u;
+            const int u = (int)(i % a.width), v = (int)(i / a.width);
+            const double z = (double)zf;
+            const double p[3] = {(((double)u - a.cx) / a.fx) * z, (((double)v - a.cy) / a.fy) * z, z};
+            double w[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) w[r] = ((a.R[3 * r] * p[0] + a.R[3 * r + 1] * p[1]) + a.R[3 * r + 2] * p[2]) + a.t[r];
+            const double d[3] = {w[0] - a.tr[0], w[1] - a.tr[1], w[2] - a.tr[2]};
+            double q[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q[c] = (a.Rr[c] * d[0] + a.Rr[3 + c] * d[1]) + a.Rr[6 + c] * d[2];
+            if (q[2] > 0.0) {
+                const double fu = floor(((a.fx * q[0]) / q[2] + a.cx) + 0.5);
+                const double fv = floor(((a.fy * q[1]) / q[2] + a.cy) + 0.5);
+                visible = (fu >= 0.0 && fu <= (double)(a.width - 1) && fv >= 0.0 && fv <= (double)(a.height - 1)) ? 1u : 0u;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    valid = overlap_wave_sum(valid);
+    visible = overlap_wave_sum(visible);
+    if (lane == 0) {  // not a persistent loop: a lane-0 branch is safe here
+        atomicAdd(counts, valid);
+        atomicAdd(counts + 1, visible);
+    }
+}
+
 static void rel_pose(const sc_pose& A, const sc_pose& B, float out[12])
 {
     for (int r = 0; r < 3; ++r) {
@@ -501,6 +558,32 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
     const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
     color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
         depth, g_ws.wz, g_ws.cs, g_ws.wb, n_frames, in, params->occ_rel, g_ws.d_fr, kf_depth, kf_weight, kf_rgba);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status sc_overlap(const float* depth, const sc_intrinsics* intr, const sc_pose* T_frame, const sc_pose* T_ref,
+                     float z_min, float z_max, uint32_t* counts, void* stream)
+{
+    if (!depth || !intr || !T_frame || !T_ref || !counts || intr->width <= 0 || intr->height <= 0 ||
+        intr->width > 16384 || intr->height > 16384 || !(intr->fx > 0.0f) || !(intr->fy > 0.0f))
+        return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    OverlapArgs a;
+    memcpy(a.R, T_frame->R, sizeof(a.R));
+    memcpy(a.t, T_frame->t, sizeof(a.t));
+    memcpy(a.Rr, T_ref->R, sizeof(a.Rr));
+    memcpy(a.tr, T_ref->t, sizeof(a.tr));
+    a.fx = intr->fx;
+    a.fy = intr->fy;
+    a.cx = intr->cx;
+    a.cy = intr->cy;
+    a.z_min = z_min;
+    a.z_max = z_max;
+    a.width = intr->width;
+    a.height = intr->height;
+    overlap_clear_kernel<<<1, 64, 0, s>>>(counts);
+    const int64_t n = (int64_t)intr->width * intr->height;
+    overlap_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(depth, a, counts);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 

@@ -2,7 +2,12 @@
 "Re-integration strategy"): host-side control over the library's calls.
 
 Frames arrive with pose estimates and are collected into the current
-keyframe (the constant-size strategy, kappa frames per keyframe).  A complete
+keyframe.  Sec. 4.2's strategies decide when a keyframe is complete: after
+kappa frames (constant size), when the current frame's motion relative to
+the keyframe's first frame exceeds a translation or rotation threshold
+(distance), or when the share of the frame's valid pixels visible in the
+keyframe's first view falls below a threshold (overlap, counted on the GPU
+by `sc_overlap`); a keyframe never exceeds 64 frames.  A complete
 keyframe is fused (Eq. 1 and the colour median, `kf_fuse`), packed, and
 integrated into the volume at its current pose estimate, which becomes its
 integration pose.  A pose-graph update supplies new estimates for every
@@ -21,11 +26,31 @@ import torch
 from . import scsurf
 
 
+MAX_FRAMES = 64  # frames one keyframe may fuse
+
+
+def relative_motion(R_kf, t_kf, R, t):
+    """(translation norm, rotation angle in radians) of T_kf^-1 T, the angle
+    as atan2 of sin and cos (R - R^T = 2 sin [axis]x, trace = 1 + 2 cos)."""
+    A = np.asarray(R_kf, np.float64).T @ np.asarray(R, np.float64)
+    d = np.asarray(R_kf, np.float64).T @ (np.asarray(t, np.float64) - np.asarray(t_kf, np.float64))
+    s = np.sqrt((A[2, 1] - A[1, 2]) ** 2 + (A[0, 2] - A[2, 0]) ** 2 + (A[1, 0] - A[0, 1]) ** 2) / 2.0
+    c = (np.trace(A) - 1.0) / 2.0
+    return float(np.sqrt(d @ d)), float(np.arctan2(s, c))
+
+
 class OnlineSession:
-    def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None):
+    def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None,
+                 strategy: str = "const", max_trans: float = 0.1, max_rot: float = 0.0873,
+                 min_overlap: float = 0.8, z_min: float = 0.3, z_max: float = 4.0):
         if kappa < 1 or m < 1:
             raise ValueError("kappa and m must be positive")
+        if strategy not in ("const", "dist", "overlap"):
+            raise ValueError(f"unknown keyframe strategy {strategy!r}")
         self.vol, self.intr, self.kappa, self.m, self.mode, self.stream = vol, intr, kappa, m, mode, stream
+        self.strategy, self.max_trans, self.max_rot, self.min_overlap = strategy, max_trans, max_rot, min_overlap
+        self.z_min, self.z_max = z_min, z_max
+        self.keyframe_sizes: list[int] = []
         self._depth, self._rgb, self._R, self._t = [], [], [], []
         self.keyframes: list[scsurf.Keyframe] = []
         self.R_int = np.zeros((0, 3, 3))  # integration poses
@@ -39,17 +64,43 @@ class OnlineSession:
     def n_keyframes(self) -> int:
         return len(self.keyframes)
 
+    def _starts_new_keyframe(self, depth, R, t) -> bool:
+        if not self._depth:
+            return False
+        if len(self._depth) >= MAX_FRAMES:
+            return True
+        if self.strategy == "dist":
+            dt, dr = relative_motion(self._R[0], self._t[0], R, t)
+            return dt > self.max_trans or dr > self.max_rot
+        if self.strategy == "overlap":
+            valid, visible = scsurf.overlap(depth, self.intr, R, t, self._R[0], self._t[0], self.z_min, self.z_max,
+                                            self.stream)
+            return valid > 0 and visible < self.min_overlap * valid
+        return False
+
     def add_frame(self, depth: torch.Tensor, rgb: torch.Tensor, R, t):
         """One RGB-D frame (device tensors, depth (H,W) f32, rgb (H,W,3) u8)
         with its pose estimate (camera to world).  Returns the index of the
-        keyframe integrated by this frame, or None."""
+        keyframe completed and integrated by this frame, or None.  With the
+        distance and overlap strategies the frame that starts a new keyframe
+        completes the previous one."""
+        done = None
+        R = np.asarray(R, np.float64)
+        t = np.asarray(t, np.float64)
+        if self.strategy != "const" and self._starts_new_keyframe(depth, R, t):
+            done = self._finish_keyframe()
         self._depth.append(depth)
         self._rgb.append(rgb)
-        self._R.append(np.asarray(R, np.float64))
-        self._t.append(np.asarray(t, np.float64))
-        if len(self._depth) < self.kappa:
-            return None
-        return self._finish_keyframe()
+        self._R.append(R)
+        self._t.append(t)
+        if self.strategy == "const" and len(self._depth) >= min(self.kappa, MAX_FRAMES):
+            done = self._finish_keyframe()
+        return done
+
+    def flush(self):
+        """Completes the current keyframe if it holds frames; returns its index
+        or None."""
+        return self._finish_keyframe() if self._depth else None
 
     def _finish_keyframe(self):
         z = torch.stack(self._depth)
@@ -57,6 +108,7 @@ class OnlineSession:
         R, t = np.array(self._R), np.array(self._t)
         kf = scsurf.kf_fuse(z, c, R, t, self.intr, stream=self.stream)
         kf = scsurf.keyframe_pack(kf, stream=self.stream)
+        self.keyframe_sizes.append(len(R))
         self._depth, self._rgb, self._R, self._t = [], [], [], []
         self.vol.integrate(kf, self.intr, R[0], t[0], stream=self.stream)
         self.keyframes.append(kf)
@@ -90,8 +142,10 @@ class OnlineSession:
         return order
 
     def final_pass(self):
-        """Re-integrates every keyframe whose integration pose differs from its
-        latest estimate, most-moved first.  Returns their indices."""
+        """Completes the current keyframe, then re-integrates every keyframe
+        whose integration pose differs from its latest estimate, most-moved
+        first.  Returns their indices."""
+        self.flush()
         if self.n_keyframes == 0:
             return []
         order, (Ri, ti) = self.vol.reintegrate_batch(self._keyframe_set(), self.intr, (self.R_int, self.t_int),

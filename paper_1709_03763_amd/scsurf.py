@@ -66,7 +66,7 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
-           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack"]
+           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap"]
 
 _lib = None
 
@@ -108,6 +108,8 @@ def lib():
     L.sc_batch_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
     L.sc_volume_stats.argtypes = [P, P, P]
     L.sc_keyframe_pack.argtypes = [ctypes.POINTER(sc_keyframe), i32, i32, P, P]
+    L.sc_overlap.argtypes = [P, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose),
+                             ctypes.c_float, ctypes.c_float, P, P]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:
@@ -399,6 +401,17 @@ def keyframe_pack(kf: Keyframe, stream=None) -> Keyframe:
     check(lib().sc_keyframe_pack(ctypes.byref(kf.c()), W, H, packed.data_ptr(), stream_handle(stream)),
           "sc_keyframe_pack")
     return Keyframe(kf.depth, kf.weight, kf.color, packed)
+
+
+def overlap(depth: torch.Tensor, intr, R, t, R_ref, t_ref, z_min=0.3, z_max=4.0, stream=None):
+    """(valid, visible) pixel counts of a frame's depth against a reference
+    view (the overlap strategy of Sec. 4.2).  Synchronises."""
+    counts = torch.empty(2, dtype=torch.int32, device=depth.device)
+    check(lib().sc_overlap(dptr(depth, torch.float32, "depth"), ctypes.byref(intrinsics(intr)),
+                           ctypes.byref(pose(R, t)), ctypes.byref(pose(R_ref, t_ref)), float(z_min), float(z_max),
+                           counts.data_ptr(), stream_handle(stream)), "sc_overlap")
+    c = counts.cpu().numpy()
+    return int(c[0]), int(c[1])
 
 
 def depth_weight(depth: torch.Tensor, intr, params=None, stream=None) -> torch.Tensor:

@@ -421,6 +421,21 @@ def workload(cfg: int) -> Workload:
     raise ValueError(f"unknown workload {cfg}")
 
 
+def scan(n_frames: int) -> Workload:
+    """The first n_frames (at most 600) of the tiny workload's room scan, one
+    frame per centimetre of path: the dense sequence keyframe strategies
+    split into keyframes."""
+    if not 1 <= n_frames <= 600:
+        raise ValueError("scan length must be in [1, 600]")
+    wl = workload(1)
+    rng = np.random.default_rng(1)
+    lo, hi = np.zeros(3), np.array([4.0, 4.0, 3.0])
+    path = room_path(rng, lo, hi, 600, step=0.01, margin=1.2)
+    _room_scene(rng, lo, hi, path, 3, 0)
+    R, t = orient_path(rng, path)
+    return Workload("scan", QVGA, wl.scene, R[:n_frames], t[:n_frames], 5, wl.volume, seed=1, invalid_frac=0.05)
+
+
 def frames(wl: Workload, idx, device="cpu", chunk=64):
     """Render frames `idx` of a workload -> (depth float32 (F,H,W), rgb uint8 (F,H,W,3)).
 

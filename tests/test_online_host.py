@@ -46,3 +46,65 @@ def test_halving_corrections_shrink_the_pose_change():
     da = np.linalg.norm(a[1] - t, axis=1)
     db = np.linalg.norm(b[1] - t, axis=1)
     assert np.all(db <= da + 1e-12)
+
+
+class _Recorder(online.OnlineSession):
+    """A session whose keyframe completion only records the frames it holds,
+    so the grouping logic runs without a device."""
+
+    def _finish_keyframe(self):
+        self.keyframe_sizes.append(len(self._R))
+        self._depth, self._rgb, self._R, self._t = [], [], [], []
+        return len(self.keyframe_sizes) - 1
+
+
+def _feed(sess, R, t):
+    done = [sess.add_frame(None, None, R[f], t[f]) for f in range(len(R))]
+    sess.flush()
+    return done
+
+
+def test_constant_strategy_groups_kappa_frames_capped_at_64():
+    R, t = _poses(23)
+    s = _Recorder(None, None, 5, 1)
+    done = _feed(s, R, t)
+    assert s.keyframe_sizes == [5, 5, 5, 5, 3]
+    assert [k for k in done if k is not None] == [0, 1, 2, 3]
+    R, t = _poses(150, seed=2)
+    s = _Recorder(None, None, 100, 1)
+    _feed(s, R, t)
+    assert s.keyframe_sizes == [64, 64, 22]
+
+
+def test_distance_strategy_splits_at_thresholds():
+    # a camera moving 1 cm per frame along x, turning 1 deg per frame about z
+    n = 40
+    R = np.array([synth.se3_exp(np.array([0, 0, 0, 0, 0, np.radians(1.0 * f)]))[0] for f in range(n)])
+    t = np.array([[0.01 * f, 0, 0] for f in range(n)])
+    s = _Recorder(None, None, 5, 1, strategy="dist", max_trans=0.045, max_rot=np.radians(100.0))
+    _feed(s, R, t)
+    assert s.keyframe_sizes == [5] * 8  # 5 cm > 4.5 cm starts the next keyframe
+    s = _Recorder(None, None, 5, 1, strategy="dist", max_trans=10.0, max_rot=np.radians(2.5))
+    _feed(s, R, t)
+    assert s.keyframe_sizes[:-1] == [3] * 13 and s.keyframe_sizes[-1] == 1
+    # a keyframe never exceeds 64 frames, even when the camera stands still
+    R0 = np.repeat(np.eye(3)[None], 130, 0)
+    s = _Recorder(None, None, 5, 1, strategy="dist")
+    _feed(s, R0, np.zeros((130, 3)))
+    assert s.keyframe_sizes == [64, 64, 2]
+
+
+def test_relative_motion_closed_forms():
+    for ang in (0.0, 0.3, 1.0, 2.5, np.pi - 1e-9):
+        axis = np.array([1.0, -2.0, 0.5]) / np.linalg.norm([1.0, -2.0, 0.5])
+        Ra, ta = synth.se3_exp(np.array([0.1, 0.2, 0.3, 0.4, -0.2, 0.9]))
+        dR, dt = synth.se3_exp(np.concatenate([[0, 0, 0], ang * axis]))
+        Rb, tb = synth.compose(Ra, ta, dR, np.array([0.3, 0.0, -0.4]))
+        d, a = online.relative_motion(Ra, ta, Rb, tb)
+        assert abs(d - 0.5) < 1e-12 and abs(a - ang) < 1e-9
+
+
+def test_unknown_strategy_is_rejected():
+    import pytest
+    with pytest.raises(ValueError):
+        online.OnlineSession(None, None, 5, 1, strategy="dvo")
