@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "keyframes re-integrated/sec (de+re) and voxel updates/sec; % of HBM peak"
 HBM_PEAK_GBS = 8000.0
-VOXEL_BYTES = 12  # FP32 D + FP32 W + RGBA8 colour
+VOXEL_BYTES = 16  # FP64 D + FP32 W + RGBA8 colour
 KF_PIXEL_BYTES = 12  # keyframe depth + weight + RGBA8 colour
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_main_traffic.json")
 KERNEL_SOURCES = ["paper_1709_03763_amd/csrc/batch.hip", "paper_1709_03763_amd/csrc/kernels.hpp",
@@ -425,7 +425,7 @@ def main():
                    "kf_fuse_hbm_frac": round(n_kf * H * Wd * (wl.kappa * 7 + 12) / fuse_s / 1e9 / HBM_PEAK_GBS, 5),
                    "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
                    # plain integration of the 200 keyframes into the empty volume: blocks written once
-                   # (read and write, 24 B per voxel) plus each keyframe read once
+                   # (read and write, 32 B per voxel) plus each keyframe read once
                    "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)
                                                / integrate_s / 1e9 / HBM_PEAK_GBS, 5),
                    "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),

@@ -122,7 +122,8 @@ sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height,
 /* ---- volume lifecycle --------------------------------------------------- */
 
 /* Creates an empty volume on the current device.  The block pool
- * (max_blocks x 6 KiB in RGBA8 mode, 16 KiB in F32 mode) and the hash table
+ * (max_blocks x 8 KiB in RGBA8 mode, 18 KiB in F32 mode: D in FP64, W in FP32,
+ * colour as RGBA8 or 3 x FP64) and the hash table
  * are allocated and cleared here.  *out is NULL on failure. */
 sc_status sc_volume_create(const sc_volume_params* params, sc_volume** out);
 
@@ -137,7 +138,8 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream);
 sc_status sc_volume_query(sc_volume* vol, void* stream, int64_t* n_blocks, int32_t* sticky_error);
 
 /* Copies the first min(n_blocks, cap) allocated blocks, in pool order, into
- * device buffers: block coordinates (int32 x 3), D (float x 512), W (float x
+ * device buffers: block coordinates (int32 x 3), D (float x 512, rounded
+ * to nearest from the FP64 voxel value), W (float x
  * 512) and colour (uint32 RGBA8 x 512, or float x 3 x 512 planar, rounded
  * from the FP64 voxel colour).  Any
  * output may be NULL.  *n_out (host) receives n_blocks.  Synchronises. */

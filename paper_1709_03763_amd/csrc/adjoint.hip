@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64) void backward_kernel(const OpDesc* __restrict__
         float w, z;
         if (!touch(op, v.mu, px, py, pz, pix, w, z)) continue;
         const int i = lane + 64 * kz;
-        const float Wv = blk[512 + i];
+        const float Wv = blk[kPoolW + i];
         if (!(Wv > 0.0f)) continue;
         const float a = w / Wv;
         const float g = gD[b * kBlockVox + i] * a;

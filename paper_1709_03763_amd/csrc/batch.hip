@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, VolDev v, int 
 // Voxel state of one lane: VPL voxels along z of the lane's (x, y) column.
 template <int CM, int VPL>
 struct LaneVox {
-    float D[VPL], W[VPL];
+    double D[VPL];
+    float W[VPL];
     uint32_t C[VPL];       // RGBA8
     double Cf[3][VPL];     // FP32-colour mode (held in FP64)
 };
@@ -162,12 +163,12 @@ __device__ inline void load_vox(LaneVox<CM, VPL>& s, const float* blk, int lane,
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
         const int i = lane + 64 * (kz0 + j);
-        s.D[j] = blk[i];
-        s.W[j] = blk[512 + i];
+        s.D[j] = reinterpret_cast<const double*>(blk)[i];
+        s.W[j] = blk[kPoolW + i];
         if (CM == SC_COLOR_RGBA8) {
-            s.C[j] = reinterpret_cast<const uint32_t*>(blk)[1024 + i];
+            s.C[j] = reinterpret_cast<const uint32_t*>(blk + kPoolC)[i];
         } else {
-            const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+            const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
             s.Cf[0][j] = Cd[i];
             s.Cf[1][j] = Cd[512 + i];
             s.Cf[2][j] = Cd[1024 + i];
@@ -180,7 +181,7 @@ __device__ inline void zero_vox(LaneVox<CM, VPL>& s)
 {
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
-        s.D[j] = 0.0f;
+        s.D[j] = 0.0;
         s.W[j] = 0.0f;
         s.C[j] = 0u;
         s.Cf[0][j] = s.Cf[1][j] = s.Cf[2][j] = 0.0;
@@ -194,12 +195,12 @@ __device__ inline void store_vox(const LaneVox<CM, VPL>& s, float* blk, int lane
     for (int j = 0; j < VPL; ++j) {
         if (!((touched >> j) & 1u)) continue;
         const int i = lane + 64 * (kz0 + j);
-        blk[i] = s.D[j];
-        blk[512 + i] = s.W[j];
+        reinterpret_cast<double*>(blk)[i] = s.D[j];
+        blk[kPoolW + i] = s.W[j];
         if (CM == SC_COLOR_RGBA8) {
-            reinterpret_cast<uint32_t*>(blk)[1024 + i] = s.C[j];
+            reinterpret_cast<uint32_t*>(blk + kPoolC)[i] = s.C[j];
         } else {
-            double* Cd = reinterpret_cast<double*>(blk + 1024);
+            double* Cd = reinterpret_cast<double*>(blk + kPoolC);
             Cd[i] = s.Cf[0][j];
             Cd[512 + i] = s.Cf[1][j];
             Cd[1024 + i] = s.Cf[2][j];
@@ -236,7 +237,7 @@ __device__ inline void apply_op(const OpDesc& op, const VolDev& v, int bx, int b
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
         if (!((h.hit >> j) & 1u)) continue;
-        const float d = distance(h.z[j], bz64 + (double)(kz0 + j) * op.az[2]);
+        const double d = distance(h.z[j], bz64 + (double)(kz0 + j) * op.az[2]);
         if (CM == SC_COLOR_RGBA8) {
             e_weight |= !update_rgba8(s.D[j], s.W[j], s.C[j], d, h.w[j], h.c[j], op.sign);
         } else {
@@ -312,13 +313,13 @@ __global__ __launch_bounds__(256) void batch_main_wave_kernel(const OpDesc* __re
 }
 
 // LDS bytes per wavefront of the compacting voxel pass: block state
-// (D, W f32; colour RGBA8 u32 or 3 x f64) and the queue of one part's
+// (D f64, W f32; colour RGBA8 u32 or 3 x f64) and the queue of one part's
 // touched voxels (voxel u16; quantised weight, keyframe depth, and RGBA8
 // colour or pixel index, 4 bytes each).
 template <int CM, int TV>
 constexpr int compact_wave_bytes()
 {
-    return 512 * (4 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 64 * TV * (2 + 4 + 4 + 4);
+    return 512 * (8 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 64 * TV * (2 + 4 + 4 + 4);
 }
 
 // Orders this wavefront's LDS accesses: the lanes that write a queue entry or
@@ -346,11 +347,11 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     const int lane = threadIdx.x & 63;
     const int wave = (int)bcast(threadIdx.x >> 6);
     unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM, TV>();
-    float* sD = reinterpret_cast<float*>(wb);
-    float* sW = sD + 512;
+    double* sD = reinterpret_cast<double*>(wb);
+    float* sW = reinterpret_cast<float*>(sD + 512);
     uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);  // RGBA8
     double* sCf = reinterpret_cast<double*>(sW + 512);     // FP32 colour: [3][512]
-    float* qw = reinterpret_cast<float*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    float* qw = reinterpret_cast<float*>(wb + 512 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
     float* qz = qw + Q;
     uint32_t* qc = reinterpret_cast<uint32_t*>(qz + Q);  // RGBA8 colour, or pixel index (FP32 colour)
     uint16_t* qvox = reinterpret_cast<uint16_t*>(qc + Q);
@@ -374,12 +375,12 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int x = lane + 64 * j;
-                sD[x] = have ? blk[x] : 0.0f;
-                sW[x] = have ? blk[512 + x] : 0.0f;
+                sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+                sW[x] = have ? blk[kPoolW + x] : 0.0f;
                 if (CM == SC_COLOR_RGBA8) {
-                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk)[1024 + x] : 0u;
+                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
                 } else {
-                    const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
                     sCf[x] = have ? Cd[x] : 0.0;
                     sCf[512 + x] = have ? Cd[512 + x] : 0.0;
                     sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
@@ -439,9 +440,10 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
                             const double pz64 =
                                 ((qz0 + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
                                 (double)(x >> 6) * op.az[2];
-                            const float d = distance(qz[e], pz64);
+                            const double d = distance(qz[e], pz64);
                             const float wq = qw[e];
-                            float D = sD[x], W = sW[x];
+                            double D = sD[x];
+                            float W = sW[x];
                             if (CM == SC_COLOR_RGBA8) {
                                 uint32_t C = sC[x];
                                 e_w |= !update_rgba8(D, W, C, d, wq, qc[e], op.sign);
@@ -471,12 +473,12 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
             for (int j = 0; j < 8; ++j) {
                 if (!((touched >> j) & 1u)) continue;
                 const int x = lane + 64 * j;
-                blk[x] = sD[x];
-                blk[512 + x] = sW[x];
+                reinterpret_cast<double*>(blk)[x] = sD[x];
+                blk[kPoolW + x] = sW[x];
                 if (CM == SC_COLOR_RGBA8) {
-                    reinterpret_cast<uint32_t*>(blk)[1024 + x] = sC[x];
+                    reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = sC[x];
                 } else {
-                    double* Cd = reinterpret_cast<double*>(blk + 1024);
+                    double* Cd = reinterpret_cast<double*>(blk + kPoolC);
                     Cd[x] = sCf[x];
                     Cd[512 + x] = sCf[512 + x];
                     Cd[1024 + x] = sCf[1024 + x];
@@ -529,7 +531,7 @@ struct PipeBlock {
 template <int CM>
 __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v, OpWalk& walk, PipeBlock& pb,
                                  VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, int& op_c, int& part_c, double& qz_c,
-                                 float base_f[3], double& qz_f, int lane, float* sD, float* sW, uint32_t* sC,
+                                 float base_f[3], double& qz_f, int lane, double* sD, float* sW, uint32_t* sC,
                                  double* sCf, float* qw, float* qz, uint32_t* qc, uint16_t* qvox)
 {
     constexpr int TV = 4;
@@ -586,9 +588,10 @@ __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v
                         const double pz64 = ((qz_c + (double)(x & 7) * op.az[0]) +
                                              (double)((x >> 3) & 7) * op.az[1]) +
                                             (double)(x >> 6) * op.az[2];
-                        const float d = distance(qz[e], pz64);
+                        const double d = distance(qz[e], pz64);
                         const float wq = qw[e];
-                        float D = sD[x], W = sW[x];
+                        double D = sD[x];
+                        float W = sW[x];
                         if (CM == SC_COLOR_RGBA8) {
                             uint32_t C = sC[x];
                             pb.e_w |= !update_rgba8(D, W, C, d, wq, qc[e], op.sign);
@@ -629,11 +632,11 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
     const int lane = threadIdx.x & 63;
     const int wave = (int)bcast(threadIdx.x >> 6);
     unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM, TV>();
-    float* sD = reinterpret_cast<float*>(wb);
-    float* sW = sD + 512;
+    double* sD = reinterpret_cast<double*>(wb);
+    float* sW = reinterpret_cast<float*>(sD + 512);
     uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);
     double* sCf = reinterpret_cast<double*>(sW + 512);
-    float* qw = reinterpret_cast<float*>(wb + 512 * (8 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    float* qw = reinterpret_cast<float*>(wb + 512 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
     float* qz = qw + Q;
     uint32_t* qc = reinterpret_cast<uint32_t*>(qz + Q);
     uint16_t* qvox = reinterpret_cast<uint16_t*>(qc + Q);
@@ -661,12 +664,12 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int x = lane + 64 * j;
-                sD[x] = have ? blk[x] : 0.0f;
-                sW[x] = have ? blk[512 + x] : 0.0f;
+                sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+                sW[x] = have ? blk[kPoolW + x] : 0.0f;
                 if (CM == SC_COLOR_RGBA8) {
-                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk)[1024 + x] : 0u;
+                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
                 } else {
-                    const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
                     sCf[x] = have ? Cd[x] : 0.0;
                     sCf[512 + x] = have ? Cd[512 + x] : 0.0;
                     sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
@@ -716,12 +719,12 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
             for (int j = 0; j < 8; ++j) {
                 if (!((pb.touched >> j) & 1u)) continue;
                 const int x = lane + 64 * j;
-                blk[x] = sD[x];
-                blk[512 + x] = sW[x];
+                reinterpret_cast<double*>(blk)[x] = sD[x];
+                blk[kPoolW + x] = sW[x];
                 if (CM == SC_COLOR_RGBA8) {
-                    reinterpret_cast<uint32_t*>(blk)[1024 + x] = sC[x];
+                    reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = sC[x];
                 } else {
-                    double* Cd = reinterpret_cast<double*>(blk + 1024);
+                    double* Cd = reinterpret_cast<double*>(blk + kPoolC);
                     Cd[x] = sCf[x];
                     Cd[512 + x] = sCf[512 + x];
                     Cd[1024 + x] = sCf[1024 + x];

@@ -13,6 +13,12 @@ constexpr uint64_t kKeyEmpty = ~0ull;      // never a packed key (bit 63 is clea
 constexpr float kWeightScale = 1024.0f;    // sample weights live on the 2^-10 grid
 constexpr float kWeightLimit = 16384.0f;   // 2^14: sums stay exact in FP32 below this
 constexpr int kMaxBatchOps = 4096;
+// Block record in the pool, in floats: D as FP64 at [0, 1024) (Eq. (2)
+// amplifies the rounding of a stored D by W / W' when most of a voxel's
+// weight is removed, so D is kept in FP64), W as FP32 at [1024, 1536), and
+// the colour from 1536 (RGBA8 u32 x 512, or FP64 x 3 x 512 planar).
+constexpr int kPoolW = 2 * kBlockVox;
+constexpr int kPoolC = 3 * kBlockVox;
 
 // 21 bits per axis, two's complement, x in the high bits.
 __host__ __device__ inline uint64_t pack_key(int x, int y, int z)
@@ -67,7 +73,7 @@ struct VolDev {
     int32_t* err;          // sticky error word
     uint32_t bucket_mask;
     int32_t max_blocks;
-    int32_t stride;        // floats per block: 1536 (RGBA8) or 4096 (F32 mode, colour as double)
+    int32_t stride;        // floats per block: 2048 (RGBA8) or 4608 (F32 mode, colour as double)
     int32_t color_mode;
     float s;               // voxel size
     float mu;              // truncation

@@ -170,7 +170,7 @@ __device__ inline bool touch(const OpDesc& op, float mu, float px, float py, flo
 }
 
 // Continuous projective distance d = Z*(pixel) - p_z with p_z in FP64.
-__device__ inline float distance(float z, double pz64) { return (float)((double)z - pz64); }
+__device__ inline double distance(float z, double pz64) { return (double)z - pz64; }
 
 // What one lane learns about its VPL voxels (z = kz0 .. kz0 + VPL - 1 of its
 // column) from one operation.
@@ -279,14 +279,16 @@ __device__ inline uint32_t mix_channel(double N, double M, double rM)
 // RGBA8 voxel held in registers; on a weight error the voxel is left as it
 // was and false is returned.  The colour is the exact rational
 // (C Wq +- c wq) / W'q on the 2^-10 weight grid (every product below 2^32,
-// so exact in FP64), rounded half to even.  Branch-free.
-__device__ inline bool update_rgba8(float& D, float& W, uint32_t& C, float d, float w, uint32_t c, int sign)
+// so exact in FP64), rounded half to even.  D is the running mean in FP64:
+// (D W +- d w) / W', both products exact, one rounded sum and one correctly
+// rounded division.  Branch-free.
+__device__ inline bool update_rgba8(double& D, float& W, uint32_t& C, double d, float w, uint32_t c, int sign)
 {
     const float sw = (sign > 0) ? w : -w;
     const float W1 = W + sw;  // exact on the 2^-10 grid
     const bool bad = !(W1 < kWeightLimit) || W1 < 0.0f;
     const bool zero = W1 == 0.0f;
-    const float D1 = (D * W + d * sw) * __builtin_amdgcn_rcpf(W1);
+    const double D1 = (D * (double)W + d * (double)sw) / (double)(zero ? 1.0f : W1);
     const double M = (double)W1 * (double)kWeightScale;
     const double Wq = (double)W * (double)kWeightScale;
     const double swq = (double)sw * (double)kWeightScale;
@@ -299,7 +301,7 @@ __device__ inline bool update_rgba8(float& D, float& W, uint32_t& C, float d, fl
         const double N = (double)((C >> (8 * k)) & 0xFFu) * Wq + (double)((c >> (8 * k)) & 0xFFu) * swq;
         C1 |= mix_channel(N, M, rM) << (8 * k);
     }
-    D = bad ? D : (zero ? 0.0f : D1);
+    D = bad ? D : (zero ? 0.0 : D1);
     C = bad ? C : (zero ? 0u : C1);
     W = bad ? W : (zero ? 0.0f : W1);
     return !bad;
@@ -307,20 +309,19 @@ __device__ inline bool update_rgba8(float& D, float& W, uint32_t& C, float d, fl
 
 // FP32-colour mode: keyframe colour FP32 in [0,1]; the voxel colour is held
 // in FP64, because Eq. (2) amplifies the rounding of the stored colour by
-// W / W' when most of a voxel's weight is removed.
-__device__ inline bool update_f32(float& D, float& W, double C[3], float d, float w, const float c[3], int sign)
+// W / W' when most of a voxel's weight is removed (as for D).
+__device__ inline bool update_f32(double& D, float& W, double C[3], double d, float w, const float c[3], int sign)
 {
     const float W1 = (sign > 0) ? W + w : W - w;
     if (sign > 0 ? !(W1 < kWeightLimit) : (W1 < 0.0f)) return false;
     if (W1 == 0.0f) {
-        D = 0.0f;
+        D = 0.0;
         W = 0.0f;
         C[0] = C[1] = C[2] = 0.0;
         return true;
     }
-    const float rcp = __builtin_amdgcn_rcpf(W1);
-    D = (sign > 0 ? (D * W + d * w) : (D * W - d * w)) * rcp;
     const double Wd = (double)W, wd = (double)w, W1d = (double)W1;
+    D = (sign > 0 ? (D * Wd + d * wd) : (D * Wd - d * wd)) / W1d;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         C[k] = (sign > 0 ? (C[k] * Wd + (double)c[k] * wd) : (C[k] * Wd - (double)c[k] * wd)) / W1d;

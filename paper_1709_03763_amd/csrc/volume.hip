@@ -157,15 +157,17 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
     for (int kz = 0; kz < 8; ++kz) {
         if (!((tmask >> kz) & 1u)) continue;
         const int i = lane + 64 * kz;
-        float D = blk[i], W = blk[512 + i];
-        const float dd = distance(hv.z[kz], bz64 + (double)kz * op.az[2]);
+        double* Dp = reinterpret_cast<double*>(blk);
+        double D = Dp[i];
+        float W = blk[kPoolW + i];
+        const double dd = distance(hv.z[kz], bz64 + (double)kz * op.az[2]);
         if (CM == SC_COLOR_RGBA8) {
-            uint32_t* Cp = reinterpret_cast<uint32_t*>(blk) + 1024;
+            uint32_t* Cp = reinterpret_cast<uint32_t*>(blk + kPoolC);
             uint32_t C = Cp[i];
             bad |= !update_rgba8(D, W, C, dd, hv.w[kz], hv.c[kz], op.sign);
             Cp[i] = C;
         } else {
-            double* Cd = reinterpret_cast<double*>(blk + 1024);
+            double* Cd = reinterpret_cast<double*>(blk + kPoolC);
             double C[3] = {Cd[i], Cd[512 + i], Cd[1024 + i]};
             const float* cp = reinterpret_cast<const float*>(op.color) + 3 * hv.pix[kz];
             const float c[3] = {cp[0], cp[1], cp[2]};
@@ -174,8 +176,8 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
             Cd[512 + i] = C[1];
             Cd[1024 + i] = C[2];
         }
-        blk[i] = D;
-        blk[512 + i] = W;
+        Dp[i] = D;
+        blk[kPoolW + i] = W;
     }
     if (__ballot(bad) != 0) set_error(v.err, SC_EWEIGHT);
 }
@@ -206,13 +208,13 @@ __global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float
     if (b >= n) return;
     const float* blk = v.pool + (size_t)b * v.stride;
     for (int i = threadIdx.x; i < kBlockVox; i += blockDim.x) {
-        if (D) D[b * kBlockVox + i] = blk[i];
-        if (W) W[b * kBlockVox + i] = blk[512 + i];
+        if (D) D[b * kBlockVox + i] = (float)reinterpret_cast<const double*>(blk)[i];
+        if (W) W[b * kBlockVox + i] = blk[kPoolW + i];
         if (C) {
             if (v.color_mode == SC_COLOR_RGBA8) {
-                reinterpret_cast<uint32_t*>(C)[b * kBlockVox + i] = reinterpret_cast<const uint32_t*>(blk)[1024 + i];
+                reinterpret_cast<uint32_t*>(C)[b * kBlockVox + i] = reinterpret_cast<const uint32_t*>(blk + kPoolC)[i];
             } else {
-                const double* Cd = reinterpret_cast<const double*>(blk + 1024);
+                const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
                 float* Cf = reinterpret_cast<float*>(C) + b * 3 * kBlockVox;
                 Cf[i] = (float)Cd[i];
                 Cf[512 + i] = (float)Cd[512 + i];
@@ -351,7 +353,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     VolDev& d = vol->dev;
     d.bucket_mask = (uint32_t)(p->n_buckets - 1);
     d.max_blocks = (int32_t)p->max_blocks;
-    d.stride = (p->color_mode == SC_COLOR_RGBA8) ? 3 * kBlockVox : 8 * kBlockVox;
+    d.stride = (p->color_mode == SC_COLOR_RGBA8) ? 4 * kBlockVox : 9 * kBlockVox;
     d.color_mode = p->color_mode;
     d.s = p->voxel_size;
     d.mu = p->trunc;
