@@ -495,151 +495,238 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     stat_add(cd, 3, worker, n_written, lane);
 }
 
-// Per-block operation walk of the pipelined pass: the operations of a block
-// in bit order, read word by word from its mask.
+// LDS bytes per wavefront of the pipelined pass: the state of one part of
+// the block (four z-slices, 256 voxels: D f64, W f32, colour RGBA8 u32 or
+// 3 x f64) and the queue of one (operation, part) step's touched voxels.
+template <int CM>
+constexpr int pipe_wave_bytes()
+{
+    return 256 * (8 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 256 * (2 + 4 + 4 + 4);
+}
+
+// Per-wavefront LDS of the pipelined pass.
+struct PipeLds {
+    double* sD;      // [256]
+    float* sW;       // [256]
+    uint32_t* sC;    // [256] RGBA8
+    double* sCf;     // [3][256] FP32-colour mode
+    float* qw;       // queue: quantised weight,
+    float* qz;       // keyframe depth,
+    uint32_t* qc;    // RGBA8 colour or pixel index (FP32 colour),
+    uint16_t* qvox;  // voxel index in the block
+};
+
+template <int CM>
+__device__ inline PipeLds pipe_lds(unsigned char* wb)
+{
+    PipeLds L;
+    L.sD = reinterpret_cast<double*>(wb);
+    L.sW = reinterpret_cast<float*>(L.sD + 256);
+    L.sC = reinterpret_cast<uint32_t*>(L.sW + 256);
+    L.sCf = reinterpret_cast<double*>(L.sW + 256);
+    L.qw = reinterpret_cast<float*>(wb + 256 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    L.qz = L.qw + 256;
+    L.qc = reinterpret_cast<uint32_t*>(L.qz + 256);
+    L.qvox = reinterpret_cast<uint16_t*>(L.qc + 256);
+    return L;
+}
+
+// Operations of a block in bit order, read word by word from its mask; the
+// walk runs once per part.
 struct OpWalk {
     const uint64_t* mask;
     int words, w;
     uint64_t m;
-    uint32_t pairs;
 };
+
+__device__ inline void walk_start(OpWalk& k)
+{
+    k.w = 0;
+    k.m = bcast64(k.mask[0]);
+}
 
 __device__ inline int walk_next(OpWalk& k)
 {
     while (k.m == 0ull) {
         if (++k.w >= k.words) return -1;
         k.m = bcast64(k.mask[k.w]);
-        k.pairs += (uint32_t)__popcll(k.m);
     }
     const int b = __ffsll((unsigned long long)k.m) - 1;
     k.m &= k.m - 1;
     return k.w * 64 + b;
 }
 
-// State of the pipelined pass within one block.
+// State of the pipelined pass within one block.  slot0 is the block's pool
+// slot before the pass (-1: not allocated), slot its current one.
 struct PipeBlock {
-    int bx, by, bz, slot, skip_op;
-    uint32_t touched, n_upd;
+    int bx, by, bz, slot0, slot;
+    uint32_t touched, n_upd, pairs;
     bool re_touch, e_na, e_w;
 };
 
+// Loads the state of part `part` (z-slices 4 part .. 4 part + 3) into LDS;
+// zeros for a block that did not exist before the pass.
+template <int CM>
+__device__ inline void pipe_load(const VolDev& v, int slot0, int part, int lane, const PipeLds& L)
+{
+    const float* blk = v.pool + (size_t)max(slot0, 0) * v.stride;
+    const bool have = slot0 >= 0;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const int xl = lane + 64 * j, x = xl + 256 * part;
+        L.sD[xl] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+        L.sW[xl] = have ? blk[kPoolW + x] : 0.0f;
+        if (CM == SC_COLOR_RGBA8) {
+            L.sC[xl] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
+        } else {
+            const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
+            L.sCf[xl] = have ? Cd[x] : 0.0;
+            L.sCf[256 + xl] = have ? Cd[512 + x] : 0.0;
+            L.sCf[512 + xl] = have ? Cd[1024 + x] : 0.0;
+        }
+    }
+}
+
+// Ends a part: allocates the block once a re-integration has touched it
+// (all lanes, uniform branch) and writes the part's touched slices back.
+template <int CM>
+__device__ inline void pipe_store(const VolDev& v, uint64_t key, PipeBlock& pb, int part, int lane, const PipeLds& L)
+{
+    if (pb.slot < 0 && __ballot(pb.re_touch) != 0ull) pb.slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
+    if (pb.slot < 0) return;
+    float* blk = v.pool + (size_t)pb.slot * v.stride;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        if (!((pb.touched >> (4 * part + j)) & 1u)) continue;
+        const int xl = lane + 64 * j, x = xl + 256 * part;
+        reinterpret_cast<double*>(blk)[x] = L.sD[xl];
+        blk[kPoolW + x] = L.sW[xl];
+        if (CM == SC_COLOR_RGBA8) {
+            reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = L.sC[xl];
+        } else {
+            double* Cd = reinterpret_cast<double*>(blk + kPoolC);
+            Cd[x] = L.sCf[xl];
+            Cd[512 + x] = L.sCf[256 + xl];
+            Cd[1024 + x] = L.sCf[512 + xl];
+        }
+    }
+}
+
+// Issues the keyframe gathers of (operation `o`, part `part`) into `f` and
+// returns the camera z of the block origin for it in `qz`.
+template <int CM>
+__device__ inline void pipe_fetch(const OpDesc& o, const VolDev& v, const PipeBlock& pb, int part, int lane,
+                                  VoxFetch<CM, 4>& f, double& qz)
+{
+    float q[3], base[3];
+    block_origin(o, v.s, pb.bx, pb.by, pb.bz, q, qz);
+    const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) base[r] = (q[r] + kx * o.a[0][r]) + ky * o.a[1][r];
+    fetch_voxels<CM, 4, true>(o, base, part * 4, f);
+}
+
 // One step of the pipelined pass: issue the keyframe gathers of the next
 // (operation, part) into `nxt`, then decide, gather into the queue and update
-// the current one from `cur`.  The dense phase reads only LDS, so the loads
-// of `nxt` stay in flight while the current part is processed.  Returns
-// false when the block has no further step.
+// the current one from `cur`.  Steps run part by part (every operation of
+// the block on part 0, then on part 1), so each voxel still sees the
+// operations in bit order.  The dense phase reads only LDS, so the loads of
+// `nxt` stay in flight while the current step is processed.  Returns false
+// when the block has no further step; otherwise op_c / part_c / qz_c name
+// the next step.
 template <int CM>
 __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v, OpWalk& walk, PipeBlock& pb,
                                  VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, int& op_c, int& part_c, double& qz_c,
-                                 float base_f[3], double& qz_f, int lane, double* sD, float* sW, uint32_t* sC,
-                                 double* sCf, float* qw, float* qz, uint32_t* qc, uint16_t* qvox)
+                                 int lane, const PipeLds& L)
 {
     constexpr int TV = 4;
-    int op_n, part_n;
-    if (part_c == 0) {
-        op_n = op_c;
-        part_n = 1;
-    } else {
+    int op_n = walk_next(walk), part_n = part_c;
+    if (op_n < 0 && part_c == 0) {
+        walk_start(walk);
         op_n = walk_next(walk);
-        part_n = 0;
+        part_n = 1;
     }
-    if (op_n >= 0) {
-        const OpDesc& on = ops[op_n];
-        if (part_n == 0) {
-            float q[3];
-            block_origin(on, v.s, pb.bx, pb.by, pb.bz, q, qz_f);
-            const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
-#pragma unroll
-            for (int r = 0; r < 3; ++r) base_f[r] = (q[r] + kx * on.a[0][r]) + ky * on.a[1][r];
-        }
-        fetch_voxels<CM, TV, true>(on, base_f, part_n * TV, nxt);
-    }
+    double qz_n = 0.0;
+    if (op_n >= 0) pipe_fetch<CM>(ops[op_n], v, pb, part_n, lane, nxt, qz_n);
     const OpDesc& op = ops[op_c];
-    if (op_c != pb.skip_op) {
-        VoxHits<CM, TV> hv;
-        decide_voxels<CM, TV>(cur, v.mu, hv);
-        uint32_t cnt = 0u;
+    pb.pairs += (part_c == 0) ? 1u : 0u;
+    VoxHits<CM, TV> hv;
+    decide_voxels<CM, TV>(cur, v.mu, hv);
+    uint32_t cnt = 0u;
 #pragma unroll
-        for (int j = 0; j < TV; ++j) {
-            const bool t = (hv.hit >> j) & 1u;
-            const uint64_t bal = __ballot(t);
-            if (t) {
-                const uint32_t pos = cnt + lanes_below(bal);
-                qvox[pos] = (uint16_t)(lane + 64 * (part_c * TV + j));
-                qw[pos] = hv.w[j];
-                qz[pos] = hv.z[j];
-                qc[pos] = (CM == SC_COLOR_RGBA8) ? hv.c[j] : (uint32_t)hv.pix[j];
-            }
-            cnt += (uint32_t)__popcll(bal);
+    for (int j = 0; j < TV; ++j) {
+        const bool t = (hv.hit >> j) & 1u;
+        const uint64_t bal = __ballot(t);
+        if (t) {
+            const uint32_t pos = cnt + lanes_below(bal);
+            L.qvox[pos] = (uint16_t)(lane + 64 * (part_c * TV + j));
+            L.qw[pos] = hv.w[j];
+            L.qz[pos] = hv.z[j];
+            L.qc[pos] = (CM == SC_COLOR_RGBA8) ? hv.c[j] : (uint32_t)hv.pix[j];
         }
-        if (cnt != 0u) {
-            if (op.sign < 0 && pb.slot < 0) {
-                pb.e_na = true;
-                pb.skip_op = op_c;
-            } else {
-                if (op.sign > 0) pb.re_touch = true;
-                pb.touched |= hv.hit << (part_c * TV);
-                pb.n_upd += __popc(hv.hit);
-                wave_lds_sync();
-                for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
-                    const uint32_t e = r0 + (uint32_t)lane;
-                    if (e < cnt) {
-                        const int x = qvox[e];
-                        const double pz64 = ((qz_c + (double)(x & 7) * op.az[0]) +
-                                             (double)((x >> 3) & 7) * op.az[1]) +
-                                            (double)(x >> 6) * op.az[2];
-                        const double d = distance(qz[e], pz64);
-                        const float wq = qw[e];
-                        double D = sD[x];
-                        float W = sW[x];
-                        if (CM == SC_COLOR_RGBA8) {
-                            uint32_t C = sC[x];
-                            pb.e_w |= !update_rgba8(D, W, C, d, wq, qc[e], op.sign);
-                            sC[x] = C;
-                        } else {
-                            const float* cp = reinterpret_cast<const float*>(op.color) + 3 * (size_t)qc[e];
-                            const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
-                            double C3[3] = {sCf[x], sCf[512 + x], sCf[1024 + x]};
-                            pb.e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
-                            sCf[x] = C3[0];
-                            sCf[512 + x] = C3[1];
-                            sCf[1024 + x] = C3[2];
-                        }
-                        sD[x] = D;
-                        sW[x] = W;
+        cnt += (uint32_t)__popcll(bal);
+    }
+    if (cnt != 0u) {
+        if (op.sign < 0 && pb.slot0 < 0) {
+            pb.e_na = true;
+        } else {
+            if (op.sign > 0) pb.re_touch = true;
+            pb.touched |= hv.hit << (part_c * TV);
+            pb.n_upd += __popc(hv.hit);
+            wave_lds_sync();
+            for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+                const uint32_t e = r0 + (uint32_t)lane;
+                if (e < cnt) {
+                    const int x = L.qvox[e];
+                    const int xl = x & 255;
+                    const double pz64 =
+                        ((qz_c + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
+                        (double)(x >> 6) * op.az[2];
+                    const double d = distance(L.qz[e], pz64);
+                    const float wq = L.qw[e];
+                    double D = L.sD[xl];
+                    float W = L.sW[xl];
+                    if (CM == SC_COLOR_RGBA8) {
+                        uint32_t C = L.sC[xl];
+                        pb.e_w |= !update_rgba8(D, W, C, d, wq, L.qc[e], op.sign);
+                        L.sC[xl] = C;
+                    } else {
+                        const float* cp = reinterpret_cast<const float*>(op.color) + 3 * (size_t)L.qc[e];
+                        const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
+                        double C3[3] = {L.sCf[xl], L.sCf[256 + xl], L.sCf[512 + xl]};
+                        pb.e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
+                        L.sCf[xl] = C3[0];
+                        L.sCf[256 + xl] = C3[1];
+                        L.sCf[512 + xl] = C3[2];
                     }
+                    L.sD[xl] = D;
+                    L.sW[xl] = W;
                 }
-                wave_lds_sync();
             }
+            wave_lds_sync();
         }
     }
     if (op_n < 0) return false;
-    if (part_n == 0) qz_c = qz_f;
     op_c = op_n;
     part_c = part_n;
+    qz_c = qz_n;
     return true;
 }
 
-// Persistent voxel pass, compacting and pipelined: the compacting pass (four
-// voxels per lane per part, LDS queue carrying the keyframe samples) with the
-// gathers of each (operation, part) issued one step ahead, through two
-// fetch buffers used alternately.
+// Persistent voxel pass, compacting and pipelined: one wavefront per block,
+// the block handled in two parts of four z-slices with only the current
+// part's state in LDS; per (operation, part) the touched voxels are gathered
+// into an LDS queue with their keyframe samples and updated densely, and the
+// gathers of each step are issued one step ahead through two fetch buffers
+// used alternately.
 template <int CM>
 __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
 {
-    constexpr int TV = 4, Q = 64 * TV;
+    constexpr int TV = 4;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = (int)bcast(threadIdx.x >> 6);
-    unsigned char* wb = smem + (size_t)wave * compact_wave_bytes<CM, TV>();
-    double* sD = reinterpret_cast<double*>(wb);
-    float* sW = reinterpret_cast<float*>(sD + 512);
-    uint32_t* sC = reinterpret_cast<uint32_t*>(sW + 512);
-    double* sCf = reinterpret_cast<double*>(sW + 512);
-    float* qw = reinterpret_cast<float*>(wb + 512 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
-    float* qz = qw + Q;
-    uint32_t* qc = reinterpret_cast<uint32_t*>(qz + Q);
-    uint16_t* qvox = reinterpret_cast<uint16_t*>(qc + Q);
+    const PipeLds L = pipe_lds<CM>(smem + (size_t)wave * pipe_wave_bytes<CM>());
     const uint32_t n = cd.counters[4];
     const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
     const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
@@ -652,87 +739,48 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
         const uint32_t h = bcast(cd.sorted[i]);
         const uint64_t key = bcast64(cd.skey[i]);
         PipeBlock pb;
-        pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
+        pb.slot0 = pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
         unpack_key(key, pb.bx, pb.by, pb.bz);
-        pb.skip_op = -1;
-        pb.touched = 0u;
-        pb.n_upd = 0u;
+        pb.touched = pb.n_upd = pb.pairs = 0u;
         pb.re_touch = pb.e_na = pb.e_w = false;
-        {
-            const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
-            const bool have = pb.slot >= 0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int x = lane + 64 * j;
-                sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
-                sW[x] = have ? blk[kPoolW + x] : 0.0f;
-                if (CM == SC_COLOR_RGBA8) {
-                    sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
-                } else {
-                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
-                    sCf[x] = have ? Cd[x] : 0.0;
-                    sCf[512 + x] = have ? Cd[512 + x] : 0.0;
-                    sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
-                }
-            }
-        }
-        wave_lds_sync();
         OpWalk walk;
         walk.mask = cd.mask + (size_t)h * cd.words;
         walk.words = cd.words;
-        walk.w = 0;
-        walk.m = bcast64(walk.mask[0]);
-        walk.pairs = (uint32_t)__popcll(walk.m);
+        walk_start(walk);
         int op_c = walk_next(walk);
         if (op_c >= 0) {
             VoxFetch<CM, TV> f0, f1;
             int part_c = 0;
-            double qz_c, qz_f;
-            float base_f[3];
-            {
-                const OpDesc& o0 = ops[op_c];
-                float q[3];
-                block_origin(o0, v.s, pb.bx, pb.by, pb.bz, q, qz_f);
-                const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
-#pragma unroll
-                for (int r = 0; r < 3; ++r) base_f[r] = (q[r] + kx * o0.a[0][r]) + ky * o0.a[1][r];
-                fetch_voxels<CM, TV, true>(o0, base_f, 0, f0);
-                qz_c = qz_f;
-            }
+            double qz_c;
+            pipe_fetch<CM>(ops[op_c], v, pb, 0, lane, f0, qz_c);
+            pipe_load<CM>(v, pb.slot0, 0, lane, L);
+            wave_lds_sync();
+            bool second = false;
             for (;;) {
-                if (!pipe_step<CM>(ops, v, walk, pb, f0, f1, op_c, part_c, qz_c, base_f, qz_f, lane, sD, sW, sC, sCf,
-                                   qw, qz, qc, qvox))
-                    break;
-                if (!pipe_step<CM>(ops, v, walk, pb, f1, f0, op_c, part_c, qz_c, base_f, qz_f, lane, sD, sW, sC, sCf,
-                                   qw, qz, qc, qvox))
-                    break;
-            }
-        }
-        n_pairs += walk.pairs;
-        n_upd += pb.n_upd;
-        const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
-        int slot = pb.slot;
-        if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
-        if (slot >= 0) {
-            float* blk = v.pool + (size_t)slot * v.stride;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (!((pb.touched >> j) & 1u)) continue;
-                const int x = lane + 64 * j;
-                reinterpret_cast<double*>(blk)[x] = sD[x];
-                blk[kPoolW + x] = sW[x];
-                if (CM == SC_COLOR_RGBA8) {
-                    reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = sC[x];
-                } else {
-                    double* Cd = reinterpret_cast<double*>(blk + kPoolC);
-                    Cd[x] = sCf[x];
-                    Cd[512 + x] = sCf[512 + x];
-                    Cd[1024 + x] = sCf[1024 + x];
+                if (!pipe_step<CM>(ops, v, walk, pb, f0, f1, op_c, part_c, qz_c, lane, L)) break;
+                if (part_c == 1 && !second) {
+                    pipe_store<CM>(v, key, pb, 0, lane, L);
+                    wave_lds_sync();
+                    pipe_load<CM>(v, pb.slot0, 1, lane, L);
+                    wave_lds_sync();
+                    second = true;
+                }
+                if (!pipe_step<CM>(ops, v, walk, pb, f1, f0, op_c, part_c, qz_c, lane, L)) break;
+                if (part_c == 1 && !second) {
+                    pipe_store<CM>(v, key, pb, 0, lane, L);
+                    wave_lds_sync();
+                    pipe_load<CM>(v, pb.slot0, 1, lane, L);
+                    wave_lds_sync();
+                    second = true;
                 }
             }
+            pipe_store<CM>(v, key, pb, 1, lane, L);
         }
+        n_pairs += pb.pairs;
+        n_upd += pb.n_upd;
+        const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
         const bool wrote = __ballot(pb.touched != 0) != 0;
-        n_written += (slot >= 0 && wrote) ? 1u : 0u;
+        n_written += (pb.slot >= 0 && wrote) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
         wave_lds_sync();
     }
@@ -851,10 +899,10 @@ static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_
         const size_t w = sch.waves_per_wg;
         if (sch.compact == 3) {
             if (rgba)
-                batch_pipe_kernel<SC_COLOR_RGBA8><<<grid, threads, w * compact_wave_bytes<SC_COLOR_RGBA8, 4>(), s>>>(
+                batch_pipe_kernel<SC_COLOR_RGBA8><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_RGBA8>(), s>>>(
                     vol->d_ops, vol->dev, vol->cand);
             else
-                batch_pipe_kernel<SC_COLOR_F32><<<grid, threads, w * compact_wave_bytes<SC_COLOR_F32, 4>(), s>>>(
+                batch_pipe_kernel<SC_COLOR_F32><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_F32>(), s>>>(
                     vol->d_ops, vol->dev, vol->cand);
         } else if (sch.compact == 1) {
             if (rgba)
@@ -1026,8 +1074,9 @@ static bool schedule_fits(const sc_volume* vol, const sc_schedule& s)
     if (!schedule_ok(s)) return false;
     if (!s.compact) return true;
     const bool rgba = vol->p.color_mode == SC_COLOR_RGBA8;
-    const int per = (s.compact == 1) ? (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 8>() : compact_wave_bytes<SC_COLOR_F32, 8>())
-                                     : (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 4>() : compact_wave_bytes<SC_COLOR_F32, 4>());
+    const int per = (s.compact == 1)   ? (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 8>() : compact_wave_bytes<SC_COLOR_F32, 8>())
+                    : (s.compact == 2) ? (rgba ? compact_wave_bytes<SC_COLOR_RGBA8, 4>() : compact_wave_bytes<SC_COLOR_F32, 4>())
+                                       : (rgba ? pipe_wave_bytes<SC_COLOR_RGBA8>() : pipe_wave_bytes<SC_COLOR_F32>());
     return s.waves_per_wg * per <= 65536;
 }
 

@@ -280,21 +280,22 @@ __device__ inline uint32_t mix_channel(double N, double M, double rM)
 // was and false is returned.  The colour is the exact rational
 // (C Wq +- c wq) / W'q on the 2^-10 weight grid (every product below 2^32,
 // so exact in FP64), rounded half to even.  D is the running mean in FP64:
-// (D W +- d w) / W', both products exact, one rounded sum and one correctly
-// rounded division.  Branch-free.
+// (D W +- d w) times the refined reciprocal of W' (the colour's reciprocal
+// of W' 2^10, rescaled exactly), within two FP64 ulps of the quotient.
+// Branch-free.
 __device__ inline bool update_rgba8(double& D, float& W, uint32_t& C, double d, float w, uint32_t c, int sign)
 {
     const float sw = (sign > 0) ? w : -w;
     const float W1 = W + sw;  // exact on the 2^-10 grid
     const bool bad = !(W1 < kWeightLimit) || W1 < 0.0f;
     const bool zero = W1 == 0.0f;
-    const double D1 = (D * (double)W + d * (double)sw) / (double)(zero ? 1.0f : W1);
     const double M = (double)W1 * (double)kWeightScale;
     const double Wq = (double)W * (double)kWeightScale;
     const double swq = (double)sw * (double)kWeightScale;
     double rM = __builtin_amdgcn_rcp(M);
     rM = fma(rM, fma(-M, rM, 1.0), rM);
     rM = fma(rM, fma(-M, rM, 1.0), rM);
+    const double D1 = (D * (double)W + d * (double)sw) * (rM * (double)kWeightScale);
     uint32_t C1 = 0u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
