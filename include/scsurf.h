@@ -304,6 +304,52 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
                                   const sc_pose* T, const float* grad_D, const float* grad_C, float* grad_depth,
                                   float* grad_color, float* grad_xi, void* stream);
 
+/* ---- iso-surface and surface metrics (Sec. 3; Sec. 5 evaluation) -------- */
+
+/* Marching Cubes over the volume (Sec. 3 "SDF volume": the iso-surface of
+ * D = 0 is extracted with Marching Cubes).  The cube of voxel n has corners
+ * n + {0,1}^3 and is meshed only when all eight corner voxels are allocated
+ * with W > 0; a corner is inside when D < 0.  The vertex on a crossing edge
+ * from voxel p to p + e_a is s (p + t e_a), t = D(p) / (D(p) - D(p + e_a)),
+ * in FP64 from the FP64 voxel D, rounded to FP32.  Triangulation: on each
+ * cube face the runs of inside corners are cut off one by one (diagonal
+ * inside corners stay apart), the face segments chain into loops, a loop is
+ * fanned from its smallest edge, or from an added centre vertex (the mean of
+ * its vertices) when it crosses one face twice; triangles face increasing D,
+ * and the mesh is closed wherever all cubes around it are meshed.
+ * Outputs (device, may be NULL): tri_xyz cap x 3 x 3 FP32 vertex positions
+ * (metres, world frame), tri_keys cap x 3 x 4 int32 vertex keys (x, y, z, k):
+ * k < 3 the edge along axis k from voxel (x, y, z), k = 3 + j the centre of
+ * loop j in the cube of voxel (x, y, z).  Triangles come in no fixed order;
+ * the first min(count, cap) are written and *n_tri (host) receives the
+ * count, so a call with cap = 0 sizes the buffers.  Synchronises. */
+sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* tri_keys, int64_t cap,
+                         int64_t* n_tri);
+
+/* The mesh's vertices, one per key (Sec. 5 measures distances between mesh
+ * vertices): tri_xyz / tri_keys as written by sc_volume_mesh (device, n_tri
+ * triangles); vert_xyz (device, cap x 3 FP32) receives the first
+ * min(count, cap) distinct vertices in no fixed order, *n_vert (host) the
+ * count.  SC_ERANGE if a voxel coordinate is outside [-2^19, 2^19).
+ * Allocates a temporary hash set; synchronises. */
+sc_status sc_mesh_vertices(const float* tri_xyz, const int32_t* tri_keys, int64_t n_tri, float* vert_xyz, int64_t cap,
+                           int64_t* n_vert, void* stream);
+
+/* Capped nearest-neighbour distances (Sec. 5 "Surface evaluation methods and
+ * metrics": CORR is the mean over the mesh vertices of the distance to the
+ * nearest reference point, COMPL the mean over the reference of the distance
+ * to the nearest mesh vertex).  For every query point (device, n_query x 3
+ * FP32) the Euclidean distance to the nearest point of ref (device, n_ref x
+ * 3 FP32), computed in FP32 as sqrt((dx^2 + dy^2) + dz^2), capped at radius
+ * (a query with no reference point within the radius, or an empty ref, gets
+ * the radius).  dist (device, n_query FP32) may be NULL; sum (device, one
+ * FP64) receives the sum of the distances when not NULL.  Exact search over a
+ * uniform grid of cells slightly larger than the radius, valid while
+ * |coordinate| / radius < 10^5.  SC_EINVAL for a radius that is not positive
+ * and finite.  Allocates temporaries; synchronises. */
+sc_status sc_nn_distance(const float* ref, int64_t n_ref, const float* query, int64_t n_query, float radius,
+                         float* dist, double* sum, void* stream);
+
 /* Library version string. */
 const char* sc_version(void);
 

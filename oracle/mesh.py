@@ -142,9 +142,23 @@ LOOPS = [case_loops(c) for c in range(256)]
 TABLE = [case_triangles(c) for c in range(256)]
 
 
-def _lookup(blocks):
-    keys = {tuple(b): i for i, b in enumerate(np.asarray(blocks, np.int64).tolist())}
-    return keys
+def _block_key(b):
+    b = np.asarray(b, np.int64) + (1 << 20)
+    return (b[..., 0] << 42) | (b[..., 1] << 21) | b[..., 2]
+
+
+def _block_finder(blocks):
+    """Index of each queried block coordinate in `blocks`, or -1."""
+    key = _block_key(blocks)
+    order = np.argsort(key)
+    sk = key[order]
+
+    def find(b):
+        k = _block_key(b)
+        pos = np.minimum(np.searchsorted(sk, k), len(sk) - 1)
+        return np.where(sk[pos] == k, order[pos], -1)
+
+    return find
 
 
 def marching_cubes(field, voxel_size):
@@ -160,7 +174,7 @@ def marching_cubes(field, voxel_size):
     s = float(np.float32(voxel_size))
     if n == 0:
         return np.zeros((0, 3, 3)), np.zeros((0, 3, 4), np.int64)
-    index = _lookup(blocks)
+    find = _block_finder(blocks)
     i = np.arange(512)
     local = np.stack([i & 7, (i >> 3) & 7, i >> 6], 1)
     # every voxel of every block anchors one cube
@@ -171,7 +185,7 @@ def marching_cubes(field, voxel_size):
         c = vox + CORNER_OFF[k]
         b = np.floor_divide(c, 8)
         l = c - 8 * b
-        bi = np.array([index.get(tuple(x), -1) for x in b.tolist()])
+        bi = find(b)
         li = l[:, 0] + 8 * l[:, 1] + 64 * l[:, 2]
         have = bi >= 0
         w = np.where(have, W[np.maximum(bi, 0), li], 0.0)

@@ -66,7 +66,8 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
-           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap"]
+           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
+           "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance"]
 
 _lib = None
 
@@ -110,6 +111,9 @@ def lib():
     L.sc_keyframe_pack.argtypes = [ctypes.POINTER(sc_keyframe), i32, i32, P, P]
     L.sc_overlap.argtypes = [P, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose),
                              ctypes.c_float, ctypes.c_float, P, P]
+    L.sc_volume_mesh.argtypes = [P, P, P, P, i64, ctypes.POINTER(i64)]
+    L.sc_mesh_vertices.argtypes = [P, P, i64, P, i64, ctypes.POINTER(i64), P]
+    L.sc_nn_distance.argtypes = [P, i64, P, i64, ctypes.c_float, P, P, P]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:
@@ -270,6 +274,21 @@ class Volume:
         check(lib().sc_volume_export(self._h, stream_handle(stream), xyz.data_ptr(), D.data_ptr(), W.data_ptr(),
                                      C.data_ptr(), n, ctypes.byref(nout)), "sc_volume_export")
         return {"blocks": xyz[:n], "D": D[:n], "W": W[:n], "C": C[:n]}
+
+    def mesh(self, stream=None):
+        """Marching Cubes of the volume: (tri_xyz (T,3,3) f32, tri_keys
+        (T,3,4) int32) device tensors, triangles in no fixed order."""
+        n = ctypes.c_int64()
+        check(lib().sc_volume_mesh(self._h, stream_handle(stream), None, None, 0, ctypes.byref(n)), "sc_volume_mesh")
+        T = n.value
+        dev = torch.device("cuda")
+        xyz = torch.empty((max(T, 1), 3, 3), dtype=torch.float32, device=dev)
+        keys = torch.empty((max(T, 1), 3, 4), dtype=torch.int32, device=dev)
+        check(lib().sc_volume_mesh(self._h, stream_handle(stream), xyz.data_ptr(), keys.data_ptr(), T,
+                                   ctypes.byref(n)), "sc_volume_mesh")
+        if n.value != T:
+            raise ScError(SC_EDEVICE, "sc_volume_mesh: triangle count changed between calls")
+        return xyz[:T], keys[:T]
 
     def export_sorted(self, stream=None):
         """Allocated blocks sorted by (x, y, z) as NumPy arrays; colour as

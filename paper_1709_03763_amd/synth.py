@@ -552,6 +552,48 @@ def loop_closure_updates(R, t, n_updates, seed, n_range=(50, 300), rho_max=0.10,
 # ----------------------------------------------------------------------------
 
 
+def _box_face_samples(rng, lo, hi, n):
+    """n points uniform on the surface of the box [lo, hi] (area-weighted faces)."""
+    ext = hi - lo
+    areas = np.array([ext[1] * ext[2], ext[0] * ext[2], ext[0] * ext[1]] * 2)
+    face = rng.choice(6, n, p=areas / areas.sum())
+    u = rng.random((n, 3))
+    pts = lo + u * ext
+    axis = face % 3
+    pts[np.arange(n), axis] = np.where(face < 3, lo[axis], hi[axis])
+    return pts
+
+
+def surface_points(scene: Scene, n: int, seed: int) -> np.ndarray:
+    """About n points uniform over the scene's visible geometry (the room's
+    inner walls and the primitives' surfaces, area-weighted), keeping those
+    on the boundary of free space: a stand-in for a reference cloud sampled
+    from the ground-truth mesh."""
+    rng = np.random.default_rng(seed)
+    lo, hi = scene.room_lo, scene.room_hi
+    ext = hi - lo
+    parts = [("room", 2 * (ext[0] * ext[1] + ext[0] * ext[2] + ext[1] * ext[2]), None)]
+    parts += [("sph", 4 * np.pi * sp[3] ** 2, sp) for sp in scene.spheres]
+    parts += [("box", 2 * ((b[3] - b[0]) * (b[4] - b[1]) + (b[3] - b[0]) * (b[5] - b[2]) + (b[4] - b[1]) * (b[5] - b[2])),
+               b) for b in scene.boxes]
+    area = np.array([p[1] for p in parts])
+    counts = rng.multinomial(n, area / area.sum())
+    out = []
+    for (kind, _, prm), k in zip(parts, counts):
+        if k == 0:
+            continue
+        if kind == "room":
+            out.append(_box_face_samples(rng, lo, hi, k))
+        elif kind == "sph":
+            v = rng.normal(size=(k, 3))
+            out.append(prm[:3] + prm[3] * v / np.linalg.norm(v, axis=1, keepdims=True))
+        else:
+            out.append(_box_face_samples(rng, prm[:3], prm[3:], k))
+    pts = np.concatenate(out)
+    keep = np.abs(scene_sdf(scene, pts)) < 1e-6
+    return pts[keep].astype(np.float32)
+
+
 def scene_sdf(scene: Scene, x: np.ndarray) -> np.ndarray:
     """Signed Euclidean distance, positive in free space, for points (N,3)."""
     x = np.asarray(x, float)
