@@ -5,7 +5,7 @@ Workload (the batched re-integration configuration): a 10 x 10 x 3 m room
 with 40 seeded boxes and spheres, 1000 synthetic 640x480 RGB-D frames fused
 5 per keyframe into 200 keyframes (kf_fuse), each keyframe cut to a seeded
 valid-pixel fraction in [0.4, 1.0] by a contiguous column strip, integrated
-into a voxel-hashed TSDF (1 cm voxels, 4 cm truncation, 2^21 buckets, FP32
+into a voxel-hashed TSDF (1 cm voxels, 4 cm truncation, 2^21 buckets, FP64
 TSDF + RGBA8 colour + FP32 weight).  A pose-graph update moves all 200 poses
 by N(0, 3 cm / 1.5 deg); one step re-integrates every changed keyframe in
 order of pose change (de-integrate at the integration pose, re-integrate at
@@ -202,6 +202,80 @@ def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20):
             "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1)}
 
 
+def mesh_stage(torch, scsurf, surface, synth, vol, wl):
+    """Marching Cubes of the benchmark volume, its distinct vertices, and CORR
+    against a dense reference cloud of the scene (wall-clock of each call,
+    which synchronises)."""
+    n_blocks, _ = vol.query()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    vol.mesh()  # warm-up (table upload)
+    (xyz, keys), mesh_s = timed(vol.mesh)
+    verts, vert_s = timed(lambda: surface.mesh_vertices(xyz, keys))
+    ref = torch.from_numpy(synth.surface_points(wl.scene, 4_000_000, 7)).cuda()
+    corr, corr_s = timed(lambda: surface.corr(verts, ref, 0.05))
+    n_tri = int(xyz.shape[0])
+    # one 9^3 halo of D (8 B) and W (4 B) read per block, triangles written (36 B positions + 48 B keys);
+    # the call meshes twice (count, then fill)
+    mesh_bytes = n_blocks * 729 * 12 * 2 + n_tri * (36 + 48)
+    return {"blocks": int(n_blocks), "triangles": n_tri, "vertices": int(verts.shape[0]),
+            "mesh_ms": round(mesh_s * 1e3, 3), "triangles_per_s": round(n_tri / mesh_s, 1),
+            "mesh_hbm_frac": round(mesh_bytes / mesh_s / 1e9 / HBM_PEAK_GBS, 5),
+            "vertices_ms": round(vert_s * 1e3, 3), "reference_points": int(ref.shape[0]),
+            "corr_ms": round(corr_s * 1e3, 3), "corr_mm": round(corr * 1e3, 4)}
+
+
+def surface_stage(torch, scsurf, surface, online, synth, log):
+    """Synthetic analogue of the keyframe-strategy study of Sec. 5 (Fig. 5):
+    the 4 x 4 x 3 m room scanned in 600 frames at 640x480 with ground-truth
+    poses, fused into keyframes by each strategy and integrated (5 mm voxels,
+    2.5 cm truncation); CORR of the mesh against a dense cloud on the scene's
+    surfaces, COMPL of the per-frame reconstruction's vertices (kappa = 1)
+    against the mesh, both capped at 5 cm."""
+    wl = synth.workload(2)
+    n = wl.n_frames
+    log(f"surface study: rendering {n} frames")
+    z, rgb = synth.frames(wl, np.arange(n), device="cuda")
+    zt = [torch.from_numpy(z[f]).cuda() for f in range(n)]
+    ct = [torch.from_numpy(rgb[f]).cuda() for f in range(n)]
+    ref = torch.from_numpy(synth.surface_points(wl.scene, 8_000_000, 5)).cuda()
+    runs = [("const", {"kappa": k}) for k in (1, 2, 5, 10, 20, 60)]
+    runs += [("dist", {"max_trans": a, "max_rot": np.radians(b)}) for a, b in ((0.05, 5.0), (0.15, 10.0), (0.4, 30.0))]
+    runs += [("overlap", {"min_overlap": o}) for o in (0.9, 0.75, 0.5)]
+    out, ref_vertices = [], None
+    for strategy, kw in runs:
+        vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 21, 1 << 20)
+        kappa = kw.pop("kappa", 5)
+        sess = online.OnlineSession(vol, wl.intr, kappa, 1, strategy=strategy, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(n):
+            sess.add_frame(zt[f], ct[f], wl.R[f], wl.t[f])
+        sess.flush()
+        torch.cuda.synchronize()
+        fuse_s = time.perf_counter() - t0
+        vol.check_error()
+        xyz, keys = vol.mesh()
+        v = surface.mesh_vertices(xyz, keys)
+        if ref_vertices is None:
+            ref_vertices = v.clone()  # the first run is kappa = 1: the reference of COMPL
+        rec = {"strategy": strategy, **{k: (round(float(x), 4) if isinstance(x, float) else x) for k, x in kw.items()},
+               "kappa": kappa if strategy == "const" else None, "keyframes": sess.n_keyframes,
+               "mean_kappa": round(n / sess.n_keyframes, 2), "fuse_integrate_s": round(fuse_s, 3),
+               "triangles": int(xyz.shape[0]), "corr_mm": round(surface.corr(v, ref, 0.05) * 1e3, 3),
+               "compl_mm": round(surface.compl(ref_vertices, v, 0.05) * 1e3, 3)}
+        log(f"surface study: {rec}")
+        out.append(rec)
+        vol.close()
+    return out
+
+
 def traffic_from_profile(digest, variant):
     """HBM bytes per launch of the voxel pass from the committed rocprofv3
     counter summary, if it was taken from the current kernel sources and the
@@ -236,6 +310,9 @@ def main():
                     help="keyframes without the interleaved copy (three gathers per voxel test)")
     ap.add_argument("--cpu-sample", type=int, default=200,
                     help="keyframes the oracle re-integrates for the CPU baseline (all 200 by default)")
+    ap.add_argument("--no-mesh", action="store_true")
+    ap.add_argument("--surface", action="store_true",
+                    help="also run the keyframe-strategy surface study (CORR / COMPL per strategy)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -247,7 +324,7 @@ def main():
     import torch
 
     import oracle
-    from paper_1709_03763_amd import scsurf, synth
+    from paper_1709_03763_amd import online, scsurf, surface, synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -354,6 +431,11 @@ def main():
                  "batched_speedup": round(pms / ms_per_step, 2)}
         log(f"plain: {pms:.3f} ms/step ({plain['batched_speedup']}x slower than batched)")
 
+    mesh_res = None
+    if not args.no_mesh:
+        mesh_res = mesh_stage(torch, scsurf, surface, synth, vol, wl)
+        log(f"mesh: {mesh_res}")
+
     online_res = None
     if not args.no_online:
         online_res = online_stage(torch, scsurf, synth)
@@ -365,6 +447,10 @@ def main():
     if not args.no_adjoint:
         adj_ms = adjoint_stage(torch, scsurf, synth)
         log(f"adjoint forward+backward (16 keyframes, 320x240): {adj_ms:.2f} ms")
+
+    surface_res = None
+    if args.surface:
+        surface_res = surface_stage(torch, scsurf, surface, online, synth, log)
 
     cpu = None
     if not args.no_cpu:
@@ -397,12 +483,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {
             "workload": "batched re-integration: 10x10x3 m room with 40 boxes/spheres, 1000 frames at 640x480 "
                         "fused 5 per keyframe into 200 keyframes with valid-pixel fractions U(0.4,1.0), "
-                        "voxel 1 cm, truncation 4 cm, 2^21 buckets, FP32 TSDF + RGBA8 colour + FP32 weight; "
+                        "voxel 1 cm, truncation 4 cm, 2^21 buckets, FP64 TSDF + RGBA8 colour + FP32 weight; "
                         "one pose-graph update moving all 200 poses by N(0, 3 cm / 1.5 deg), keyframes "
                         "ordered by pose change, de-integrated and re-integrated in one persistent launch",
             "keyframes": n_kf, "operations": n_ops, "resolution": [Wd, H], "blocks": n_blocks_after,
@@ -429,8 +515,11 @@ def main():
                    "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)
                                                / integrate_s / 1e9 / HBM_PEAK_GBS, 5),
                    "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),
-                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms, "online_loop": online_res},
+                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms, "online_loop": online_res,
+                   "mesh": mesh_res},
     }
+    if surface_res is not None:
+        out["surface_study"] = surface_res
     print(json.dumps(out), flush=True)
     vol.close()
 

@@ -211,10 +211,20 @@ def corridor_path(rng, n_frames, x0=1.0, x1=39.0):
     return pts
 
 
-def orient_path(rng, pts, sweep=1.0, pitch_amp=math.radians(12.0)):
-    """Yaw follows the heading plus a slow sweep; pitch stays within +-15 deg."""
+def _smooth(x, sigma):
+    """Gaussian smoothing with edge padding (sigma in samples)."""
+    r = int(3 * sigma)
+    k = np.exp(-0.5 * (np.arange(-r, r + 1) / sigma) ** 2)
+    k /= k.sum()
+    return np.convolve(np.pad(x, r, mode="edge"), k, mode="valid")
+
+
+def orient_path(rng, pts, sweep=1.0, pitch_amp=math.radians(12.0), heading_sigma=30.0):
+    """Yaw follows the heading (smoothed over about a second, so a hand-held
+    pan stays below a few degrees per frame through tight turns) plus a slow
+    sweep; pitch stays within +-15 deg."""
     d = np.gradient(pts, axis=0)
-    heading = np.unwrap(np.arctan2(d[:, 1], d[:, 0]))
+    heading = _smooth(np.unwrap(np.arctan2(d[:, 1], d[:, 0])), heading_sigma)
     n = len(pts)
     k = np.arange(n)
     ph = rng.uniform(0, 2 * math.pi, size=2)
