@@ -33,7 +33,7 @@ METRIC = "keyframes re-integrated/sec (de+re) and voxel updates/sec; % of HBM pe
 HBM_PEAK_GBS = 8000.0
 VOXEL_BYTES = 16  # FP64 D + FP32 W + RGBA8 colour
 KF_PIXEL_BYTES = 12  # keyframe depth + weight + RGBA8 colour
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_main_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "voxel_pass_traffic_batched_reintegration.json")
 KERNEL_SOURCES = ["paper_1709_03763_amd/csrc/batch.hip", "paper_1709_03763_amd/csrc/kernels.hpp",
                   "paper_1709_03763_amd/csrc/common.hpp"]
 
