@@ -495,21 +495,21 @@ __global__ __launch_bounds__(256) void batch_compact_kernel(const OpDesc* __rest
     stat_add(cd, 3, worker, n_written, lane);
 }
 
-// LDS bytes per wavefront of the pipelined pass: the state of one part of
-// the block (four z-slices, 256 voxels: D f64, W f32, colour RGBA8 u32 or
-// 3 x f64) and the queue of one (operation, part) step's touched voxels.
+// LDS bytes per wavefront of the pipelined pass: the block state (512
+// voxels: D f64, W f32, colour RGBA8 u32 or 3 x f64) and a queue of 128
+// touched voxels (two z-slices of a lane group).
 template <int CM>
 constexpr int pipe_wave_bytes()
 {
-    return 256 * (8 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 256 * (2 + 4 + 4 + 4);
+    return 512 * (8 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 128 * (2 + 4 + 4 + 4);
 }
 
 // Per-wavefront LDS of the pipelined pass.
 struct PipeLds {
-    double* sD;      // [256]
-    float* sW;       // [256]
-    uint32_t* sC;    // [256] RGBA8
-    double* sCf;     // [3][256] FP32-colour mode
+    double* sD;      // [512]
+    float* sW;       // [512]
+    uint32_t* sC;    // [512] RGBA8
+    double* sCf;     // [3][512] FP32-colour mode
     float* qw;       // queue: quantised weight,
     float* qz;       // keyframe depth,
     uint32_t* qc;    // RGBA8 colour or pixel index (FP32 colour),
@@ -521,29 +521,22 @@ __device__ inline PipeLds pipe_lds(unsigned char* wb)
 {
     PipeLds L;
     L.sD = reinterpret_cast<double*>(wb);
-    L.sW = reinterpret_cast<float*>(L.sD + 256);
-    L.sC = reinterpret_cast<uint32_t*>(L.sW + 256);
-    L.sCf = reinterpret_cast<double*>(L.sW + 256);
-    L.qw = reinterpret_cast<float*>(wb + 256 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
-    L.qz = L.qw + 256;
-    L.qc = reinterpret_cast<uint32_t*>(L.qz + 256);
-    L.qvox = reinterpret_cast<uint16_t*>(L.qc + 256);
+    L.sW = reinterpret_cast<float*>(L.sD + 512);
+    L.sC = reinterpret_cast<uint32_t*>(L.sW + 512);
+    L.sCf = reinterpret_cast<double*>(L.sW + 512);
+    L.qw = reinterpret_cast<float*>(wb + 512 * (12 + (CM == SC_COLOR_RGBA8 ? 4 : 24)));
+    L.qz = L.qw + 128;
+    L.qc = reinterpret_cast<uint32_t*>(L.qz + 128);
+    L.qvox = reinterpret_cast<uint16_t*>(L.qc + 128);
     return L;
 }
 
-// Operations of a block in bit order, read word by word from its mask; the
-// walk runs once per part.
+// Operations of a block in bit order, read word by word from its mask.
 struct OpWalk {
     const uint64_t* mask;
     int words, w;
     uint64_t m;
 };
-
-__device__ inline void walk_start(OpWalk& k)
-{
-    k.w = 0;
-    k.m = bcast64(k.mask[0]);
-}
 
 __device__ inline int walk_next(OpWalk& k)
 {
@@ -556,64 +549,17 @@ __device__ inline int walk_next(OpWalk& k)
     return k.w * 64 + b;
 }
 
-// State of the pipelined pass within one block.  slot0 is the block's pool
-// slot before the pass (-1: not allocated), slot its current one.
+// State of the pipelined pass within one block.  slot is the block's pool
+// slot before the pass (-1: not allocated).
 struct PipeBlock {
-    int bx, by, bz, slot0, slot;
+    int bx, by, bz, slot;
     uint32_t touched, n_upd, pairs;
     bool re_touch, e_na, e_w;
 };
 
-// Loads the state of part `part` (z-slices 4 part .. 4 part + 3) into LDS;
-// zeros for a block that did not exist before the pass.
-template <int CM>
-__device__ inline void pipe_load(const VolDev& v, int slot0, int part, int lane, const PipeLds& L)
-{
-    const float* blk = v.pool + (size_t)max(slot0, 0) * v.stride;
-    const bool have = slot0 >= 0;
-#pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const int xl = lane + 64 * j, x = xl + 256 * part;
-        L.sD[xl] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
-        L.sW[xl] = have ? blk[kPoolW + x] : 0.0f;
-        if (CM == SC_COLOR_RGBA8) {
-            L.sC[xl] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
-        } else {
-            const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
-            L.sCf[xl] = have ? Cd[x] : 0.0;
-            L.sCf[256 + xl] = have ? Cd[512 + x] : 0.0;
-            L.sCf[512 + xl] = have ? Cd[1024 + x] : 0.0;
-        }
-    }
-}
-
-// Ends a part: allocates the block once a re-integration has touched it
-// (all lanes, uniform branch) and writes the part's touched slices back.
-template <int CM>
-__device__ inline void pipe_store(const VolDev& v, uint64_t key, PipeBlock& pb, int part, int lane, const PipeLds& L)
-{
-    if (pb.slot < 0 && __ballot(pb.re_touch) != 0ull) pb.slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
-    if (pb.slot < 0) return;
-    float* blk = v.pool + (size_t)pb.slot * v.stride;
-#pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        if (!((pb.touched >> (4 * part + j)) & 1u)) continue;
-        const int xl = lane + 64 * j, x = xl + 256 * part;
-        reinterpret_cast<double*>(blk)[x] = L.sD[xl];
-        blk[kPoolW + x] = L.sW[xl];
-        if (CM == SC_COLOR_RGBA8) {
-            reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = L.sC[xl];
-        } else {
-            double* Cd = reinterpret_cast<double*>(blk + kPoolC);
-            Cd[x] = L.sCf[xl];
-            Cd[512 + x] = L.sCf[256 + xl];
-            Cd[1024 + x] = L.sCf[512 + xl];
-        }
-    }
-}
-
-// Issues the keyframe gathers of (operation `o`, part `part`) into `f` and
-// returns the camera z of the block origin for it in `qz`.
+// Issues the keyframe gathers of (operation `o`, part `part`: z-slices
+// 4 part .. 4 part + 3) into `f` and returns the camera z of the block origin
+// in `qz`.
 template <int CM>
 __device__ inline void pipe_fetch(const OpDesc& o, const VolDev& v, const PipeBlock& pb, int part, int lane,
                                   VoxFetch<CM, 4>& f, double& qz)
@@ -627,24 +573,26 @@ __device__ inline void pipe_fetch(const OpDesc& o, const VolDev& v, const PipeBl
 }
 
 // One step of the pipelined pass: issue the keyframe gathers of the next
-// (operation, part) into `nxt`, then decide, gather into the queue and update
-// the current one from `cur`.  Steps run part by part (every operation of
-// the block on part 0, then on part 1), so each voxel still sees the
-// operations in bit order.  The dense phase reads only LDS, so the loads of
-// `nxt` stay in flight while the current step is processed.  Returns false
-// when the block has no further step; otherwise op_c / part_c / qz_c name
-// the next step.
+// (operation, part) into `nxt`, then decide the current one from `cur` and
+// update its touched voxels: two z-slices at a time, gathered with their
+// keyframe samples into the LDS queue (ballot + mbcnt) and updated densely
+// by all 64 lanes.  The dense phase reads only LDS, so the loads of `nxt`
+// stay in flight meanwhile.  Per voxel the operations apply in bit order.
+// Returns false when the block has no further step; otherwise op_c /
+// part_c / qz_c name the next step.
 template <int CM>
 __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v, OpWalk& walk, PipeBlock& pb,
                                  VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, int& op_c, int& part_c, double& qz_c,
                                  int lane, const PipeLds& L)
 {
     constexpr int TV = 4;
-    int op_n = walk_next(walk), part_n = part_c;
-    if (op_n < 0 && part_c == 0) {
-        walk_start(walk);
-        op_n = walk_next(walk);
+    int op_n, part_n;
+    if (part_c == 0) {
+        op_n = op_c;
         part_n = 1;
+    } else {
+        op_n = walk_next(walk);
+        part_n = 0;
     }
     double qz_n = 0.0;
     if (op_n >= 0) pipe_fetch<CM>(ops[op_n], v, pb, part_n, lane, nxt, qz_n);
@@ -652,55 +600,60 @@ __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v
     pb.pairs += (part_c == 0) ? 1u : 0u;
     VoxHits<CM, TV> hv;
     decide_voxels<CM, TV>(cur, v.mu, hv);
-    uint32_t cnt = 0u;
+    const bool any = __ballot(hv.hit != 0u) != 0ull;
+    if (any && op.sign < 0 && pb.slot < 0) {
+        pb.e_na = true;
+    } else if (any) {
+        if (op.sign > 0) pb.re_touch = true;
+        pb.touched |= hv.hit << (part_c * TV);
+        pb.n_upd += __popc(hv.hit);
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+            uint32_t cnt = 0u;
 #pragma unroll
-    for (int j = 0; j < TV; ++j) {
-        const bool t = (hv.hit >> j) & 1u;
-        const uint64_t bal = __ballot(t);
-        if (t) {
-            const uint32_t pos = cnt + lanes_below(bal);
-            L.qvox[pos] = (uint16_t)(lane + 64 * (part_c * TV + j));
-            L.qw[pos] = hv.w[j];
-            L.qz[pos] = hv.z[j];
-            L.qc[pos] = (CM == SC_COLOR_RGBA8) ? hv.c[j] : (uint32_t)hv.pix[j];
-        }
-        cnt += (uint32_t)__popcll(bal);
-    }
-    if (cnt != 0u) {
-        if (op.sign < 0 && pb.slot0 < 0) {
-            pb.e_na = true;
-        } else {
-            if (op.sign > 0) pb.re_touch = true;
-            pb.touched |= hv.hit << (part_c * TV);
-            pb.n_upd += __popc(hv.hit);
+            for (int jj = 0; jj < 2; ++jj) {
+                // slices jj and 2 + jj picked by selects, so no register array is indexed at run time
+                const int j = 2 * half + jj;
+                const bool t = (hv.hit >> j) & 1u;
+                const uint64_t bal = __ballot(t);
+                if (t) {
+                    const uint32_t pos = cnt + lanes_below(bal);
+                    L.qvox[pos] = (uint16_t)(lane + 64 * (part_c * TV + j));
+                    L.qw[pos] = half ? hv.w[2 + jj] : hv.w[jj];
+                    L.qz[pos] = half ? hv.z[2 + jj] : hv.z[jj];
+                    L.qc[pos] = (CM == SC_COLOR_RGBA8) ? (half ? hv.c[2 + jj] : hv.c[jj])
+                                                       : (uint32_t)(half ? hv.pix[2 + jj] : hv.pix[jj]);
+                }
+                cnt += (uint32_t)__popcll(bal);
+            }
+            if (cnt == 0u) continue;
             wave_lds_sync();
             for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
                 const uint32_t e = r0 + (uint32_t)lane;
                 if (e < cnt) {
                     const int x = L.qvox[e];
-                    const int xl = x & 255;
                     const double pz64 =
                         ((qz_c + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) +
                         (double)(x >> 6) * op.az[2];
                     const double d = distance(L.qz[e], pz64);
                     const float wq = L.qw[e];
-                    double D = L.sD[xl];
-                    float W = L.sW[xl];
+                    double D = L.sD[x];
+                    float W = L.sW[x];
                     if (CM == SC_COLOR_RGBA8) {
-                        uint32_t C = L.sC[xl];
+                        uint32_t C = L.sC[x];
                         pb.e_w |= !update_rgba8(D, W, C, d, wq, L.qc[e], op.sign);
-                        L.sC[xl] = C;
+                        L.sC[x] = C;
                     } else {
                         const float* cp = reinterpret_cast<const float*>(op.color) + 3 * (size_t)L.qc[e];
                         const float c[3] = {__ldg(cp), __ldg(cp + 1), __ldg(cp + 2)};
-                        double C3[3] = {L.sCf[xl], L.sCf[256 + xl], L.sCf[512 + xl]};
+                        double C3[3] = {L.sCf[x], L.sCf[512 + x], L.sCf[1024 + x]};
                         pb.e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
-                        L.sCf[xl] = C3[0];
-                        L.sCf[256 + xl] = C3[1];
-                        L.sCf[512 + xl] = C3[2];
+                        L.sCf[x] = C3[0];
+                        L.sCf[512 + x] = C3[1];
+                        L.sCf[1024 + x] = C3[2];
                     }
-                    L.sD[xl] = D;
-                    L.sW[xl] = W;
+                    L.sD[x] = D;
+                    L.sW[x] = W;
                 }
             }
             wave_lds_sync();
@@ -713,12 +666,11 @@ __device__ inline bool pipe_step(const OpDesc* __restrict__ ops, const VolDev& v
     return true;
 }
 
-// Persistent voxel pass, compacting and pipelined: one wavefront per block,
-// the block handled in two parts of four z-slices with only the current
-// part's state in LDS; per (operation, part) the touched voxels are gathered
-// into an LDS queue with their keyframe samples and updated densely, and the
-// gathers of each step are issued one step ahead through two fetch buffers
-// used alternately.
+// Persistent voxel pass, compacting and pipelined: one wavefront per block
+// with the block state in LDS; per (operation, part of four z-slices) the
+// touched voxels are gathered into an LDS queue with their keyframe samples
+// and updated densely, and the gathers of each step are issued one step
+// ahead through two fetch buffers used alternately.
 template <int CM>
 __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
 {
@@ -739,48 +691,70 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
         const uint32_t h = bcast(cd.sorted[i]);
         const uint64_t key = bcast64(cd.skey[i]);
         PipeBlock pb;
-        pb.slot0 = pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
+        pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
         unpack_key(key, pb.bx, pb.by, pb.bz);
         pb.touched = pb.n_upd = pb.pairs = 0u;
         pb.re_touch = pb.e_na = pb.e_w = false;
+        {
+            const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
+            const bool have = pb.slot >= 0;
+#pragma unroll 4
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                L.sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+                L.sW[x] = have ? blk[kPoolW + x] : 0.0f;
+                if (CM == SC_COLOR_RGBA8) {
+                    L.sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
+                } else {
+                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
+                    L.sCf[x] = have ? Cd[x] : 0.0;
+                    L.sCf[512 + x] = have ? Cd[512 + x] : 0.0;
+                    L.sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
+                }
+            }
+        }
+        wave_lds_sync();
         OpWalk walk;
         walk.mask = cd.mask + (size_t)h * cd.words;
         walk.words = cd.words;
-        walk_start(walk);
+        walk.w = 0;
+        walk.m = bcast64(walk.mask[0]);
         int op_c = walk_next(walk);
         if (op_c >= 0) {
             VoxFetch<CM, TV> f0, f1;
             int part_c = 0;
             double qz_c;
             pipe_fetch<CM>(ops[op_c], v, pb, 0, lane, f0, qz_c);
-            pipe_load<CM>(v, pb.slot0, 0, lane, L);
-            wave_lds_sync();
-            bool second = false;
             for (;;) {
                 if (!pipe_step<CM>(ops, v, walk, pb, f0, f1, op_c, part_c, qz_c, lane, L)) break;
-                if (part_c == 1 && !second) {
-                    pipe_store<CM>(v, key, pb, 0, lane, L);
-                    wave_lds_sync();
-                    pipe_load<CM>(v, pb.slot0, 1, lane, L);
-                    wave_lds_sync();
-                    second = true;
-                }
                 if (!pipe_step<CM>(ops, v, walk, pb, f1, f0, op_c, part_c, qz_c, lane, L)) break;
-                if (part_c == 1 && !second) {
-                    pipe_store<CM>(v, key, pb, 0, lane, L);
-                    wave_lds_sync();
-                    pipe_load<CM>(v, pb.slot0, 1, lane, L);
-                    wave_lds_sync();
-                    second = true;
-                }
             }
-            pipe_store<CM>(v, key, pb, 1, lane, L);
         }
         n_pairs += pb.pairs;
         n_upd += pb.n_upd;
         const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
+        int slot = pb.slot;
+        if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
+        if (slot >= 0) {
+            float* blk = v.pool + (size_t)slot * v.stride;
+#pragma unroll 2
+            for (int j = 0; j < 8; ++j) {
+                if (!((pb.touched >> j) & 1u)) continue;
+                const int x = lane + 64 * j;
+                reinterpret_cast<double*>(blk)[x] = L.sD[x];
+                blk[kPoolW + x] = L.sW[x];
+                if (CM == SC_COLOR_RGBA8) {
+                    reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = L.sC[x];
+                } else {
+                    double* Cd = reinterpret_cast<double*>(blk + kPoolC);
+                    Cd[x] = L.sCf[x];
+                    Cd[512 + x] = L.sCf[512 + x];
+                    Cd[1024 + x] = L.sCf[1024 + x];
+                }
+            }
+        }
         const bool wrote = __ballot(pb.touched != 0) != 0;
-        n_written += (pb.slot >= 0 && wrote) ? 1u : 0u;
+        n_written += (slot >= 0 && wrote) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
         wave_lds_sync();
     }
