@@ -161,24 +161,27 @@ def _block_finder(blocks):
     return find
 
 
-def marching_cubes(field, voxel_size):
+def marching_cubes(field, voxel_size, anchor_blocks=None):
     """Triangle soup of a volume export {'blocks' (n,3), 'D' (n,512),
     'W' (n,512)}: (tri (T,3,3) float64 positions in metres, edges (T,3,4)
     int64 rows (x, y, z, k) naming each vertex: k < 3 the edge along axis k
     from voxel (x, y, z), k = 3 + j the centre of loop j of the cube of
-    voxel (x, y, z))."""
+    voxel (x, y, z)).  With `anchor_blocks` (K,3), only the cubes whose
+    corner 0 lies in those blocks are meshed (their corners may lie in any
+    block of the field).  Triangles come grouped by case."""
     blocks = np.asarray(field["blocks"], np.int64)
     D = np.asarray(field["D"], np.float64)
     W = np.asarray(field["W"], np.float64)
-    n = len(blocks)
     s = float(np.float32(voxel_size))
-    if n == 0:
-        return np.zeros((0, 3, 3)), np.zeros((0, 3, 4), np.int64)
+    empty = (np.zeros((0, 3, 3)), np.zeros((0, 3, 4), np.int64))
+    if len(blocks) == 0:
+        return empty
     find = _block_finder(blocks)
     i = np.arange(512)
     local = np.stack([i & 7, (i >> 3) & 7, i >> 6], 1)
-    # every voxel of every block anchors one cube
-    vox = (8 * blocks[:, None, :] + local[None, :, :]).reshape(-1, 3)
+    anchors = blocks if anchor_blocks is None else np.asarray(anchor_blocks, np.int64).reshape(-1, 3)
+    # every voxel of every anchor block anchors one cube
+    vox = (8 * anchors[:, None, :] + local[None, :, :]).reshape(-1, 3)
     Dc = np.zeros((len(vox), 8))
     ok = np.ones(len(vox), bool)
     for k in range(8):
@@ -194,31 +197,36 @@ def marching_cubes(field, voxel_size):
     case = np.zeros(len(vox), np.int64)
     for k in range(8):
         case |= (Dc[:, k] < 0).astype(np.int64) << k
+    meshed = np.nonzero(ok & (case != 0) & (case != 255))[0]
     tri, edg = [], []
-    for c_idx in np.nonzero(ok & (case != 0) & (case != 255))[0]:
+    for c in np.unique(case[meshed]):
+        sel = meshed[case[meshed] == c]
+        g = vox[sel]
         pos, key = {}, {}
         for e in range(12):
             lo, hi, a = edge_corners(e)
-            p = vox[c_idx] + CORNER_OFF[lo]
-            d0, d1 = Dc[c_idx, lo], Dc[c_idx, hi]
-            if (d0 < 0) == (d1 < 0):
+            if ((c >> lo) & 1) == ((c >> hi) & 1):
                 continue
-            tt = d0 / (d0 - d1)
-            x = [s * float(p[0]), s * float(p[1]), s * float(p[2])]
-            x[a] = s * (float(p[a]) + tt)
+            p = g + CORNER_OFF[lo]
+            d0, d1 = Dc[sel, lo], Dc[sel, hi]
+            t = d0 / (d0 - d1)
+            x = s * p.astype(np.float64)
+            x[:, a] = s * (p[:, a].astype(np.float64) + t)
             pos[e] = x
-            key[e] = [int(p[0]), int(p[1]), int(p[2]), a]
-        for j, (loop, centre) in enumerate(LOOPS[case[c_idx]]):
+            key[e] = np.concatenate([p, np.full((len(sel), 1), a)], 1)
+        for j, (loop, centre) in enumerate(LOOPS[c]):
             if centre:
-                acc = [0.0, 0.0, 0.0]
+                acc = np.zeros((len(sel), 3))
                 for e in loop:
-                    acc = [acc[r] + pos[e][r] for r in range(3)]
-                pos[12 + j] = [acc[r] / len(loop) for r in range(3)]
-                key[12 + j] = [int(vox[c_idx][0]), int(vox[c_idx][1]), int(vox[c_idx][2]), 3 + j]
-        for t in TABLE[case[c_idx]]:
-            tri.append([pos[v] for v in t])
-            edg.append([key[v] for v in t])
-    return np.array(tri, np.float64).reshape(-1, 3, 3), np.array(edg, np.int64).reshape(-1, 3, 4)
+                    acc = acc + pos[e]
+                pos[12 + j] = acc / len(loop)
+                key[12 + j] = np.concatenate([g, np.full((len(sel), 1), 3 + j)], 1)
+        for t3 in TABLE[c]:
+            tri.append(np.stack([pos[v] for v in t3], 1))
+            edg.append(np.stack([key[v] for v in t3], 1))
+    if not tri:
+        return empty
+    return np.concatenate(tri), np.concatenate(edg).astype(np.int64)
 
 
 def unique_vertices(tri, edges):

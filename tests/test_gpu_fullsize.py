@@ -110,3 +110,90 @@ def test_touched_blocks_of_sampled_operations_are_allocated(full):
         rec = probe.record(kfs[k], wl.intr, R, t)
         blocks = set(map(tuple, np.floor_divide(rec["n"], 8).tolist()))
         assert blocks <= have, f"operation {j}: {len(blocks - have)} touched blocks missing"
+
+
+@pytest.fixture(scope="module")
+def oracle_field(full):
+    """The oracle's own field after the same 600 operations."""
+    wl, kfs, field, ops, vol = full
+    _say("oracle: 200 integrations and the 400-operation update")
+    ref = oracle.Volume(S, MU)
+    for k, sign, R, t in ops:
+        rc = ref.integrate(kfs[k], wl.intr, R, t) if sign > 0 else ref.deintegrate(kfs[k], wl.intr, R, t)
+        assert rc == oracle.OK
+    return ref.export()
+
+
+def _anchor_blocks(keys):
+    """Block of the cube each triangle comes from: the centre vertex's voxel
+    when the triangle has one, else the componentwise minimum of its edge
+    keys (three edge vertices of one cube never all lie on its far faces)."""
+    k = keys.astype(np.int64)
+    centre = k[:, :, 3] >= 3
+    anchor = k[:, :, :3].min(axis=1)
+    has_c = centre.any(axis=1)
+    ci = np.argmax(centre, axis=1)
+    anchor[has_c] = k[has_c, ci[has_c], :3]
+    return np.floor_divide(anchor, 8)
+
+
+def _pack(b):
+    b = np.asarray(b, np.int64) + (1 << 20)
+    return (b[:, 0] << 42) | (b[:, 1] << 21) | b[:, 2]
+
+
+def test_mesh_on_sampled_blocks_matches_oracle(full, oracle_field):
+    """Marching Cubes at the benchmark's full size: the cubes anchored in 3000
+    sampled blocks give the same triangles (keys and orientation) on the
+    GPU and in the oracle, with vertices within 1e-6 m."""
+    from oracle import mesh as M
+    wl, kfs, field, ops, vol = full
+    rng = np.random.default_rng(3)
+    ob = oracle_field["blocks"]
+    pick = ob[rng.choice(len(ob), 3000, replace=False)]
+    tri_o, key_o = M.marching_cubes(oracle_field, S, pick)
+    assert np.isin(_pack(_anchor_blocks(key_o)), _pack(pick)).all(), "the anchor rule holds on the oracle's mesh"
+    xyz, keys = vol.mesh()
+    _say(f"full-size mesh: {xyz.shape[0]} triangles on the GPU")
+    kg = keys.cpu().numpy().astype(np.int64)
+    mine = np.isin(_pack(_anchor_blocks(kg)), _pack(pick))
+    kg, xg = kg[mine], xyz.cpu().numpy().astype(np.float64)[mine]
+    assert len(kg) == len(key_o) > 10000
+    allk = np.concatenate([kg.reshape(-1, 4), key_o.reshape(-1, 4)])
+    _, inv = np.unique(allk, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    ig, io = inv[:kg.size // 4].reshape(-1, 3), inv[kg.size // 4:].reshape(-1, 3)
+
+    def canon(t):
+        r = np.argmin(t, axis=1)
+        rows = np.arange(len(t))
+        c = np.stack([t[rows, r], t[rows, (r + 1) % 3], t[rows, (r + 2) % 3]], 1)
+        return c[np.lexsort((c[:, 2], c[:, 1], c[:, 0]))]
+
+    np.testing.assert_array_equal(canon(ig), canon(io))
+    pg = np.zeros((inv.max() + 1, 3))
+    po = np.zeros_like(pg)
+    pg[ig.reshape(-1)] = xg.reshape(-1, 3)
+    po[io.reshape(-1)] = tri_o.reshape(-1, 3)
+    err = np.abs(pg - po).max()
+    _say(f"full-size mesh: {len(kg)} triangles in the sampled blocks, max vertex difference {err:.2e} m")
+    assert err <= 1e-6
+
+
+def test_nn_distance_full_size_sampled():
+    """Capped distances at the benchmark's sizes (3 M queries against 4 M
+    reference points on the large room's surfaces), checked on 200 k
+    sampled queries against the oracle."""
+    from oracle import mesh as M
+    from paper_1709_03763_amd import surface
+    wl = synth.workload(4)
+    ref = synth.surface_points(wl.scene, 4_000_000, 7)
+    rng = np.random.default_rng(8)
+    q = synth.surface_points(wl.scene, 3_000_000, 9)
+    q = (q + rng.normal(0, 0.01, q.shape)).astype(np.float32)
+    d, total = surface.nn_distance(torch.from_numpy(ref).cuda(), torch.from_numpy(q).cuda(), 0.05)
+    d = d.cpu().numpy()
+    pick = rng.choice(len(q), 200_000, replace=False)
+    exp = M.nn_distance(ref.astype(np.float64), q[pick].astype(np.float64), float(np.float32(0.05)))
+    np.testing.assert_allclose(d[pick], exp, rtol=1e-6, atol=1e-9)
+    assert total == pytest.approx(float(d.astype(np.float64).sum()), rel=1e-9)
