@@ -276,6 +276,151 @@ def surface_stage(torch, scsurf, surface, online, synth, log):
     return out
 
 
+def _rgba(rgb):
+    col = np.zeros(rgb.shape[:2] + (4,), np.uint8)
+    col[..., :3] = rgb
+    return col
+
+
+def _update_rates(torch, scsurf, vol, kset, intr, A, B, m, mode, fn, steps):
+    """(keyframes re-integrated/s, updates/s, voxel updates per update as the
+    volume's counters report them) of `steps` alternating updates
+    A -> B -> A ... (two untimed updates first; the volume ends at A)."""
+    state = [A, B]
+
+    def step():
+        order, _ = fn(kset, intr, state[0], state[1], m, mode)
+        state[0], state[1] = state[1], state[0]
+        return order
+
+    steps += steps & 1  # an even count leaves the keyframes integrated at A again
+    step()
+    step()
+    torch.cuda.synchronize()
+    s0 = vol.stats()
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(steps):
+        n += len(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    upd = vol.stats()[2] - s0[2]
+    vol.check_error()
+    return n / dt, steps / dt, upd / steps
+
+
+def _oracle_rate(oracle, kfs, intr, A, B, sample, threads, s, mu):
+    """Oracle keyframes re-integrated/s (de at A, re at B) over `sample`."""
+    oracle.set_threads(threads)
+    vol = oracle.Volume(s, mu)
+    for k in sample:
+        vol.integrate(kfs[k], intr, A[0][k], A[1][k])
+    t0 = time.perf_counter()
+    for k in sample:
+        assert vol.deintegrate(kfs[k], intr, A[0][k], A[1][k]) == oracle.OK
+    for k in sample:
+        assert vol.integrate(kfs[k], intr, B[0][k], B[1][k]) == oracle.OK
+    return len(sample) / (time.perf_counter() - t0)
+
+
+def configs_stage(torch, scsurf, synth, oracle, log):
+    """Rates on the other workloads: plain tiny (one keyframe of five frames'
+    first frame at 320x240, a 1 cm / 0.5 deg perturbation), plain full
+    resolution (10 keyframes at 640x480, 5 mm voxels, N(0, 2 cm / 1 deg)),
+    and the corridor (600 keyframes at 640x480, 20 loop-closure updates of
+    the Eq. 3 window of 100).  Keyframes are the first rendered frame of each
+    group with the oracle's depth weight (seeded weights for the corridor).
+    GPU: plain per-keyframe and batched paths; oracle: FP64 on 1 and on all
+    host threads."""
+    n_all = oracle.threads()
+    out = {}
+
+    def dev(k):
+        return scsurf.Keyframe(torch.from_numpy(k["depth"]).cuda(), torch.from_numpy(k["weight"]).cuda(),
+                               torch.from_numpy(k["color"]).cuda())
+
+    for cfg in (1, 2):
+        wl = synth.workload(cfg)
+        first = np.array([g[0] for g in synth.keyframe_groups(wl)])
+        z, rgb = synth.frames(wl, first, device="cuda")
+        kfs = []
+        for k in range(len(first)):
+            w = oracle.depth_weight(z[k], wl.intr)
+            kfs.append({"depth": np.where(w > 0, z[k], 0).astype(np.float32), "weight": w, "color": _rgba(rgb[k])})
+        A = (wl.R[first], wl.t[first])
+        B = synth.perturb_all(A[0], A[1], 0.01, 0.5, 1) if cfg == 1 else synth.perturb_all(A[0], A[1], 0.02, 1.0, 2)
+        s, mu = wl.volume.voxel_size, wl.volume.trunc
+        nb = 1 << (16 if cfg == 1 else 20)
+        vol = scsurf.Volume(s, mu, nb, nb // 2, scsurf.COLOR_RGBA8, max_batch_ops=64)
+        dks = [dev(k) for k in kfs]
+        for k in range(len(kfs)):
+            vol.integrate(dks[k], wl.intr, A[0][k], A[1][k])
+        kset = scsurf.KeyframeSet(dks)
+        n = len(kfs)
+        steps = 200 if cfg == 1 else 20
+        plain = _update_rates(torch, scsurf, vol, dks, wl.intr, A, B, n, scsurf.SEL_ALL_ORDERED,
+                              vol.reintegrate_plain, steps)
+        batch = _update_rates(torch, scsurf, vol, kset, wl.intr, A, B, n, scsurf.SEL_ALL_ORDERED,
+                              vol.reintegrate_batch, steps)
+        vol.close()
+        sample = list(range(n))
+        o1 = _oracle_rate(oracle, kfs, wl.intr, A, B, sample[:3], 1, s, mu)
+        on = _oracle_rate(oracle, kfs, wl.intr, A, B, sample, n_all, s, mu)
+        per_update = batch[2]  # the batched pass counts its voxel updates; the plain path does the same work
+        out[f"config{cfg}"] = {"keyframes": n, "voxel_updates_per_update": int(per_update),
+                               "plain_kf_per_s": round(plain[0], 1),
+                               "plain_voxel_updates_per_s": round(plain[1] * per_update, 1),
+                               "batched_kf_per_s": round(batch[0], 1),
+                               "batched_voxel_updates_per_s": round(batch[1] * per_update, 1),
+                               "oracle_1core_kf_per_s": round(o1, 3), f"oracle_{n_all}core_kf_per_s": round(on, 3)}
+        log(f"config {cfg}: {out[f'config{cfg}']}")
+    # corridor
+    wl = synth.workload(5)
+    first = np.array([g[0] for g in synth.keyframe_groups(wl)[:600]])
+    log("corridor: rendering 600 keyframes")
+    z, rgb = synth.frames(wl, first, device="cuda")
+    rng = np.random.default_rng(55)
+    kfs = []
+    for k in range(len(first)):
+        w = rng.integers(64, 4096, z[k].shape).astype(np.float32) / 1024.0
+        w = np.where(z[k] > 0, w, 0).astype(np.float32)
+        kfs.append({"depth": np.where(w > 0, z[k], 0).astype(np.float32), "weight": w, "color": _rgba(rgb[k])})
+    R, t = wl.R[first], wl.t[first]
+    vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, 1 << 21, scsurf.COLOR_RGBA8,
+                        max_batch_ops=256)
+    dks = [dev(k) for k in kfs]
+    for k in range(len(kfs)):
+        vol.integrate(dks[k], wl.intr, R[k], t[k])
+    kset = scsurf.KeyframeSet(dks)
+    updates = list(synth.loop_closure_updates(R, t, 20, 5))
+    Ti = (R.copy(), t.copy())
+    vol.reintegrate_batch(kset, wl.intr, Ti, updates[0], 100, scsurf.SEL_EQ3)  # warm-up, then back
+    vol.reintegrate_batch(kset, wl.intr, updates[0], Ti, 100, scsurf.SEL_EQ3)
+    torch.cuda.synchronize()
+    s0 = vol.stats()
+    t0 = time.perf_counter()
+    n = 0
+    for Tn in updates:
+        order, Ti = vol.reintegrate_batch(kset, wl.intr, Ti, Tn, 100, scsurf.SEL_EQ3)
+        n += len(order)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    upd = vol.stats()[2] - s0[2]
+    nb = vol.check_error()
+    vol.close()
+    sample = list(range(0, 600, 60))
+    A = (R, t)
+    B = synth.perturb_all(R, t, 0.05, 1.5, 6)
+    o1 = _oracle_rate(oracle, kfs, wl.intr, A, B, sample[:3], 1, wl.volume.voxel_size, wl.volume.trunc)
+    on = _oracle_rate(oracle, kfs, wl.intr, A, B, sample, n_all, wl.volume.voxel_size, wl.volume.trunc)
+    out["config5"] = {"keyframes": 600, "updates": len(updates), "reintegrated": n, "blocks": int(nb),
+                      "batched_kf_per_s": round(n / dt, 1), "batched_voxel_updates_per_s": round(upd / dt, 1),
+                      "oracle_1core_kf_per_s": round(o1, 3), f"oracle_{n_all}core_kf_per_s": round(on, 3)}
+    log(f"config 5: {out['config5']}")
+    oracle.set_threads(n_all)
+    return out
+
+
 def traffic_from_profile(digest, variant):
     """HBM bytes per launch of the voxel pass from the committed rocprofv3
     counter summary, if it was taken from the current kernel sources and the
@@ -311,6 +456,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200,
                     help="keyframes the oracle re-integrates for the CPU baseline (all 200 by default)")
     ap.add_argument("--no-mesh", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="also time the plain tiny, plain full-resolution and corridor workloads (GPU and oracle)")
     ap.add_argument("--surface", action="store_true",
                     help="also run the keyframe-strategy surface study (CORR / COMPL per strategy)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -448,6 +595,10 @@ def main():
         adj_ms = adjoint_stage(torch, scsurf, synth)
         log(f"adjoint forward+backward (16 keyframes, 320x240): {adj_ms:.2f} ms")
 
+    configs_res = None
+    if args.configs:
+        configs_res = configs_stage(torch, scsurf, synth, oracle, log)
+
     surface_res = None
     if args.surface:
         surface_res = surface_stage(torch, scsurf, surface, online, synth, log)
@@ -462,6 +613,13 @@ def main():
                "sample": f"{len(sample)} of the {n_kf} keyframes, each de-integrated at its integration pose and "
                          f"re-integrated at its new pose on a volume holding those {len(sample)} ({dt:.1f} s)"}
         log(f"oracle: {rate:.3f} keyframes/s on {oracle.threads()} threads")
+        if args.configs:
+            n_all = oracle.threads()
+            oracle.set_threads(1)
+            rate1, _ = cpu_baseline(oracle, kfs_np, wl.intr, A, B, sample[:3])
+            oracle.set_threads(n_all)
+            cpu["one_core_value"] = round(rate1, 4)
+            log(f"oracle on one thread: {rate1:.3f} keyframes/s")
 
     if args.calib_copy_gib > 0:
         n = int(args.calib_copy_gib * (1 << 30)) // 4
@@ -520,6 +678,8 @@ def main():
     }
     if surface_res is not None:
         out["surface_study"] = surface_res
+    if configs_res is not None:
+        out["configs"] = configs_res
     print(json.dumps(out), flush=True)
     vol.close()
 

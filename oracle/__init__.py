@@ -70,6 +70,8 @@ def lib():
         L.of_fuse_color.restype = None
         L.of_fuse_color.argtypes = [P, P, P, P, i32, i32, i32, P, P, P, i32, f32, P, P, P]
         L.ov_threads.restype = i32
+        L.ov_set_threads.restype = i32
+        L.ov_set_threads.argtypes = [i32]
         L.ov_voxel_sequence.restype = i32
         L.ov_voxel_sequence.argtypes = [P, P, P, P, i32, i32, P, i32, P, P, P, P, P, P, P, P]
         _lib = L
@@ -284,3 +286,8 @@ def kf_fuse(depth, rgb, intr, R, t, ref=0, z_min=0.3, z_max=4.0, disc_rel=0.05, 
 
 def threads() -> int:
     return int(lib().ov_threads())
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops (for timing); returns it."""
+    return int(lib().ov_set_threads(int(n)))

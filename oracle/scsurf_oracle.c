@@ -1043,6 +1043,19 @@ void of_fuse_color(const float* Z, const float* wz, const uint16_t* cs, const do
     free(obs);
 }
 
+/* Sets the OpenMP thread count used by the oracle's parallel loops (for
+ * timing it on one core or on all of them); returns the new maximum. */
+int ov_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 int ov_threads(void)
 {
 #ifdef _OPENMP

@@ -30,7 +30,10 @@ def compare_fields(gpu, ref, d_tol=1e-5, c_tol=1e-5, exact_color=True):
     assert dmax <= d_tol, f"max |D - D_ref| = {dmax}"
     if exact_color:
         np.testing.assert_array_equal(gpu["C"].astype(np.float64), ref["C"])
+        cmax = 0.0
     else:
         cmax = float(np.abs(gpu["C"].astype(np.float64) - ref["C"]).max()) if len(rb) else 0.0
         assert cmax <= c_tol, f"max |C - C_ref| = {cmax}"
+    print(f"[parity] {len(rb)} blocks identical, W identical, max |D - D_oracle| = {dmax:.2e} m, "
+          f"max |C - C_oracle| = {cmax:.2e}", flush=True)
     return dmax
