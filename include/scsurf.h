@@ -326,6 +326,14 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
 sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* tri_keys, int64_t cap,
                          int64_t* n_tri);
 
+/* The case table sc_volume_mesh uses, as built on the host (no device
+ * work): loops (host, 256 x 16 bytes) holds, per case (bit k set = corner k
+ * inside), its loops in order, each a header byte (vertex count, | 0x80
+ * when fanned around a centre vertex) followed by its edge numbers, ended by
+ * a zero header or the 16th byte; ntri (host, 256 bytes) the triangle count
+ * per case.  Either may be NULL, not both. */
+sc_status sc_mesh_table(uint8_t* loops, uint8_t* ntri);
+
 /* The mesh's vertices, one per key (Sec. 5 measures distances between mesh
  * vertices): tri_xyz / tri_keys as written by sc_volume_mesh (device, n_tri
  * triangles); vert_xyz (device, cap x 3 FP32) receives the first

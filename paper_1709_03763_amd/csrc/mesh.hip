@@ -492,6 +492,16 @@ using namespace sc;
 
 extern "C" {
 
+sc_status sc_mesh_table(uint8_t* loops, uint8_t* ntri)
+{
+    if (!loops && !ntri) return SC_EINVAL;
+    McTable T;
+    if (!mc_build(T)) return SC_EDEVICE;
+    if (loops) memcpy(loops, T.loops, sizeof(T.loops));
+    if (ntri) memcpy(ntri, T.ntri, sizeof(T.ntri));
+    return SC_OK;
+}
+
 sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* tri_keys, int64_t cap, int64_t* n_tri)
 {
     if (!vol || cap < 0 || !n_tri) return SC_EINVAL;

@@ -67,7 +67,7 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
-           "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance"]
+           "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table"]
 
 _lib = None
 
@@ -114,6 +114,7 @@ def lib():
     L.sc_volume_mesh.argtypes = [P, P, P, P, i64, ctypes.POINTER(i64)]
     L.sc_mesh_vertices.argtypes = [P, P, i64, P, i64, ctypes.POINTER(i64), P]
     L.sc_nn_distance.argtypes = [P, i64, P, i64, ctypes.c_float, P, P, P]
+    L.sc_mesh_table.argtypes = [P, P]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:

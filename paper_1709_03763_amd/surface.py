@@ -19,6 +19,25 @@ def _dptr(t: torch.Tensor, dtype, what):
     return t.data_ptr() if t.numel() else None
 
 
+def mesh_table():
+    """The library's Marching Cubes case table: per case, a list of
+    (edges in loop order, fanned around a centre vertex), and the triangle
+    counts."""
+    import numpy as np
+    loops = np.zeros((256, 16), np.uint8)
+    ntri = np.zeros(256, np.uint8)
+    scsurf.check(scsurf.lib().sc_mesh_table(loops.ctypes.data, ntri.ctypes.data), "sc_mesh_table")
+    out = []
+    for c in range(256):
+        row, p, cur = loops[c], 0, []
+        while p < 16 and row[p]:
+            n = int(row[p] & 0x7F)
+            cur.append(([int(e) for e in row[p + 1:p + 1 + n]], bool(row[p] & 0x80)))
+            p += 1 + n
+        out.append(cur)
+    return out, ntri.astype(int).tolist()
+
+
 def mesh_vertices(tri_xyz: torch.Tensor, tri_keys: torch.Tensor, stream=None) -> torch.Tensor:
     """Distinct vertices (V,3) of a triangle soup from `Volume.mesh`."""
     n_tri = int(tri_xyz.shape[0])

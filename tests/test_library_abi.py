@@ -54,3 +54,13 @@ def test_library_rejects_bad_arguments():
         scsurf.select_dist([1.0, 2.0], 0, scsurf.SEL_EQ3)
     with pytest.raises(scsurf.ScError):
         scsurf.select_dist([1.0, 2.0], 1, 7)
+
+
+def test_library_mesh_table_matches_oracle():
+    """The library builds its Marching Cubes table on the host from the same
+    rule as the oracle, with code of its own; all 256 cases must agree."""
+    from oracle import mesh as M
+    from paper_1709_03763_amd import surface
+    loops, ntri = surface.mesh_table()
+    assert loops == [[(list(l), bool(c)) for l, c in M.LOOPS[k]] for k in range(256)]
+    assert ntri == [len(M.TABLE[k]) for k in range(256)]
