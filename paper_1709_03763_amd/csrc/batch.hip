@@ -50,6 +50,18 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
     }
 }
 
+// Workgroups of cand_batch_kernel that fit on one CU at once (registers and
+// LDS); the kernel strides over its items statically, so a grid larger than
+// this runs its surplus as a second, mostly idle wave of workgroups.
+int cand_batch_resident_wgs()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cand_batch_kernel, CandCfg<kTileBatch, kCellBatch>::threads,
+                                                     0) != hipSuccess)
+        n = 0;
+    return std::max(1, std::min(n, 8));
+}
+
 __device__ inline int mask_count(const CandDev& cd, uint32_t h)
 {
     int c = 0;
@@ -856,8 +868,8 @@ static void launch_candidates(sc_volume* vol, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
-    cand_batch_kernel<<<vol->n_cu * 8, CandCfg<kTileBatch, kCellBatch>::threads, 0, s>>>(vol->d_ops, vol->d_hdr,
-                                                                                       vol->dev, vol->cand);
+    cand_batch_kernel<<<vol->n_cu * vol->cand_wgs, CandCfg<kTileBatch, kCellBatch>::threads, 0, s>>>(
+        vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, vol->dev, n_bins);

@@ -131,4 +131,6 @@ struct sc_volume {
     int timing_cap, timing_n;
     sc_schedule sched;
     int n_cu;
+    int cand_wgs;            // resident workgroups per CU of the batched candidate kernel
+    int plain_wgs;           // resident workgroups per CU of the plain update kernel
 };

@@ -306,7 +306,7 @@ sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     vol->parity ^= 1;
     dim3 tiles((in->width + kTilePlain - 1) / kTilePlain, (in->height + kTilePlain - 1) / kTilePlain);
     cand_plain_kernel<<<tiles, CandCfg<kTilePlain, kCellPlain>::threads, 0, s>>>(op, vol->dev, vol->cand, p);
-    const int grid = vol->n_cu * 4;
+    const int grid = vol->n_cu * vol->plain_wgs;  // resident at once: the first items are assigned statically
     if (vol->p.color_mode == SC_COLOR_RGBA8)
         update_plain_kernel<SC_COLOR_RGBA8><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
     else
@@ -347,6 +347,16 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     vol->p = *p;
     vol->device = dev;
     vol->n_cu = prop.multiProcessorCount;
+    vol->cand_wgs = cand_batch_resident_wgs();
+    {
+        int n = 0;
+        const hipError_t e = (p->color_mode == SC_COLOR_RGBA8)
+                                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, update_plain_kernel<SC_COLOR_RGBA8>,
+                                                                               256, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, update_plain_kernel<SC_COLOR_F32>,
+                                                                               256, 0);
+        vol->plain_wgs = (e == hipSuccess) ? std::max(1, std::min(n, 4)) : 1;
+    }
     vol->sched.vpl = 8;
     vol->sched.waves_per_wg = 4;
     vol->sched.wgs_per_cu = 4;
