@@ -38,15 +38,23 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
                                                          VolDev v, CandDev cd)
 {
     __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    __shared__ int next;
     const int tiles = hdr->tiles_x * hdr->tiles_y;
     const int items = hdr->n_ops * tiles;
-    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    // first item static, then one pop per item from the batch's tile cursor:
+    // tiles differ widely in cost (grazing surfaces give large cell boxes),
+    // so a static stride leaves a tail of workgroups with heavy tiles
+    int it = blockIdx.x;
+    while (it < items) {
         const int o = it / tiles;
         const int tile = it - o * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
         cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds);
         __syncthreads();
+        if (threadIdx.x == 0) next = (int)gridDim.x + (int)atomicAdd(cd.counters + 6, 1u);
+        __syncthreads();
+        it = next;
     }
 }
 

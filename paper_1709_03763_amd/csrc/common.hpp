@@ -89,7 +89,7 @@ struct CandDev {
     uint64_t* skey;       // block key of each sorted entry
     int32_t* sslot;       // pool slot of each sorted entry's block before the pass (-1: not allocated)
     uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity),
-                          // [4] batch candidates, [5] batch work cursor
+                          // [4] batch candidates, [5] batch work cursor, [6] batch tile cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
     unsigned long long* stats;  // cumulative: candidate blocks, (block, op) pairs, voxel updates, blocks written
     uint32_t mask_bits;   // cand buckets - 1
