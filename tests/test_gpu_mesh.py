@@ -163,3 +163,30 @@ def test_surface_metrics_match_oracle(fields):
         assert c == pytest.approx(co, rel=1e-5)
         assert m == pytest.approx(mo, rel=1e-5)
         assert 0 < c < radius and 0 < m < radius
+
+
+def test_mesh_capacity_below_count_writes_a_prefix(fields):
+    """With cap below the triangle count the call reports the full count and
+    writes cap triangles, each one of the full set."""
+    import ctypes
+    wl, vol, tri, keys = fields
+    xyz_all, k_all = vol.mesh()
+    n_all = xyz_all.shape[0]
+    cap = 1000
+    xyz = torch.full((cap, 3, 3), float("nan"), device="cuda")
+    k = torch.full((cap, 3, 4), -7, dtype=torch.int32, device="cuda")
+    n = ctypes.c_int64()
+    scsurf.check(scsurf.lib().sc_volume_mesh(vol._h, None, xyz.data_ptr(), k.data_ptr(), cap, ctypes.byref(n)),
+                 "sc_volume_mesh")
+    assert n.value == n_all
+    full = {tuple(t.reshape(-1).tolist()) for t in k_all.cpu().numpy()}
+    part = k.cpu().numpy()
+    assert all(tuple(t.reshape(-1).tolist()) in full for t in part)
+    assert not torch.isnan(xyz).any()
+
+
+def test_nn_distance_of_a_cloud_to_itself_is_zero():
+    rng = np.random.default_rng(12)
+    p = torch.from_numpy(rng.uniform(-2, 2, (5000, 3)).astype(np.float32)).cuda()
+    d, total = surface.nn_distance(p, p, 0.05)
+    assert float(d.abs().max()) == 0.0 and total == 0.0

@@ -181,3 +181,12 @@ def test_strategy_session_matches_oracle(scan, strategy):
     dmax = compare_fields(got, exp)
     _say(f"{strategy} session: keyframe sizes {sizes}, max |D - D_oracle| = {dmax:.2e}")
     vol.close()
+
+
+def test_overlap_of_an_invalid_frame_is_empty():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    intr = synth.QVGA
+    z = torch.zeros((intr.height, intr.width), device="cuda")
+    assert scsurf.overlap(z, intr, np.eye(3), np.zeros(3), np.eye(3), np.zeros(3)) == (0, 0)
+    z = torch.full((intr.height, intr.width), 5.0, device="cuda")  # beyond z_max
+    assert scsurf.overlap(z, intr, np.eye(3), np.zeros(3), np.eye(3), np.zeros(3)) == (0, 0)
