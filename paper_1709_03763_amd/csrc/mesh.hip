@@ -321,38 +321,57 @@ __device__ inline uint64_t vertex_key(const int32_t* k, bool& bad)
            (uint64_t)(k[3] & 7);
 }
 
+constexpr int kVertPerThread = 8;  // vertex instances per thread: one reservation per 2048
+
+// Inserts each vertex key into the hash set; the threads that insert a key
+// first append its position.  A workgroup scans its winners in LDS and
+// reserves their range with one atomic.
 __global__ __launch_bounds__(256) void unique_vertex_kernel(const float* __restrict__ xyz, const int32_t* __restrict__ keys,
                                                             int64_t n, uint64_t* table, uint32_t mask, float* out,
                                                             int64_t cap, unsigned long long* count, int* err)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool won = false, bad = false;
-    if (i < n) {
+    __shared__ uint32_t part[256];
+    __shared__ unsigned long long base;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kVertPerThread;
+    uint32_t won = 0u;
+    bool bad = false;
+    for (int k = 0; k < kVertPerThread; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= n) break;
         const uint64_t key = vertex_key(keys + 4 * i, bad);
         uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32) & mask;
         for (uint32_t probe = 0; probe <= mask; ++probe) {
             const uint64_t old = atomicCAS((unsigned long long*)(table + h), (unsigned long long)kKeyEmpty,
                                            (unsigned long long)key);
             if (old == kKeyEmpty) {
-                won = true;
+                won |= 1u << k;
                 break;
             }
             if (old == key) break;
             h = (h + 1) & mask;
         }
     }
-    const uint64_t bal = __ballot(won);
-    unsigned long long base = 0;
-    if (lane == 0 && bal) base = atomicAdd(count, (unsigned long long)__popcll(bal));  // not a loop
-    base = __shfl(base, 0);
-    if (won) {
-        const unsigned long long pos = base + lanes_below(bal);
+    const uint32_t mine = (uint32_t)__popc(won);
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t y = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (threadIdx.x == 255) base = atomicAdd(count, (unsigned long long)part[255]);
+    __syncthreads();
+    unsigned long long pos = base + part[threadIdx.x] - mine;
+    for (int k = 0; k < kVertPerThread; ++k) {
+        if (!((won >> k) & 1u)) continue;
+        const int64_t i = i0 + k;
         if ((int64_t)pos < cap) {
             out[3 * pos] = xyz[3 * i];
             out[3 * pos + 1] = xyz[3 * i + 1];
             out[3 * pos + 2] = xyz[3 * i + 2];
         }
+        ++pos;
     }
     if (bad) atomicOr(err, 1);
 }
@@ -411,15 +430,19 @@ __global__ __launch_bounds__(256) void nn_count_kernel(const float* __restrict__
     atomicAdd(g.cnt + h, 1u);
 }
 
-// Offsets: a workgroup scans its 256 slots and reserves their range with one
+constexpr int kSlotsPerThread = 16;  // grid slots per thread: one reservation per 4096
+
+// Offsets: a workgroup scans its 4096 slots and reserves their range with one
 // atomic (ranges of different workgroups need not be in slot order).
 __global__ __launch_bounds__(256) void nn_offset_kernel(NnGrid g, uint32_t n_slots, uint32_t* total)
 {
     __shared__ uint32_t part[256];
     __shared__ uint32_t base;
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t c = (i < n_slots) ? g.cnt[i] : 0u;
-    part[threadIdx.x] = c;
+    const uint32_t i0 = (blockIdx.x * 256u + threadIdx.x) * kSlotsPerThread;
+    uint32_t mine = 0u;
+    for (int k = 0; k < kSlotsPerThread; ++k)
+        if (i0 + k < n_slots) mine += g.cnt[i0 + k];
+    part[threadIdx.x] = mine;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
         const uint32_t y = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0u;
@@ -429,7 +452,12 @@ __global__ __launch_bounds__(256) void nn_offset_kernel(NnGrid g, uint32_t n_slo
     }
     if (threadIdx.x == 255) base = atomicAdd(total, part[255]);
     __syncthreads();
-    if (i < n_slots) g.off[i] = base + part[threadIdx.x] - c;
+    uint32_t off = base + part[threadIdx.x] - mine;
+    for (int k = 0; k < kSlotsPerThread; ++k)
+        if (i0 + k < n_slots) {
+            g.off[i0 + k] = off;
+            off += g.cnt[i0 + k];
+        }
 }
 
 __global__ __launch_bounds__(256) void nn_scatter_kernel(const float* __restrict__ ref, int64_t n, NnGrid g,
@@ -549,9 +577,10 @@ sc_status sc_mesh_vertices(const float* tri_xyz, const int32_t* tri_keys, int64_
         fill_u64(table, kKeyEmpty, slots, s);
         ok = hipMemsetAsync(d_count, 0, sizeof(unsigned long long), s) == hipSuccess &&
              hipMemsetAsync(d_err, 0, sizeof(int), s) == hipSuccess;
+        const int64_t per_wg = 256 * kVertPerThread;
         if (ok)
-            unique_vertex_kernel<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tri_xyz, tri_keys, nv, table, slots - 1,
-                                                                             vert_xyz, cap, d_count, d_err);
+            unique_vertex_kernel<<<(unsigned)((nv + per_wg - 1) / per_wg), 256, 0, s>>>(
+                tri_xyz, tri_keys, nv, table, slots - 1, vert_xyz, cap, d_count, d_err);
         ok = ok && hipGetLastError() == hipSuccess;
         ok = ok && hipMemcpyAsync(&count, d_count, sizeof(count), hipMemcpyDeviceToHost, s) == hipSuccess;
         ok = ok && hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess;
@@ -597,7 +626,8 @@ sc_status sc_nn_distance(const float* ref, int64_t n_ref, const float* query, in
             fill_u32(total, 0u, 1, s);
             const unsigned grid_r = (unsigned)((n_ref + 255) / 256);
             nn_count_kernel<<<grid_r, 256, 0, s>>>(ref, n_ref, g, slot_of);
-            nn_offset_kernel<<<(slots + 255) / 256, 256, 0, s>>>(g, slots, total);
+            nn_offset_kernel<<<(slots + 256 * kSlotsPerThread - 1) / (256 * kSlotsPerThread), 256, 0, s>>>(g, slots,
+                                                                                                          total);
             nn_scatter_kernel<<<grid_r, 256, 0, s>>>(ref, n_ref, g, slot_of);
         }
     }
