@@ -320,9 +320,11 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
  * Outputs (device, may be NULL): tri_xyz cap x 3 x 3 FP32 vertex positions
  * (metres, world frame), tri_keys cap x 3 x 4 int32 vertex keys (x, y, z, k):
  * k < 3 the edge along axis k from voxel (x, y, z), k = 3 + j the centre of
- * loop j in the cube of voxel (x, y, z).  Triangles come in no fixed order;
- * the first min(count, cap) are written and *n_tri (host) receives the
- * count, so a call with cap = 0 sizes the buffers.  Synchronises. */
+ * loop j in the cube of voxel (x, y, z).  Triangles come in a fixed order
+ * (blocks in pool order, cubes in voxel order within a block); the first
+ * min(count, cap) are written and *n_tri (host) receives the count, so a
+ * call with cap = 0 sizes the buffers.  Allocates temporaries (per-block
+ * counts and offsets); synchronises. */
 sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* tri_keys, int64_t cap,
                          int64_t* n_tri);
 

@@ -141,15 +141,18 @@ static sc_status mc_table_ready()
 
 // ---------------------------------------------------------------------------
 // Marching Cubes: one wavefront per allocated block; the block and its +x,
-// +y, +z neighbours' first layers (9 x 9 x 9 voxels) are staged in LDS, each
-// lane meshes eight cubes, and a wavefront reserves its triangles with one
-// atomic.
+// +y, +z neighbours' first layers (9 x 9 x 9 voxels) are staged in LDS and
+// each lane meshes eight cubes.  A count pass stores each block's triangle
+// count, a scan turns the counts into offsets, and the fill pass writes each
+// block's triangles from its offset: no shared counter, and the output order
+// is fixed (pool order, then cube order).
 // ---------------------------------------------------------------------------
 
 struct MeshOut {
-    float* xyz;                  // cap x 3 x 3, or null (count only)
+    float* xyz;                  // cap x 3 x 3, or null
     int32_t* keys;               // cap x 3 x 4, or null
-    unsigned long long* count;   // triangles found
+    uint32_t* counts;            // count pass: triangles per block (else null)
+    const uint64_t* offsets;     // fill pass: first triangle of each block
     int64_t cap;
 };
 
@@ -240,19 +243,19 @@ __global__ __launch_bounds__(64) void mesh_kernel(VolDev v, MeshOut out)
         cases[j] = ok ? cs : 0u;
         mine += g_mc.ntri[cases[j]];
     }
-    // wavefront-exclusive prefix of the triangle counts, one reservation
+    // wavefront-exclusive prefix of the triangle counts: the count pass
+    // stores the block's total, the fill pass writes from the block's offset
     uint32_t incl = mine;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    const uint32_t total = __shfl(incl, 63);
-    unsigned long long base = 0;
-    if (lane == 63 && total) base = atomicAdd(out.count, (unsigned long long)total);  // one lane, not a loop
-    base = __shfl(base, 63);
-    if (!out.xyz && !out.keys) return;
-    unsigned long long t = base + (incl - mine);
+    if (out.counts) {
+        if (lane == 63) out.counts[b] = incl;
+        return;
+    }
+    unsigned long long t = out.offsets[b] + (incl - mine);
     const double s = (double)v.s;
     for (int j = 0; j < 8; ++j) {
         const uint32_t cs = cases[j];
@@ -305,6 +308,71 @@ __global__ __launch_bounds__(64) void mesh_kernel(VolDev v, MeshOut out)
             ++li;
         }
     }
+}
+
+// Exclusive scan of per-block triangle counts into 64-bit offsets: 1024
+// counts per workgroup, then one workgroup scans the workgroup sums in
+// chunks with a running carry, then the carries are added.
+__global__ __launch_bounds__(256) void scan_local_kernel(const uint32_t* __restrict__ in, uint64_t* out, uint64_t* sums,
+                                                         uint32_t n)
+{
+    __shared__ uint64_t part[256];
+    const uint32_t i0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
+    uint64_t v[4], mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (i0 + k < n) ? (uint64_t)in[i0 + k] : 0ull;
+        mine += v[k];
+    }
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint64_t y = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    uint64_t run = part[threadIdx.x] - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k < n) out[i0 + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(uint64_t* sums, uint32_t n, uint64_t* total)
+{
+    __shared__ uint64_t part[256];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0ull;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < n; c0 += 256u) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint64_t mine = (i < n) ? sums[i] : 0ull;
+        part[threadIdx.x] = mine;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const uint64_t y = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0ull;
+            __syncthreads();
+            part[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < n) sums[i] = carry + part[threadIdx.x] - mine;
+        __syncthreads();
+        if (threadIdx.x == 255) carry += part[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(uint64_t* out, const uint64_t* __restrict__ sums, uint32_t n)
+{
+    const uint32_t i0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
+    const uint64_t c = sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) out[i0 + k] += c;
 }
 
 // ---------------------------------------------------------------------------
@@ -538,19 +606,38 @@ sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* 
     int64_t nb = 0;
     st = sc_volume_query(vol, stream, &nb, nullptr);
     if (st != SC_OK) return st;
+    *n_tri = 0;
+    if (nb == 0) return SC_OK;
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long* d_count = nullptr;
-    MESH_TRY(hipMalloc(&d_count, sizeof(unsigned long long)));
-    unsigned long long count = 0;
-    bool ok = hipMemsetAsync(d_count, 0, sizeof(unsigned long long), s) == hipSuccess;
-    MeshOut out{cap > 0 ? tri_xyz : nullptr, cap > 0 ? tri_keys : nullptr, d_count, cap};
-    if (ok && nb > 0) mesh_kernel<<<(unsigned)nb, 64, 0, s>>>(vol->dev, out);
-    ok = ok && hipGetLastError() == hipSuccess;
-    ok = ok && hipMemcpyAsync(&count, d_count, sizeof(count), hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipStreamSynchronize(s) == hipSuccess;
-    (void)hipFree(d_count);
+    const uint32_t n = (uint32_t)nb;
+    const uint32_t wgs = (n + 1023u) / 1024u;
+    uint32_t* counts = nullptr;
+    uint64_t *offsets = nullptr, *sums = nullptr, *d_total = nullptr;
+    bool ok = hipMalloc(&counts, sizeof(uint32_t) * n) == hipSuccess;
+    ok = ok && hipMalloc(&offsets, sizeof(uint64_t) * n) == hipSuccess;
+    ok = ok && hipMalloc(&sums, sizeof(uint64_t) * wgs) == hipSuccess;
+    ok = ok && hipMalloc(&d_total, sizeof(uint64_t)) == hipSuccess;
+    uint64_t total = 0;
+    if (ok) {
+        MeshOut cnt{nullptr, nullptr, counts, nullptr, 0};
+        mesh_kernel<<<n, 64, 0, s>>>(vol->dev, cnt);
+        scan_local_kernel<<<wgs, 256, 0, s>>>(counts, offsets, sums, n);
+        scan_sums_kernel<<<1, 256, 0, s>>>(sums, wgs, d_total);
+        scan_add_kernel<<<wgs, 256, 0, s>>>(offsets, sums, n);
+        if (cap > 0 && (tri_xyz || tri_keys)) {
+            MeshOut fill{tri_xyz, tri_keys, nullptr, offsets, cap};
+            mesh_kernel<<<n, 64, 0, s>>>(vol->dev, fill);
+        }
+        ok = hipGetLastError() == hipSuccess;
+        ok = ok && hipMemcpyAsync(&total, d_total, sizeof(total), hipMemcpyDeviceToHost, s) == hipSuccess;
+        ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    }
+    (void)hipFree(counts);
+    (void)hipFree(offsets);
+    (void)hipFree(sums);
+    (void)hipFree(d_total);
     if (!ok) return SC_EDEVICE;
-    *n_tri = (int64_t)count;
+    *n_tri = (int64_t)total;
     return SC_OK;
 }
 
