@@ -409,8 +409,8 @@ static bool intr_valid(const sc_intrinsics* in)
 }
 
 // Overlap counts (valid, visible) of one frame with a reference view, FP64
-// in the written order; one thread per pixel, a wavefront reduction, then one
-// atomic per wavefront and counter.
+// in the written order; each thread counts kOverlapPix pixels, a workgroup
+// reduces in LDS and adds its two totals with one atomic each.
 struct OverlapArgs {
     double R[9], t[3], Rr[9], tr[3];
     double fx, fy, cx, cy;
@@ -418,12 +418,7 @@ struct OverlapArgs {
     int32_t width, height;
 };
 
-__device__ inline uint32_t overlap_wave_sum(uint32_t x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
+constexpr int kOverlapPix = 16;
 
 __global__ void overlap_clear_kernel(uint32_t* counts)
 {
@@ -433,36 +428,45 @@ __global__ void overlap_clear_kernel(uint32_t* counts)
 __global__ __launch_bounds__(256) void overlap_kernel(const float* __restrict__ depth, OverlapArgs a,
                                                       uint32_t* counts)
 {
+    __shared__ uint32_t red[2][256];
     const int64_t n = (int64_t)a.width * a.height;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kOverlapPix;
     uint32_t valid = 0u, visible = 0u;
-    if (i < n) {
+    for (int k = 0; k < kOverlapPix; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= n) break;
         const float zf = depth[i];
-        if (zf >= a.z_min && zf <= a.z_max) {
-            valid = 1u;
-            const int u = (int)(i % a.width), v = (int)(i / a.width);
-            const double z = (double)zf;
-            const double p[3] = {(((double)u - a.cx) / a.fx) * z, (((double)v - a.cy) / a.fy) * z, z};
-            double w[3];
+        if (!(zf >= a.z_min && zf <= a.z_max)) continue;
+        ++valid;
+        const int u = (int)(i % a.width), v = (int)(i / a.width);
+        const double z = (double)zf;
+        const double p[3] = {(((double)u - a.cx) / a.fx) * z, (((double)v - a.cy) / a.fy) * z, z};
+        double w[3];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) w[r] = ((a.R[3 * r] * p[0] + a.R[3 * r + 1] * p[1]) + a.R[3 * r + 2] * p[2]) + a.t[r];
-            const double d[3] = {w[0] - a.tr[0], w[1] - a.tr[1], w[2] - a.tr[2]};
-            double q[3];
+        for (int r = 0; r < 3; ++r) w[r] = ((a.R[3 * r] * p[0] + a.R[3 * r + 1] * p[1]) + a.R[3 * r + 2] * p[2]) + a.t[r];
+        const double d[3] = {w[0] - a.tr[0], w[1] - a.tr[1], w[2] - a.tr[2]};
+        double q[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) q[c] = (a.Rr[c] * d[0] + a.Rr[3 + c] * d[1]) + a.Rr[6 + c] * d[2];
-            if (q[2] > 0.0) {
-                const double fu = floor(((a.fx * q[0]) / q[2] + a.cx) + 0.5);
-                const double fv = floor(((a.fy * q[1]) / q[2] + a.cy) + 0.5);
-                visible = (fu >= 0.0 && fu <= (double)(a.width - 1) && fv >= 0.0 && fv <= (double)(a.height - 1)) ? 1u : 0u;
-            }
+        for (int c = 0; c < 3; ++c) q[c] = (a.Rr[c] * d[0] + a.Rr[3 + c] * d[1]) + a.Rr[6 + c] * d[2];
+        if (q[2] > 0.0) {
+            const double fu = floor(((a.fx * q[0]) / q[2] + a.cx) + 0.5);
+            const double fv = floor(((a.fy * q[1]) / q[2] + a.cy) + 0.5);
+            visible += (fu >= 0.0 && fu <= (double)(a.width - 1) && fv >= 0.0 && fv <= (double)(a.height - 1)) ? 1u : 0u;
         }
     }
-    const int lane = threadIdx.x & 63;
-    valid = overlap_wave_sum(valid);
-    visible = overlap_wave_sum(visible);
-    if (lane == 0) {  // not a persistent loop: a lane-0 branch is safe here
-        atomicAdd(counts, valid);
-        atomicAdd(counts + 1, visible);
+    red[0][threadIdx.x] = valid;
+    red[1][threadIdx.x] = visible;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (red[0][0]) atomicAdd(counts, red[0][0]);
+        if (red[1][0]) atomicAdd(counts + 1, red[1][0]);
     }
 }
 
@@ -583,7 +587,8 @@ sc_status sc_overlap(const float* depth, const sc_intrinsics* intr, const sc_pos
     a.height = intr->height;
     overlap_clear_kernel<<<1, 64, 0, s>>>(counts);
     const int64_t n = (int64_t)intr->width * intr->height;
-    overlap_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(depth, a, counts);
+    const int64_t per_wg = 256 * kOverlapPix;
+    overlap_kernel<<<(unsigned)((n + per_wg - 1) / per_wg), 256, 0, s>>>(depth, a, counts);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
