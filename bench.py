@@ -465,7 +465,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the surface-correction path runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "(sharding across GPUs is designed, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
