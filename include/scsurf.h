@@ -146,6 +146,19 @@ sc_status sc_volume_query(sc_volume* vol, void* stream, int64_t* n_blocks, int32
 sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, float* D, float* W, void* C,
                            int64_t cap, int64_t* n_out);
 
+/* Loads blocks into the volume (the inverse of sc_volume_export, for
+ * checkpoints and for meshing given fields): block coordinates (device int32
+ * n x 3) are allocated as by hash_alloc and each block's record is written
+ * from D (device float n x 512, stored in FP64), W (float n x 512; weights
+ * belong on the 2^-10 grid below 2^14, not checked) and C (uint32 RGBA8
+ * n x 512, or float n x 3 x 512 planar in FP32-colour mode), in the layout
+ * sc_volume_export writes; a NULL field is stored as zeros.  Blocks already
+ * present are overwritten; with duplicate coordinates in one call, which
+ * record lands is unspecified.  SC_EINVAL if n exceeds max_blocks;
+ * synchronises and returns the sticky error (SC_EPOOLFULL, SC_EHASHFULL). */
+sc_status sc_volume_import(sc_volume* vol, void* stream, const int32_t* block_xyz, const float* D, const float* W,
+                           const void* C, int64_t n);
+
 /* ---- keyframe fusion (Sec. 3 "Keyframe Fusion", Eq. 1) ------------------- */
 
 /* Overlap of a frame with a keyframe's reference view (Sec. 4.2, the

@@ -202,6 +202,32 @@ __global__ __launch_bounds__(256) void update_plain_kernel(OpDesc op, VolDev v, 
     }
 }
 
+// Writes imported block records into their pool slots (D widened to FP64;
+// FP32 colour widened to the FP64 planes).
+__global__ void import_kernel(VolDev v, const int32_t* __restrict__ slots, int64_t n, const float* __restrict__ D,
+                              const float* __restrict__ W, const void* __restrict__ C)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = slots[b];
+    if (slot < 0) return;
+    float* blk = v.pool + (size_t)slot * v.stride;
+    for (int i = threadIdx.x; i < kBlockVox; i += blockDim.x) {
+        const size_t g = (size_t)b * kBlockVox + i;
+        reinterpret_cast<double*>(blk)[i] = D ? (double)D[g] : 0.0;
+        blk[kPoolW + i] = W ? W[g] : 0.0f;
+        if (v.color_mode == SC_COLOR_RGBA8) {
+            reinterpret_cast<uint32_t*>(blk + kPoolC)[i] = C ? reinterpret_cast<const uint32_t*>(C)[g] : 0u;
+        } else {
+            const float* Cf = reinterpret_cast<const float*>(C) + (size_t)b * 3 * kBlockVox;
+            double* Cd = reinterpret_cast<double*>(blk + kPoolC);
+            Cd[i] = C ? (double)Cf[i] : 0.0;
+            Cd[512 + i] = C ? (double)Cf[512 + i] : 0.0;
+            Cd[1024 + i] = C ? (double)Cf[1024 + i] : 0.0;
+        }
+    }
+}
+
 __global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float* W, void* C)
 {
     const int64_t b = blockIdx.x;
@@ -495,6 +521,27 @@ sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, flo
     HIP_TRY(hipStreamSynchronize(s));
     if (n_out) *n_out = nb;
     return SC_OK;
+}
+
+sc_status sc_volume_import(sc_volume* vol, void* stream, const int32_t* block_xyz, const float* D, const float* W,
+                           const void* C, int64_t n)
+{
+    if (!vol || n < 0 || (n > 0 && !block_xyz) || n > vol->p.max_blocks) return SC_EINVAL;
+    if (n == 0) return SC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* slots = nullptr;
+    HIP_TRY(hipMalloc(&slots, sizeof(int32_t) * (size_t)n));
+    sc_status st = hash_alloc(vol, block_xyz, n, slots, stream);
+    if (st == SC_OK) {
+        import_kernel<<<(unsigned)n, 256, 0, s>>>(vol->dev, slots, n, D, W, C);
+        st = hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+    }
+    int64_t nb = 0;
+    int32_t sticky = 0;
+    if (st == SC_OK) st = sc_volume_query(vol, stream, &nb, &sticky);
+    (void)hipFree(slots);
+    if (st != SC_OK) return st;
+    return sticky;
 }
 
 sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream)

@@ -67,7 +67,8 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
-           "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table"]
+           "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table",
+           "sc_volume_import"]
 
 _lib = None
 
@@ -115,6 +116,7 @@ def lib():
     L.sc_mesh_vertices.argtypes = [P, P, i64, P, i64, ctypes.POINTER(i64), P]
     L.sc_nn_distance.argtypes = [P, i64, P, i64, ctypes.c_float, P, P, P]
     L.sc_mesh_table.argtypes = [P, P]
+    L.sc_volume_import.argtypes = [P, P, P, P, P, P, i64]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                                           ctypes.POINTER(sc_pose), P, P, P, P, P, P]
     for name in EXPORTS:
@@ -275,6 +277,23 @@ class Volume:
         check(lib().sc_volume_export(self._h, stream_handle(stream), xyz.data_ptr(), D.data_ptr(), W.data_ptr(),
                                      C.data_ptr(), n, ctypes.byref(nout)), "sc_volume_export")
         return {"blocks": xyz[:n], "D": D[:n], "W": W[:n], "C": C[:n]}
+
+    def import_field(self, field, stream=None):
+        """Loads blocks {"blocks" (n,3) int32, "D" (n,512) f32, "W" (n,512) f32,
+        optional "C" (n,512,4) uint8 or (n,3,512) f32} given as device
+        tensors, in the layout `export` returns."""
+        xyz = field["blocks"].to(torch.int32).contiguous()
+        n = int(xyz.shape[0])
+        D = field["D"].to(torch.float32).contiguous()
+        W = field["W"].to(torch.float32).contiguous()
+        C = field.get("C")
+        if C is not None:
+            C = C.contiguous()
+        if D.shape != (n, 512) or W.shape != (n, 512):
+            raise ValueError("D and W must be (n, 512)")
+        check(lib().sc_volume_import(self._h, stream_handle(stream), xyz.data_ptr() if n else None,
+                                     D.data_ptr() if n else None, W.data_ptr() if n else None,
+                                     C.data_ptr() if (C is not None and n) else None, n), "sc_volume_import")
 
     def mesh(self, stream=None):
         """Marching Cubes of the volume: (tri_xyz (T,3,3) f32, tri_keys
