@@ -8,9 +8,10 @@
 //                  2^-10 grid, z on the 2^-20 m grid), so that colliding
 //                  atomics cannot change a bit; Eq. 1's running weighted mean
 //                  equals sum(w z) / sum(w)
-//   sharpen        unsharp mask C + (C - G * C), G the binomial [1 4 6 4 1]/16
-//                  kernel, exact in units of 1/256
-//   blur sums      re-blur measure on integer luminance (exact int64 sums)
+//   color_prep     unsharp mask C + (C - G * C), G the binomial [1 4 6 4 1]/16
+//                  kernel, exact in units of 1/256, and the re-blur measure's
+//                  integer luminance sums (exact int64 per-tile partials)
+//   blur_final     per-frame sums of the partials and w_b
 //   color_kernel   back-warp of each keyframe pixel into every frame,
 //                  bilinear sample of the sharpened colour, weight w_b * w_z,
 //                  per-channel lower weighted median
@@ -154,92 +155,128 @@ __global__ void depth_final_kernel(const unsigned long long* KW, const unsigned 
 
 __device__ inline int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
-__global__ void sharpen_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H, uint16_t* __restrict__ out)
+__device__ inline int luma(uint32_t px) { return (77 * (int)(px & 255u) + 150 * (int)((px >> 8) & 255u) + 29 * (int)(px >> 16) + 128) >> 8; }
+
+// Colour pre-processing of one 64 x 16 tile of one frame.  The tile and a
+// halo (2 pixels for the 5-tap binomial, 5 before and 4 after for the 9-tap
+// re-blur box) are staged in LDS with coordinates clamped to the image, which
+// is the edge rule of both filters; each thread then produces four pixels of
+// the unsharp mask and adds their re-blur terms to four int64 sums, reduced
+// over the workgroup and stored as the tile's partial sums (no atomics).
+//   sums k = 0..3: sF_h, sV_h, sF_v, sV_v, the 9x-scaled horizontal and
+//   vertical variation of the frame and of its re-blurred copy (the box
+//   difference telescopes to two samples).
+constexpr int kPrepTW = 64, kPrepTH = 16;
+constexpr int kPrepLW = kPrepTW + 9, kPrepLH = kPrepTH + 9;
+constexpr int kPrepHalo = 5;
+
+__global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H,
+                                                         int tiles_x, int tiles, uint16_t* __restrict__ out,
+                                                         long long* __restrict__ parts)
 {
+    __shared__ uint32_t pix[kPrepLH][kPrepLW];
+    __shared__ int lum[kPrepLH][kPrepLW];
+    __shared__ long long red[4][4];
+    const int f = blockIdx.y, tile = blockIdx.x;
+    if (f >= n || tile >= tiles) return;
+    const int u0 = (tile % tiles_x) * kPrepTW, v0 = (tile / tiles_x) * kPrepTH;
     const int64_t np = (int64_t)W * H;
-    const int f = blockIdx.y;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n || idx >= np) return;
-    const int u = (int)(idx % W), v = (int)(idx / W);
     const uint8_t* C = rgb + (size_t)f * np * 3;
+    for (int p = threadIdx.x; p < kPrepLW * kPrepLH; p += blockDim.x) {
+        const int i = p % kPrepLW, j = p / kPrepLW;
+        const int uu = clampi(u0 - kPrepHalo + i, 0, W - 1), vv = clampi(v0 - kPrepHalo + j, 0, H - 1);
+        const uint8_t* q = C + 3 * ((size_t)vv * W + uu);
+        const uint32_t px = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+        pix[j][i] = px;
+        lum[j][i] = luma(px);
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kPrepTW - 1), ty = threadIdx.x / kPrepTW;
     const int g[5] = {1, 4, 6, 4, 1};
-    int S[3] = {0, 0, 0};
-#pragma unroll
-    for (int j = -2; j <= 2; ++j) {
-        const int vv = clampi(v + j, 0, H - 1);
-        int row[3] = {0, 0, 0};
-#pragma unroll
-        for (int i = -2; i <= 2; ++i) {
-            const int uu = clampi(u + i, 0, W - 1);
-            const uint8_t* px = C + 3 * ((size_t)vv * W + uu);
-            row[0] += g[i + 2] * px[0];
-            row[1] += g[i + 2] * px[1];
-            row[2] += g[i + 2] * px[2];
-        }
-        S[0] += g[j + 2] * row[0];
-        S[1] += g[j + 2] * row[1];
-        S[2] += g[j + 2] * row[2];
-    }
-    const uint8_t* c0 = C + 3 * idx;
-    uint16_t* o = out + (size_t)f * np * 3 + 3 * idx;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int val = 512 * (int)c0[k] - S[k];
-        o[k] = (uint16_t)clampi(val, 0, 65280);
-    }
-}
-
-__device__ inline int luma(const uint8_t* px) { return (77 * px[0] + 150 * px[1] + 29 * px[2] + 128) >> 8; }
-
-// sums[f*4 + {0,1,2,3}] = sF_h, sV_h, sF_v, sV_v (re-blur with a 9-tap box,
-// kept as 9x integer sums; the box difference telescopes to two samples).
-__global__ __launch_bounds__(256) void blur_sums_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H,
-                                                        unsigned long long* sums)
-{
-    const int64_t np = (int64_t)W * H;
-    const int f = blockIdx.y;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     long long acc[4] = {0, 0, 0, 0};
-    if (f < n && idx < np) {
-        const int u = (int)(idx % W), v = (int)(idx / W);
-        const uint8_t* C = rgb + (size_t)f * np * 3;
-        auto Y = [&](int uu, int vv) { return luma(C + 3 * ((size_t)vv * W + uu)); };
-        const int y0 = Y(u, v);
+    const int u = u0 + tx, i = tx + kPrepHalo;
+#pragma unroll 1
+    for (int r = 0; r < kPrepTH / 4; ++r) {
+        const int y = ty + 4 * r, v = v0 + y, j = y + kPrepHalo;
+        if (u >= W || v >= H) continue;
+        int S[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = -2; b <= 2; ++b) {
+            int row[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = -2; a <= 2; ++a) {
+                const uint32_t px = pix[j + b][i + a];
+                row[0] += g[a + 2] * (int)(px & 255u);
+                row[1] += g[a + 2] * (int)((px >> 8) & 255u);
+                row[2] += g[a + 2] * (int)(px >> 16);
+            }
+            S[0] += g[b + 2] * row[0];
+            S[1] += g[b + 2] * row[1];
+            S[2] += g[b + 2] * row[2];
+        }
+        const uint32_t c0 = pix[j][i];
+        uint16_t* o = out + (size_t)f * np * 3 + 3 * ((size_t)v * W + u);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int val = 512 * (int)((c0 >> (8 * k)) & 255u) - S[k];
+            o[k] = (uint16_t)clampi(val, 0, 65280);
+        }
+        const int y0 = lum[j][i];
         if (u >= 1) {
-            const long long dF = 9LL * abs(y0 - Y(u - 1, v));
-            const long long dB = abs(Y(clampi(u + 4, 0, W - 1), v) - Y(clampi(u - 5, 0, W - 1), v));
-            acc[0] = dF;
-            acc[1] = dF > dB ? dF - dB : 0;
+            const long long dF = 9LL * abs(y0 - lum[j][i - 1]);
+            const long long dB = abs(lum[j][i + 4] - lum[j][i - 5]);
+            acc[0] += dF;
+            acc[1] += dF > dB ? dF - dB : 0;
         }
         if (v >= 1) {
-            const long long dF = 9LL * abs(y0 - Y(u, v - 1));
-            const long long dB = abs(Y(u, clampi(v + 4, 0, H - 1)) - Y(u, clampi(v - 5, 0, H - 1)));
-            acc[2] = dF;
-            acc[3] = dF > dB ? dF - dB : 0;
+            const long long dF = 9LL * abs(y0 - lum[j - 1][i]);
+            const long long dB = abs(lum[j + 4][i] - lum[j - 5][i]);
+            acc[2] += dF;
+            acc[3] += dF > dB ? dF - dB : 0;
         }
     }
-    __shared__ long long red[4][256];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    for (int k = 0; k < 4; ++k)
+        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        parts[((size_t)f * tiles + tile) * 4 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     }
-    if (threadIdx.x < 4 && f < n) atomicAdd(sums + 4 * f + threadIdx.x, (unsigned long long)red[threadIdx.x][0]);
 }
 
-__global__ void blur_final_kernel(const unsigned long long* sums, int n, double* wb)
+// One workgroup per frame: the tiles' partial sums in a fixed order, then
+// w_b = 1 - max(blur_h, blur_v) in FP64.
+__global__ __launch_bounds__(256) void blur_final_kernel(const long long* __restrict__ parts, int n, int tiles,
+                                                         double* wb)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ long long red[4][4];
+    const int f = blockIdx.x;
     if (f >= n) return;
-    const long long sFh = (long long)sums[4 * f], sVh = (long long)sums[4 * f + 1];
-    const long long sFv = (long long)sums[4 * f + 2], sVv = (long long)sums[4 * f + 3];
-    const double bh = sFh > 0 ? (double)(sFh - sVh) / (double)sFh : 0.0;
-    const double bv = sFv > 0 ? (double)(sFv - sVv) / (double)sFv : 0.0;
-    wb[f] = 1.0 - (bh > bv ? bh : bv);
+    long long acc[4] = {0, 0, 0, 0};
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += parts[((size_t)f * tiles + t) * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long s[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        const double bh = s[0] > 0 ? (double)(s[0] - s[1]) / (double)s[0] : 0.0;
+        const double bv = s[2] > 0 ? (double)(s[2] - s[3]) / (double)s[2] : 0.0;
+        wb[f] = 1.0 - (bh > bv ? bh : bv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -349,7 +386,8 @@ struct FuseWs {
     float* wz = nullptr;
     uint16_t* cs = nullptr;
     unsigned long long* acc = nullptr;   // KW, KZ
-    unsigned long long* sums = nullptr;  // 4 per frame
+    long long* parts = nullptr;          // 4 per colour-prep tile and frame
+    size_t cap_parts = 0;
     double* wb = nullptr;
     FuseFrames* d_fr = nullptr;
     FuseFrames* h_fr = nullptr;
@@ -358,7 +396,12 @@ struct FuseWs {
 
 static FuseWs g_ws;
 
-static sc_status ws_reserve(size_t np, size_t frames)
+// Colour-prep tiles of one W x H frame.
+static int prep_tiles_x(int W) { return (W + kPrepTW - 1) / kPrepTW; }
+static int prep_tiles(int W, int H) { return prep_tiles_x(W) * ((H + kPrepTH - 1) / kPrepTH); }
+
+// np pixels per frame, frames frames, parts int64 colour-prep partials.
+static sc_status ws_reserve(size_t np, size_t frames, size_t parts)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
@@ -368,7 +411,8 @@ static sc_status ws_reserve(size_t np, size_t frames)
         g_ws.wz = nullptr;
         g_ws.cs = nullptr;
         g_ws.acc = nullptr;
-        g_ws.sums = nullptr;
+        g_ws.parts = nullptr;
+        g_ws.cap_parts = 0;
         g_ws.wb = nullptr;
         g_ws.d_fr = nullptr;
         g_ws.h_fr = nullptr;
@@ -380,7 +424,6 @@ static sc_status ws_reserve(size_t np, size_t frames)
         if (hipHostMalloc((void**)&g_ws.h_fr, sizeof(FuseFrames), hipHostMallocDefault) != hipSuccess) return SC_ENOMEM;
         if (hipEventCreateWithFlags(&g_ws.staged, hipEventDisableTiming) != hipSuccess) return SC_EDEVICE;
         if (hipEventRecord(g_ws.staged, 0) != hipSuccess) return SC_EDEVICE;
-        if (hipMalloc(&g_ws.sums, sizeof(unsigned long long) * 4 * kMaxFrames) != hipSuccess) return SC_ENOMEM;
         if (hipMalloc(&g_ws.wb, sizeof(double) * kMaxFrames) != hipSuccess) return SC_ENOMEM;
     }
     if (np * frames > g_ws.cap_px * g_ws.cap_frames || np > g_ws.cap_px) {
@@ -393,11 +436,20 @@ static sc_status ws_reserve(size_t np, size_t frames)
         g_ws.wz = nullptr;
         g_ws.cs = nullptr;
         g_ws.acc = nullptr;
+        g_ws.cap_px = g_ws.cap_frames = 0;
         if (hipMalloc(&g_ws.wz, sizeof(float) * px * fr) != hipSuccess) return SC_ENOMEM;
         if (hipMalloc(&g_ws.cs, sizeof(uint16_t) * 3 * px * fr) != hipSuccess) return SC_ENOMEM;
         if (hipMalloc(&g_ws.acc, sizeof(unsigned long long) * 2 * px) != hipSuccess) return SC_ENOMEM;
         g_ws.cap_px = px;
         g_ws.cap_frames = fr;
+    }
+    if (parts > g_ws.cap_parts) {
+        if (hipDeviceSynchronize() != hipSuccess) return SC_EDEVICE;
+        (void)hipFree(g_ws.parts);
+        g_ws.parts = nullptr;
+        g_ws.cap_parts = 0;
+        if (hipMalloc(&g_ws.parts, sizeof(long long) * parts) != hipSuccess) return SC_ENOMEM;
+        g_ws.cap_parts = parts;
     }
     return SC_OK;
 }
@@ -493,12 +545,10 @@ static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& 
 
 static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, double* wb, hipStream_t s)
 {
-    const int64_t np = (int64_t)W * H;
-    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n);
-    sharpen_kernel<<<grid, 256, 0, s>>>(rgb, n, W, H, sharp);
-    fill_u64(reinterpret_cast<uint64_t*>(g_ws.sums), 0ull, 4 * (size_t)n, s);
-    blur_sums_kernel<<<grid, 256, 0, s>>>(rgb, n, W, H, g_ws.sums);
-    blur_final_kernel<<<1, 64, 0, s>>>(g_ws.sums, n, wb);
+    const int tiles = prep_tiles(W, H);
+    color_prep_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp,
+                                                                        g_ws.parts);
+    blur_final_kernel<<<n, 256, 0, s>>>(g_ws.parts, n, tiles, wb);
 }
 
 }  // namespace sc
@@ -522,7 +572,8 @@ sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int
         width > 16384 || height > 16384)
         return SC_EINVAL;
     std::lock_guard<std::mutex> lk(g_ws.mu);
-    const sc_status st = ws_reserve((size_t)width * height, (size_t)n_frames);
+    const sc_status st =
+        ws_reserve((size_t)width * height, (size_t)n_frames, 4 * (size_t)prep_tiles(width, height) * n_frames);
     if (st != SC_OK) return st;
     launch_color_prep(rgb, n_frames, width, height, sharp_out, wb_out, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
@@ -539,7 +590,7 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
     const sc_intrinsics in = *intr;
     const int64_t np = (int64_t)in.width * in.height;
     std::lock_guard<std::mutex> lk(g_ws.mu);
-    sc_status st = ws_reserve((size_t)np, (size_t)n_frames);
+    sc_status st = ws_reserve((size_t)np, (size_t)n_frames, 4 * (size_t)prep_tiles(in.width, in.height) * n_frames);
     if (st != SC_OK) return st;
     if (hipEventSynchronize(g_ws.staged) != hipSuccess) return SC_EDEVICE;
     for (int i = 0; i < n_frames; ++i) {

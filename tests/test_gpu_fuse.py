@@ -45,6 +45,19 @@ def test_color_prep_bit_exact(c1):
     np.testing.assert_array_equal(wb.cpu().numpy(), exp)
 
 
+@pytest.mark.parametrize("W,H,n", [(2, 2, 1), (70, 19, 3), (641, 83, 2), (64, 16, 1)])
+def test_color_prep_ragged_sizes(W, H, n):
+    # tiles of 64 x 16 with a ragged last row and column, images narrower than
+    # the filters' reach (edge clamping), several frames in one call
+    _say(f"colour prep {W}x{H}, {n} frames")
+    rng = np.random.default_rng(W * 1000 + H)
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    imgs[-1] = np.clip(imgs[-1].astype(np.int64) // 4 + 100, 0, 255).astype(np.uint8)
+    sharp, wb = scsurf.color_prep(torch.from_numpy(imgs).cuda())
+    np.testing.assert_array_equal(sharp.cpu().numpy(), np.stack([oracle.sharpen(im) for im in imgs]))
+    np.testing.assert_array_equal(wb.cpu().numpy(), np.array([1.0 - oracle.blur(im)[0] for im in imgs]))
+
+
 def _check_fuse(wl, z, rgb, R, t):
     kf = scsurf.kf_fuse(torch.from_numpy(z).cuda(), torch.from_numpy(rgb).cuda(), R, t, wl.intr)
     ref = oracle.kf_fuse(z, rgb, wl.intr, R, t)
