@@ -66,43 +66,66 @@ __device__ inline bool project(const sc_intrinsics& in, const float q[3], float&
 // depth weight
 // ---------------------------------------------------------------------------
 
-__global__ void depth_weight_kernel(const float* __restrict__ Z, int n, sc_intrinsics in, sc_fuse_params p,
-                                    float* __restrict__ wz)
+// One 64 x 16 tile per workgroup: the back-projection of every pixel of the
+// tile and a one-pixel halo is computed once into LDS (two divisions per
+// pixel), and each pixel reads its four neighbours' points from there; the
+// operations are those of the per-pixel definition, so the result is the
+// same bit for bit.
+constexpr int kDwTW = 64, kDwTH = 16;
+constexpr int kDwLW = kDwTW + 2, kDwLH = kDwTH + 2;
+
+__global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restrict__ Z, int n, sc_intrinsics in,
+                                                           sc_fuse_params p, int tiles_x, int tiles,
+                                                           float* __restrict__ wz)
 {
+    __shared__ float sx[kDwLH][kDwLW], sy[kDwLH][kDwLW], sz[kDwLH][kDwLW];
     const int W = in.width, H = in.height;
     const int64_t np = (int64_t)W * H;
-    const int f = blockIdx.y;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n || idx >= np) return;
-    const int u = (int)(idx % W), v = (int)(idx / W);
+    const int f = blockIdx.y, tile = blockIdx.x;
+    if (f >= n || tile >= tiles) return;
+    const int u0 = (tile % tiles_x) * kDwTW, v0 = (tile / tiles_x) * kDwTH;
     const float* Zf = Z + (size_t)f * np;
-    float out = 0.0f;
-    const float z = Zf[idx];
-    if (zvalid(z, p.z_min, p.z_max) && u >= 1 && u <= W - 2 && v >= 1 && v <= H - 2) {
-        const float zl = Zf[idx - 1], zr = Zf[idx + 1], zu = Zf[idx - W], zd = Zf[idx + W];
-        const bool ok = zvalid(zl, p.z_min, p.z_max) && zvalid(zr, p.z_min, p.z_max) && zvalid(zu, p.z_min, p.z_max) &&
-                        zvalid(zd, p.z_min, p.z_max);
-        const float th = p.disc_rel * z;
-        if (ok && !(fabsf(zl - z) > th) && !(fabsf(zr - z) > th) && !(fabsf(zu - z) > th) && !(fabsf(zd - z) > th)) {
-            float Pl[3], Pr[3], Pu[3], Pd[3];
-            backproject((float)(u - 1), (float)v, zl, in, Pl);
-            backproject((float)(u + 1), (float)v, zr, in, Pr);
-            backproject((float)u, (float)(v - 1), zu, in, Pu);
-            backproject((float)u, (float)(v + 1), zd, in, Pd);
-            const float a0 = Pr[0] - Pl[0], a1 = Pr[1] - Pl[1], a2 = Pr[2] - Pl[2];
-            const float b0 = Pd[0] - Pu[0], b1 = Pd[1] - Pu[1], b2 = Pd[2] - Pu[2];
-            const float nx = a1 * b2 - a2 * b1;
-            const float ny = a2 * b0 - a0 * b2;
-            const float nz = a0 * b1 - a1 * b0;
-            const float nn = (nx * nx + ny * ny) + nz * nz;
-            if (nn > 0.0f) {
-                const float c = fabsf(nz) / sqrtf(nn);
-                const float w = c / (z * z);
-                out = rintf(w * kWeightScale) / kWeightScale;
+    for (int q = threadIdx.x; q < kDwLW * kDwLH; q += blockDim.x) {
+        const int i = q % kDwLW, j = q / kDwLW;
+        const int uu = u0 - 1 + i, vv = v0 - 1 + j;
+        float P[3] = {0.0f, 0.0f, 0.0f};
+        if (uu >= 0 && uu < W && vv >= 0 && vv < H) backproject((float)uu, (float)vv, Zf[(size_t)vv * W + uu], in, P);
+        sx[j][i] = P[0];
+        sy[j][i] = P[1];
+        sz[j][i] = P[2];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kDwTW - 1), ty = threadIdx.x / kDwTW;
+    const int u = u0 + tx, i = tx + 1;
+#pragma unroll 1
+    for (int r = 0; r < kDwTH / 4; ++r) {
+        const int v = v0 + ty + 4 * r, j = ty + 4 * r + 1;
+        if (u >= W || v >= H) continue;
+        float out = 0.0f;
+        const float z = sz[j][i];
+        if (zvalid(z, p.z_min, p.z_max) && u >= 1 && u <= W - 2 && v >= 1 && v <= H - 2) {
+            const float zl = sz[j][i - 1], zr = sz[j][i + 1], zu = sz[j - 1][i], zd = sz[j + 1][i];
+            const bool ok = zvalid(zl, p.z_min, p.z_max) && zvalid(zr, p.z_min, p.z_max) &&
+                            zvalid(zu, p.z_min, p.z_max) && zvalid(zd, p.z_min, p.z_max);
+            const float th = p.disc_rel * z;
+            if (ok && !(fabsf(zl - z) > th) && !(fabsf(zr - z) > th) && !(fabsf(zu - z) > th) &&
+                !(fabsf(zd - z) > th)) {
+                // neighbours (u - 1, v), (u + 1, v), (u, v - 1), (u, v + 1)
+                const float a0 = sx[j][i + 1] - sx[j][i - 1], a1 = sy[j][i + 1] - sy[j][i - 1], a2 = zr - zl;
+                const float b0 = sx[j + 1][i] - sx[j - 1][i], b1 = sy[j + 1][i] - sy[j - 1][i], b2 = zd - zu;
+                const float nx = a1 * b2 - a2 * b1;
+                const float ny = a2 * b0 - a0 * b2;
+                const float nz = a0 * b1 - a1 * b0;
+                const float nn = (nx * nx + ny * ny) + nz * nz;
+                if (nn > 0.0f) {
+                    const float c = fabsf(nz) / sqrtf(nn);
+                    const float w = c / (z * z);
+                    out = rintf(w * kWeightScale) / kWeightScale;
+                }
             }
         }
+        wz[(size_t)f * np + (size_t)v * W + u] = out;
     }
-    wz[(size_t)f * np + idx] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -538,9 +561,9 @@ static void rel_pose(const sc_pose& A, const sc_pose& B, float out[12])
 static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& in, const sc_fuse_params& p, float* out,
                                 hipStream_t s)
 {
-    const int64_t np = (int64_t)in.width * in.height;
-    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n);
-    depth_weight_kernel<<<grid, 256, 0, s>>>(depth, n, in, p, out);
+    const int tiles_x = (in.width + kDwTW - 1) / kDwTW;
+    const int tiles = tiles_x * ((in.height + kDwTH - 1) / kDwTH);
+    depth_weight_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(depth, n, in, p, tiles_x, tiles, out);
 }
 
 static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, double* wb, hipStream_t s)

@@ -45,6 +45,29 @@ def test_color_prep_bit_exact(c1):
     np.testing.assert_array_equal(wb.cpu().numpy(), exp)
 
 
+@pytest.mark.parametrize("W,H,n", [(3, 3, 1), (70, 19, 3), (641, 83, 2), (64, 16, 1)])
+def test_depth_weight_ragged_sizes(W, H, n):
+    # 64 x 16 tiles with a ragged last row and column; a tilted plane with
+    # noise, depth steps (discontinuity rejection) and holes / out-of-range
+    # depths (validity), several frames in one call
+    _say(f"depth weight {W}x{H}, {n} frames")
+    rng = np.random.default_rng(W * 7 + H)
+    intr = synth.Intrinsics(W, H, 0.8 * W, 0.8 * W, 0.5 * (W - 1), 0.5 * (H - 1))
+    uu, vv = np.meshgrid(np.arange(W), np.arange(H))
+    z = np.empty((n, H, W), np.float32)
+    for f in range(n):
+        zf = 1.2 + 0.002 * (f + 1) * uu + 0.003 * vv + 0.001 * rng.standard_normal((H, W))
+        zf[:, W // 2:] += 0.4 * (f % 2)
+        zf[rng.random((H, W)) < 0.05] = 0.0
+        zf[rng.random((H, W)) < 0.02] = 9.0
+        z[f] = zf
+    got = scsurf.depth_weight(torch.from_numpy(z).cuda(), intr).cpu().numpy()
+    exp = np.stack([oracle.depth_weight(z[f], intr) for f in range(n)])
+    np.testing.assert_array_equal(got, exp)
+    if W >= 64:
+        assert (exp > 0).mean() > 0.5
+
+
 @pytest.mark.parametrize("W,H,n", [(2, 2, 1), (70, 19, 3), (641, 83, 2), (64, 16, 1)])
 def test_color_prep_ragged_sizes(W, H, n):
     # tiles of 64 x 16 with a ragged last row and column, images narrower than
