@@ -617,6 +617,7 @@ sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* 
     ok = ok && hipMalloc(&offsets, sizeof(uint64_t) * n) == hipSuccess;
     ok = ok && hipMalloc(&sums, sizeof(uint64_t) * wgs) == hipSuccess;
     ok = ok && hipMalloc(&d_total, sizeof(uint64_t)) == hipSuccess;
+    const bool allocated = ok;
     uint64_t total = 0;
     if (ok) {
         MeshOut cnt{nullptr, nullptr, counts, nullptr, 0};
@@ -636,7 +637,7 @@ sc_status sc_volume_mesh(sc_volume* vol, void* stream, float* tri_xyz, int32_t* 
     (void)hipFree(offsets);
     (void)hipFree(sums);
     (void)hipFree(d_total);
-    if (!ok) return SC_EDEVICE;
+    if (!ok) return allocated ? SC_EDEVICE : SC_ENOMEM;
     *n_tri = (int64_t)total;
     return SC_OK;
 }
@@ -658,6 +659,7 @@ sc_status sc_mesh_vertices(const float* tri_xyz, const int32_t* tri_keys, int64_
     bool ok = hipMalloc(&table, sizeof(uint64_t) * slots) == hipSuccess;
     ok = ok && hipMalloc(&d_count, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc(&d_err, sizeof(int)) == hipSuccess;
+    const bool allocated = ok;
     unsigned long long count = 0;
     int err = 0;
     if (ok) {
@@ -676,7 +678,7 @@ sc_status sc_mesh_vertices(const float* tri_xyz, const int32_t* tri_keys, int64_
     (void)hipFree(table);
     (void)hipFree(d_count);
     (void)hipFree(d_err);
-    if (!ok) return SC_EDEVICE;
+    if (!ok) return allocated ? SC_EDEVICE : SC_ENOMEM;
     if (err) return SC_ERANGE;
     *n_vert = (int64_t)count;
     return SC_OK;
@@ -697,7 +699,7 @@ sc_status sc_nn_distance(const float* ref, int64_t n_ref, const float* query, in
     g.mask = slots - 1;
     uint32_t* slot_of = nullptr;
     uint32_t* total = nullptr;
-    bool ok = true;
+    bool ok = true, allocated = true;
     if (n_ref > 0) {
         ok = ok && hipMalloc(&g.keys, sizeof(uint64_t) * slots) == hipSuccess;
         ok = ok && hipMalloc(&g.cnt, sizeof(uint32_t) * slots) == hipSuccess;
@@ -706,6 +708,7 @@ sc_status sc_nn_distance(const float* ref, int64_t n_ref, const float* query, in
         ok = ok && hipMalloc(&g.pts, sizeof(float) * 3 * (size_t)n_ref) == hipSuccess;
         ok = ok && hipMalloc(&slot_of, sizeof(uint32_t) * (size_t)n_ref) == hipSuccess;
         ok = ok && hipMalloc(&total, sizeof(uint32_t)) == hipSuccess;
+        allocated = ok;
         if (ok) {
             fill_u64(g.keys, kKeyEmpty, slots, s);
             fill_u32(g.cnt, 0u, slots, s);
@@ -730,7 +733,7 @@ sc_status sc_nn_distance(const float* ref, int64_t n_ref, const float* query, in
     (void)hipFree(g.pts);
     (void)hipFree(slot_of);
     (void)hipFree(total);
-    return ok ? SC_OK : SC_EDEVICE;
+    return ok ? SC_OK : (allocated ? SC_EDEVICE : SC_ENOMEM);
 }
 
 }  // extern "C"
