@@ -151,6 +151,17 @@ def dptr(t: torch.Tensor, dtype=None, what="tensor") -> int:
     return t.data_ptr()
 
 
+def _check_shape(t: torch.Tensor, shape, what: str):
+    """The library takes plain pointers and sizes: shapes are checked here,
+    before a kernel could read past a buffer."""
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _image_size(intr):
+    return int(intr.height), int(intr.width)
+
+
 def intrinsics(intr) -> sc_intrinsics:
     return sc_intrinsics(float(intr.fx), float(intr.fy), float(intr.cx), float(intr.cy), int(intr.width),
                          int(intr.height))
@@ -187,6 +198,22 @@ class Keyframe:
     color: torch.Tensor
     packed: Optional[torch.Tensor] = None  # (H,W,4) int32 interleaved copy from keyframe_pack
 
+    def image_size(self):
+        """(H, W) after checking that the keyframe's tensors agree."""
+        if self.depth.dim() != 2:
+            raise ValueError("keyframe depth must be (H, W)")
+        H, W = (int(x) for x in self.depth.shape)
+        _check_shape(self.weight, (H, W), "keyframe weight")
+        if self.color.dtype == torch.uint8:
+            _check_shape(self.color, (H, W, 4), "RGBA8 keyframe colour")
+        elif self.color.dtype == torch.float32:
+            _check_shape(self.color, (H, W, 3), "FP32 keyframe colour")
+        else:
+            raise ValueError("keyframe colour must be uint8 (H, W, 4) or float32 (H, W, 3)")
+        if self.packed is not None:
+            _check_shape(self.packed, (H, W, 4), "packed keyframe")
+        return H, W
+
     def c(self) -> sc_keyframe:
         packed = None if self.packed is None else dptr(self.packed, torch.int32, "packed")
         return sc_keyframe(dptr(self.depth, torch.float32, "depth"), dptr(self.weight, torch.float32, "weight"),
@@ -200,6 +227,12 @@ class KeyframeSet:
 
     def __init__(self, kfs):
         self.kfs = list(kfs)
+        sizes = {k.image_size() for k in self.kfs}
+        kinds = {k.color.dtype for k in self.kfs}
+        if len(sizes) > 1 or len(kinds) > 1:
+            raise ValueError("the keyframes of one call must share their image size and colour type")
+        self.size = sizes.pop() if sizes else None
+        self.color_dtype = kinds.pop() if kinds else None
         self.arr = (sc_keyframe * len(self.kfs))()
         for i, k in enumerate(self.kfs):
             self.arr[i] = k.c()
@@ -208,10 +241,8 @@ class KeyframeSet:
         return len(self.kfs)
 
 
-def keyframes(kfs):
-    if isinstance(kfs, KeyframeSet):
-        return kfs.arr
-    return KeyframeSet(kfs).arr
+def keyframes(kfs) -> KeyframeSet:
+    return kfs if isinstance(kfs, KeyframeSet) else KeyframeSet(kfs)
 
 
 def fuse_params(z_min=0.3, z_max=4.0, disc_rel=0.05, occ_rel=0.05) -> sc_fuse_params:
@@ -289,15 +320,27 @@ class Volume:
         C = field.get("C")
         if C is not None:
             C = C.contiguous()
+        if xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("blocks must be (n, 3)")
         if D.shape != (n, 512) or W.shape != (n, 512):
             raise ValueError("D and W must be (n, 512)")
+        if C is not None:
+            if self.color_mode == COLOR_RGBA8:
+                if C.dtype != torch.uint8:
+                    raise ValueError("RGBA8 colour must be uint8")
+                _check_shape(C, (n, 512, 4), "C")
+            else:
+                if C.dtype != torch.float32:
+                    raise ValueError("FP32 colour must be float32")
+                _check_shape(C, (n, 3, 512), "C")
         check(lib().sc_volume_import(self._h, stream_handle(stream), xyz.data_ptr() if n else None,
                                      D.data_ptr() if n else None, W.data_ptr() if n else None,
                                      C.data_ptr() if (C is not None and n) else None, n), "sc_volume_import")
 
     def mesh(self, stream=None):
         """Marching Cubes of the volume: (tri_xyz (T,3,3) f32, tri_keys
-        (T,3,4) int32) device tensors, triangles in no fixed order."""
+        (T,3,4) int32) device tensors, triangles in the library's fixed order
+        (blocks in pool order, cubes in voxel order)."""
         n = ctypes.c_int64()
         check(lib().sc_volume_mesh(self._h, stream_handle(stream), None, None, 0, ctypes.byref(n)), "sc_volume_mesh")
         T = n.value
@@ -325,17 +368,33 @@ class Volume:
         check(e, "device error")
         return n
 
+    def _check_keyframes(self, kset: KeyframeSet, intr, *pose_sets):
+        """Keyframe images of the intrinsics' size, colour of the volume's
+        mode, one pose per keyframe in each pose array."""
+        if kset.size is not None and kset.size != _image_size(intr):
+            raise ValueError(f"keyframes are {kset.size}, the intrinsics say {_image_size(intr)}")
+        want = torch.uint8 if self.color_mode == COLOR_RGBA8 else torch.float32
+        if kset.color_dtype is not None and kset.color_dtype != want:
+            raise ValueError(f"this volume takes {want} keyframe colour, got {kset.color_dtype}")
+        for ps in pose_sets:
+            if len(ps) != len(kset):
+                raise ValueError(f"{len(ps)} poses for {len(kset)} keyframes")
+
     def integrate(self, kf: Keyframe, intr, R, t, stream=None):
+        self._check_keyframes(KeyframeSet([kf]), intr)
         k = kf.c()
         check(lib().tsdf_integrate(self._h, ctypes.byref(k), ctypes.byref(intrinsics(intr)), ctypes.byref(pose(R, t)),
                                    stream_handle(stream)), "tsdf_integrate")
 
     def deintegrate(self, kf: Keyframe, intr, R, t, stream=None):
+        self._check_keyframes(KeyframeSet([kf]), intr)
         k = kf.c()
         check(lib().tsdf_deintegrate(self._h, ctypes.byref(k), ctypes.byref(intrinsics(intr)),
                                      ctypes.byref(pose(R, t)), stream_handle(stream)), "tsdf_deintegrate")
 
     def hash_alloc(self, block_xyz: torch.Tensor, want_slots=True, stream=None):
+        if block_xyz.dim() != 2 or block_xyz.shape[1] != 3:
+            raise ValueError("block_xyz must be (n, 3)")
         n = block_xyz.shape[0]
         slots = torch.empty(n, dtype=torch.int32, device=block_xyz.device) if want_slots else None
         check(lib().hash_alloc(self._h, dptr(block_xyz, torch.int32, "block_xyz"), n,
@@ -343,9 +402,11 @@ class Volume:
         return slots
 
     def _reint(self, fn, kfs, intr, T_int, T_new, m, mode, stream):
-        karr = keyframes(kfs)
+        kset = keyframes(kfs)
         Ti = poses(*T_int)
         Tn = poses(*T_new)
+        self._check_keyframes(kset, intr, Ti, Tn)
+        karr = kset.arr
         sel = (ctypes.c_int32 * len(kfs))()
         ns = ctypes.c_int32()
         check(fn(self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), Ti, Tn, m, mode, sel, ctypes.byref(ns),
@@ -371,12 +432,13 @@ class Volume:
         return (s.vpl, s.waves_per_wg, s.wgs_per_cu, s.compact)
 
     def autotune(self, kfs, intr, T_int, T_new, m, mode=SEL_EQ3, stream=None):
-        karr = keyframes(kfs)
+        kset = keyframes(kfs)
+        Ti, Tn = poses(*T_int), poses(*T_new)
+        self._check_keyframes(kset, intr, Ti, Tn)
         best = sc_schedule()
         ms = ctypes.c_float()
-        check(lib().sc_autotune(self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), poses(*T_int),
-                                poses(*T_new), m, mode, ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)),
-              "sc_autotune")
+        check(lib().sc_autotune(self._h, kset.arr, len(kfs), ctypes.byref(intrinsics(intr)), Ti, Tn, m, mode,
+                                ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)), "sc_autotune")
         return (best.vpl, best.waves_per_wg, best.wgs_per_cu, best.compact), float(ms.value)
 
     def batch_timing(self, capacity: int):
@@ -398,9 +460,21 @@ class Volume:
         return tuple(int(x) for x in out)
 
     def integrate_backward(self, kfs, intr, R, t, grad_D, grad_C, grad_depth, grad_color, grad_xi, stream=None):
-        karr = keyframes(kfs)
+        kset = keyframes(kfs)
+        T = poses(R, t)
+        self._check_keyframes(kset, intr, T)
+        n_blocks, _ = self.query(stream)
+        H, W = _image_size(intr)
+        _check_shape(grad_D, (n_blocks, 512), "grad_D")
+        if grad_C is not None:
+            _check_shape(grad_C, (n_blocks, 3, 512), "grad_C")
+        _check_shape(grad_depth, (len(kset), H, W), "grad_depth")
+        if grad_color is not None:
+            _check_shape(grad_color, (len(kset), H, W, 3), "grad_color")
+        _check_shape(grad_xi, (len(kset), 6), "grad_xi")
+        karr = kset.arr
         check(lib().tsdf_integrate_backward(
-            self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), poses(R, t), dptr(grad_D, torch.float32, "grad_D"),
+            self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), T, dptr(grad_D, torch.float32, "grad_D"),
             dptr(grad_C, torch.float32, "grad_C") if grad_C is not None else None,
             dptr(grad_depth, torch.float32, "grad_depth"),
             dptr(grad_color, torch.float32, "grad_color") if grad_color is not None else None,
@@ -445,6 +519,8 @@ def keyframe_pack(kf: Keyframe, stream=None) -> Keyframe:
 def overlap(depth: torch.Tensor, intr, R, t, R_ref, t_ref, z_min=0.3, z_max=4.0, stream=None):
     """(valid, visible) pixel counts of a frame's depth against a reference
     view (the overlap strategy of Sec. 4.2).  Synchronises."""
+    if depth.numel() != int(intr.width) * int(intr.height):
+        raise ValueError(f"depth has {depth.numel()} pixels, the intrinsics say {intr.width} x {intr.height}")
     counts = torch.empty(2, dtype=torch.int32, device=depth.device)
     check(lib().sc_overlap(dptr(depth, torch.float32, "depth"), ctypes.byref(intrinsics(intr)),
                            ctypes.byref(pose(R, t)), ctypes.byref(pose(R_ref, t_ref)), float(z_min), float(z_max),
@@ -455,6 +531,7 @@ def overlap(depth: torch.Tensor, intr, R, t, R_ref, t_ref, z_min=0.3, z_max=4.0,
 
 def depth_weight(depth: torch.Tensor, intr, params=None, stream=None) -> torch.Tensor:
     depth = depth if depth.dim() == 3 else depth[None]
+    _check_shape(depth, (depth.shape[0],) + _image_size(intr), "depth")
     out = torch.empty_like(depth)
     p = params or fuse_params()
     check(lib().sc_depth_weight(dptr(depth, torch.float32, "depth"), depth.shape[0], ctypes.byref(intrinsics(intr)),
@@ -464,6 +541,8 @@ def depth_weight(depth: torch.Tensor, intr, params=None, stream=None) -> torch.T
 
 def color_prep(rgb: torch.Tensor, stream=None):
     rgb = rgb if rgb.dim() == 4 else rgb[None]
+    if rgb.dim() != 4 or rgb.shape[3] != 3:
+        raise ValueError("rgb must be (n, H, W, 3) or (H, W, 3)")
     n, H, W, _ = rgb.shape
     sharp = torch.empty((n, H, W, 3), dtype=torch.uint16, device=rgb.device)
     wb = torch.empty(n, dtype=torch.float64, device=rgb.device)
@@ -474,13 +553,20 @@ def color_prep(rgb: torch.Tensor, stream=None):
 
 def kf_fuse(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref=0, stream=None) -> Keyframe:
     """Fuses frames (n,H,W) / (n,H,W,3) at poses (R, t) into one keyframe."""
+    if depth.dim() != 3:
+        raise ValueError("depth must be (n, H, W)")
     n, H, W = depth.shape
+    _check_shape(depth, (n,) + _image_size(intr), "depth")
+    _check_shape(rgb, (n, H, W, 3), "rgb")
+    T = poses(R, t)
+    if len(T) != n:
+        raise ValueError(f"{len(T)} poses for {n} frames")
     dev = depth.device
     kd = torch.empty((H, W), dtype=torch.float32, device=dev)
     kw = torch.empty((H, W), dtype=torch.float32, device=dev)
     kc = torch.empty((H, W, 4), dtype=torch.uint8, device=dev)
     p = params or fuse_params()
-    check(lib().kf_fuse(dptr(depth, torch.float32, "depth"), dptr(rgb, torch.uint8, "rgb"), poses(R, t), n, ref,
+    check(lib().kf_fuse(dptr(depth, torch.float32, "depth"), dptr(rgb, torch.uint8, "rgb"), T, n, ref,
                         ctypes.byref(intrinsics(intr)), ctypes.byref(p), kd.data_ptr(), kw.data_ptr(), kc.data_ptr(),
                         stream_handle(stream)), "kf_fuse")
     return Keyframe(kd, kw, kc)

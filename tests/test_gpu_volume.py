@@ -178,10 +178,35 @@ def test_argument_errors_enqueue_nothing():
     with pytest.raises(scsurf.ScError):
         scsurf.Volume(S, MU, 1000, 1 << 10)  # not a power of two
     vol = scsurf.Volume(S, MU, 1 << 10, 1 << 10)
+    # zero-size images agree with zero-size intrinsics, so the binding passes
+    # them on and the library's own check rejects them
     intr = synth.Intrinsics(0, 0, 1.0, 1.0, 0.0, 0.0)
-    z = torch.zeros((4, 4), device="cuda")
+    z = torch.zeros((0, 0), device="cuda")
     with pytest.raises(scsurf.ScError):
-        vol.integrate(scsurf.Keyframe(z, z, torch.zeros((4, 4, 4), dtype=torch.uint8, device="cuda")), intr,
+        vol.integrate(scsurf.Keyframe(z, z, torch.zeros((0, 0, 4), dtype=torch.uint8, device="cuda")), intr,
                       np.eye(3), np.zeros(3))
+    assert vol.query() == (0, 0)
+    vol.close()
+
+
+def test_binding_rejects_mismatched_arguments(c1):
+    wl, kf, T0, T1 = c1
+    _say("binding checks: image size, colour type, pose counts, import layout")
+    dk, dkf = _dev_kf(kf), _dev_kf(as_f32_color(kf), f32=True)
+    vol = scsurf.Volume(S, MU, 1 << 16, 1 << 15)
+    small = synth.Intrinsics(wl.intr.width - 1, wl.intr.height, wl.intr.fx, wl.intr.fy, wl.intr.cx, wl.intr.cy)
+    with pytest.raises(ValueError, match="intrinsics"):
+        vol.integrate(dk, small, *T0)
+    with pytest.raises(ValueError, match="colour"):
+        vol.integrate(dkf, wl.intr, *T0)
+    R2, t2 = np.repeat(T0[0][None], 2, 0), np.repeat(np.asarray(T0[1])[None], 2, 0)
+    with pytest.raises(ValueError, match="poses"):
+        vol.reintegrate_batch([dk], wl.intr, (R2, t2), (R2[:1], t2[:1]), 1)
+    f = {"blocks": torch.zeros((2, 3), dtype=torch.int32, device="cuda"),
+         "D": torch.zeros((2, 512), device="cuda"), "W": torch.zeros((2, 512), device="cuda"),
+         "C": torch.zeros((2, 512, 3), dtype=torch.uint8, device="cuda")}
+    with pytest.raises(ValueError, match="C"):
+        vol.import_field(f)
+    # nothing reached the device
     assert vol.query() == (0, 0)
     vol.close()
