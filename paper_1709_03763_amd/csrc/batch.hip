@@ -77,6 +77,43 @@ __device__ inline int mask_count(const CandDev& cd, uint32_t h)
     return c;
 }
 
+// Orders this wavefront's LDS accesses: the lanes that write a queue entry or
+// a voxel are not the lanes that read it next.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Occupied buckets of one wavefront's stretch [base, base + kCollect) of the
+// candidate table (clipped at b1), compacted into the wavefront's LDS list in
+// bucket order; returns their number.  All key loads issue together, so the
+// scans below wait for one load latency per stretch instead of one per
+// bucket a lane visits.  Every lane of the wavefront takes part.
+constexpr int kCollectPerLane = 8;
+constexpr int kCollect = 64 * kCollectPerLane;
+
+__device__ inline int wave_collect(const CandDev& cd, uint32_t base, uint32_t b1, uint32_t* list, int lane)
+{
+    uint64_t key[kCollectPerLane];
+#pragma unroll
+    for (int k = 0; k < kCollectPerLane; ++k) {
+        const uint32_t i = base + 64u * k + (uint32_t)lane;
+        key[k] = i < b1 ? cd.keys[i] : kKeyEmpty;
+    }
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < kCollectPerLane; ++k) {
+        const bool occ = key[k] != kKeyEmpty;
+        const uint64_t bal = __ballot(occ);
+        if (occ) list[n + (int)lanes_below(bal)] = base + 64u * k + (uint32_t)lane;
+        n += __popcll(bal);
+    }
+    wave_lds_sync();
+    return n;
+}
+
 // Each workgroup takes a contiguous share of the candidate table's buckets,
 // so the histogram and the scatter below see the same buckets per workgroup.
 __device__ inline void wg_share(uint32_t n, uint32_t& b0, uint32_t& b1)
@@ -91,12 +128,17 @@ __device__ inline void wg_share(uint32_t n, uint32_t& b0, uint32_t& b1)
 __global__ __launch_bounds__(256) void hist_kernel(CandDev cd, int n_bins)
 {
     __shared__ uint32_t h[kMaxBatchOps + 1];
+    __shared__ uint32_t lst[4][kCollect];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t b0, b1;
     wg_share(cd.mask_bits + 1u, b0, b1);
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
-        if (cd.keys[i] != kKeyEmpty) atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
+    for (uint32_t base = b0 + wave * kCollect; base < b1; base += 4 * kCollect) {
+        const int n = wave_collect(cd, base, b1, lst[wave], lane);
+        for (int r = lane; r < n; r += 64) atomicAdd(h + min(mask_count(cd, lst[wave][r]), n_bins - 1), 1u);
+        wave_lds_sync();
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
         if (h[c]) atomicAdd(cd.bins + c, h[c]);
@@ -142,29 +184,39 @@ __global__ __launch_bounds__(1024) void scan_kernel(CandDev cd, int n_bins)
 // Scatter into operation-count order: each workgroup reserves one range per
 // count it holds, then places its buckets inside those ranges, with each
 // block's key and current pool slot (looked up here, in parallel, so the
-// voxel pass starts a block with one round of independent loads).
+// voxel pass starts a block with one round of independent loads).  Both
+// passes over the workgroup's buckets compact the occupied ones first.
 __global__ __launch_bounds__(256) void scatter_kernel(CandDev cd, VolDev v, int n_bins)
 {
     __shared__ uint32_t h[kMaxBatchOps + 1];
+    __shared__ uint32_t lst[4][kCollect];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t b0, b1;
     wg_share(cd.mask_bits + 1u, b0, b1);
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x) h[c] = 0u;
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
-        if (cd.keys[i] != kKeyEmpty) atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
+    for (uint32_t base = b0 + wave * kCollect; base < b1; base += 4 * kCollect) {
+        const int n = wave_collect(cd, base, b1, lst[wave], lane);
+        for (int r = lane; r < n; r += 64) atomicAdd(h + min(mask_count(cd, lst[wave][r]), n_bins - 1), 1u);
+        wave_lds_sync();
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < n_bins; c += blockDim.x)
         if (h[c]) h[c] = atomicAdd(cd.bins + c, h[c]);
     __syncthreads();
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const uint64_t key = cd.keys[i];
-        if (key == kKeyEmpty) continue;
-        const uint32_t pos = atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
-        int bx, by, bz;
-        unpack_key(key, bx, by, bz);
-        cd.sorted[pos] = i;
-        cd.skey[pos] = key;
-        cd.sslot[pos] = vol_find(v, key, bx, by, bz);
+    for (uint32_t base = b0 + wave * kCollect; base < b1; base += 4 * kCollect) {
+        const int n = wave_collect(cd, base, b1, lst[wave], lane);
+        for (int r = lane; r < n; r += 64) {
+            const uint32_t i = lst[wave][r];
+            const uint64_t key = cd.keys[i];
+            const uint32_t pos = atomicAdd(h + min(mask_count(cd, i), n_bins - 1), 1u);
+            int bx, by, bz;
+            unpack_key(key, bx, by, bz);
+            cd.sorted[pos] = i;
+            cd.skey[pos] = key;
+            cd.sslot[pos] = vol_find(v, key, bx, by, bz);
+        }
+        wave_lds_sync();
     }
 }
 
@@ -340,15 +392,6 @@ template <int CM, int TV>
 constexpr int compact_wave_bytes()
 {
     return 512 * (8 + 4 + (CM == SC_COLOR_RGBA8 ? 4 : 24)) + 64 * TV * (2 + 4 + 4 + 4);
-}
-
-// Orders this wavefront's LDS accesses: the lanes that write a queue entry or
-// a voxel are not the lanes that read it next.
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Persistent voxel pass, compacting: one wavefront per block with the block
