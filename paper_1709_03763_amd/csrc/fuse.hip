@@ -73,6 +73,7 @@ __device__ inline bool project(const sc_intrinsics& in, const float q[3], float&
 // same bit for bit.
 constexpr int kDwTW = 64, kDwTH = 16;
 constexpr int kDwLW = kDwTW + 2, kDwLH = kDwTH + 2;
+constexpr int kDwStage = (kDwLW * kDwLH + 255) / 256;  // staged pixels per thread (256 threads)
 
 __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restrict__ Z, int n, sc_intrinsics in,
                                                            sc_fuse_params p, int tiles_x, int tiles,
@@ -85,14 +86,26 @@ __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restri
     if (f >= n || tile >= tiles) return;
     const int u0 = (tile % tiles_x) * kDwTW, v0 = (tile / tiles_x) * kDwTH;
     const float* Zf = Z + (size_t)f * np;
-    for (int q = threadIdx.x; q < kDwLW * kDwLH; q += blockDim.x) {
-        const int i = q % kDwLW, j = q / kDwLW;
-        const int uu = u0 - 1 + i, vv = v0 - 1 + j;
-        float P[3] = {0.0f, 0.0f, 0.0f};
-        if (uu >= 0 && uu < W && vv >= 0 && vv < H) backproject((float)uu, (float)vv, Zf[(size_t)vv * W + uu], in, P);
-        sx[j][i] = P[0];
-        sy[j][i] = P[1];
-        sz[j][i] = P[2];
+    // staging: every depth load of a thread issues before the divisions
+    float zs[kDwStage];
+#pragma unroll
+    for (int k = 0; k < kDwStage; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        const int uu = u0 - 1 + q % kDwLW, vv = v0 - 1 + q / kDwLW;
+        zs[k] = (q < kDwLW * kDwLH && uu >= 0 && uu < W && vv >= 0 && vv < H) ? Zf[(size_t)vv * W + uu] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kDwStage; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        if (q < kDwLW * kDwLH) {
+            const int i = q % kDwLW, j = q / kDwLW;
+            const int uu = u0 - 1 + i, vv = v0 - 1 + j;
+            float P[3] = {0.0f, 0.0f, 0.0f};
+            if (uu >= 0 && uu < W && vv >= 0 && vv < H) backproject((float)uu, (float)vv, zs[k], in, P);
+            sx[j][i] = P[0];
+            sy[j][i] = P[1];
+            sz[j][i] = P[2];
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x & (kDwTW - 1), ty = threadIdx.x / kDwTW;
@@ -183,21 +196,27 @@ __device__ inline int luma(uint32_t px) { return (77 * (int)(px & 255u) + 150 * 
 // Colour pre-processing of one 64 x 16 tile of one frame.  The tile and a
 // halo (2 pixels for the 5-tap binomial, 5 before and 4 after for the 9-tap
 // re-blur box) are staged in LDS with coordinates clamped to the image, which
-// is the edge rule of both filters; each thread then produces four pixels of
-// the unsharp mask and adds their re-blur terms to four int64 sums, reduced
-// over the workgroup and stored as the tile's partial sums (no atomics).
+// is the edge rule of both filters.  The binomial runs separably on pixels
+// packed as R | G << 16 | B << 32: every channel's weighted sum stays below
+// 16 * 16 * 255 < 2^16, so the 16-bit lanes never carry into each other and
+// the sums are the per-channel integers.  Each thread then produces four
+// pixels of the unsharp mask and adds their re-blur terms to four int64
+// sums, reduced over the workgroup and stored as the tile's partial sums (no
+// atomics).
 //   sums k = 0..3: sF_h, sV_h, sF_v, sV_v, the 9x-scaled horizontal and
 //   vertical variation of the frame and of its re-blurred copy (the box
 //   difference telescopes to two samples).
 constexpr int kPrepTW = 64, kPrepTH = 16;
 constexpr int kPrepLW = kPrepTW + 9, kPrepLH = kPrepTH + 9;
 constexpr int kPrepHalo = 5;
+constexpr int kPrepStage = (kPrepLW * kPrepLH + 255) / 256;  // staged pixels per thread (256 threads)
 
 __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H,
                                                          int tiles_x, int tiles, uint16_t* __restrict__ out,
                                                          long long* __restrict__ parts)
 {
-    __shared__ uint32_t pix[kPrepLH][kPrepLW];
+    __shared__ uint64_t pix[kPrepLH][kPrepLW];
+    __shared__ uint64_t hsum[kPrepTH + 4][kPrepTW];  // horizontal binomial of staged rows 3 .. 22
     __shared__ int lum[kPrepLH][kPrepLW];
     __shared__ long long red[4][4];
     const int f = blockIdx.y, tile = blockIdx.x;
@@ -205,43 +224,51 @@ __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restri
     const int u0 = (tile % tiles_x) * kPrepTW, v0 = (tile / tiles_x) * kPrepTH;
     const int64_t np = (int64_t)W * H;
     const uint8_t* C = rgb + (size_t)f * np * 3;
-    for (int p = threadIdx.x; p < kPrepLW * kPrepLH; p += blockDim.x) {
-        const int i = p % kPrepLW, j = p / kPrepLW;
-        const int uu = clampi(u0 - kPrepHalo + i, 0, W - 1), vv = clampi(v0 - kPrepHalo + j, 0, H - 1);
-        const uint8_t* q = C + 3 * ((size_t)vv * W + uu);
-        const uint32_t px = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
-        pix[j][i] = px;
-        lum[j][i] = luma(px);
+    // staging: every load of a thread issues before its first LDS store
+    uint32_t st[kPrepStage];
+#pragma unroll
+    for (int k = 0; k < kPrepStage; ++k) {
+        const int p = (int)threadIdx.x + 256 * k;
+        st[k] = 0u;
+        if (p < kPrepLW * kPrepLH) {
+            const int i = p % kPrepLW, j = p / kPrepLW;
+            const int uu = clampi(u0 - kPrepHalo + i, 0, W - 1), vv = clampi(v0 - kPrepHalo + j, 0, H - 1);
+            const uint8_t* q = C + 3 * ((size_t)vv * W + uu);
+            st[k] = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPrepStage; ++k) {
+        const int p = (int)threadIdx.x + 256 * k;
+        if (p < kPrepLW * kPrepLH) {
+            const int i = p % kPrepLW, j = p / kPrepLW;
+            const uint32_t px = st[k];
+            pix[j][i] = (uint64_t)(px & 255u) | ((uint64_t)((px >> 8) & 255u) << 16) | ((uint64_t)(px >> 16) << 32);
+            lum[j][i] = luma(px);
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < (kPrepTH + 4) * kPrepTW; p += blockDim.x) {
+        const int c = p % kPrepTW, jr = p / kPrepTW;
+        const uint64_t* row = &pix[jr + kPrepHalo - 2][c + kPrepHalo - 2];
+        hsum[jr][c] = (row[0] + 4 * row[1]) + ((6 * row[2] + 4 * row[3]) + row[4]);
     }
     __syncthreads();
     const int tx = threadIdx.x & (kPrepTW - 1), ty = threadIdx.x / kPrepTW;
-    const int g[5] = {1, 4, 6, 4, 1};
     long long acc[4] = {0, 0, 0, 0};
     const int u = u0 + tx, i = tx + kPrepHalo;
 #pragma unroll 1
     for (int r = 0; r < kPrepTH / 4; ++r) {
         const int y = ty + 4 * r, v = v0 + y, j = y + kPrepHalo;
         if (u >= W || v >= H) continue;
-        int S[3] = {0, 0, 0};
-#pragma unroll
-        for (int b = -2; b <= 2; ++b) {
-            int row[3] = {0, 0, 0};
-#pragma unroll
-            for (int a = -2; a <= 2; ++a) {
-                const uint32_t px = pix[j + b][i + a];
-                row[0] += g[a + 2] * (int)(px & 255u);
-                row[1] += g[a + 2] * (int)((px >> 8) & 255u);
-                row[2] += g[a + 2] * (int)(px >> 16);
-            }
-            S[0] += g[b + 2] * row[0];
-            S[1] += g[b + 2] * row[1];
-            S[2] += g[b + 2] * row[2];
-        }
-        const uint32_t c0 = pix[j][i];
+        // staged row j + b is hsum row y + 2 + b
+        const uint64_t S = (hsum[y][tx] + 4 * hsum[y + 1][tx]) +
+                           ((6 * hsum[y + 2][tx] + 4 * hsum[y + 3][tx]) + hsum[y + 4][tx]);
+        const uint64_t c0 = pix[j][i];
         uint16_t* o = out + (size_t)f * np * 3 + 3 * ((size_t)v * W + u);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int val = 512 * (int)((c0 >> (8 * k)) & 255u) - S[k];
+            const int val = 512 * (int)((c0 >> (16 * k)) & 0xFFFFu) - (int)((S >> (16 * k)) & 0xFFFFu);
             o[k] = (uint16_t)clampi(val, 0, 65280);
         }
         const int y0 = lum[j][i];
