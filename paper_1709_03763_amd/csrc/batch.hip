@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
                                                          VolDev v, CandDev cd)
 {
     __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
     __shared__ int next;
     const int tiles = hdr->tiles_x * hdr->tiles_y;
     const int items = hdr->n_ops * tiles;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
         const int tile = it - o * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
-        cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds);
+        cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
         __syncthreads();
         if (threadIdx.x == 0) next = (int)gridDim.x + (int)atomicAdd(cd.counters + 6, 1u);
         __syncthreads();
@@ -75,15 +76,6 @@ __device__ inline int mask_count(const CandDev& cd, uint32_t h)
     int c = 0;
     for (int w = 0; w < cd.words; ++w) c += __popcll(cd.mask[(size_t)h * cd.words + w]);
     return c;
-}
-
-// Orders this wavefront's LDS accesses: the lanes that write a queue entry or
-// a voxel are not the lanes that read it next.
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Occupied buckets of one wavefront's stretch [base, base + kCollect) of the

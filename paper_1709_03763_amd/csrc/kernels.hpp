@@ -42,6 +42,15 @@ __device__ inline uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Orders this wavefront's LDS accesses: the lanes that write a list or queue
+// entry or a voxel are not the lanes that read it next.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Adds k to *ctr once per wavefront; every lane receives the old value.
 __device__ inline uint32_t wave_fetch_add(uint32_t* ctr, uint32_t k, int lane)
 {
@@ -610,7 +619,7 @@ __device__ inline void insert_pixels(uint64_t* lds, const CandDev& cd, const Vol
 // them by scanning the table instead.
 template <int TILE, int CELL>
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
-                                 int ty, int op_bit, uint64_t* lds)
+                                 int ty, int op_bit, uint64_t* lds, uint16_t* idx)
 {
     constexpr int kCells = TILE / CELL;
     constexpr int kThreads = CandCfg<TILE, CELL>::threads;
@@ -677,14 +686,31 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
         }
     }
     __syncthreads();
-    // insert the tile's blocks; new candidates are appended with one atomic
-    // per wavefront (every lane runs the same kSet / kThreads iterations)
+    // insert the tile's blocks: each wavefront first compacts the occupied
+    // entries of its part of the set into its index list (about one in twenty
+    // is occupied), then claims them 64 at a time, so it waits for about one
+    // claim latency rather than one per round holding an occupied entry; new
+    // candidates are appended with one atomic per wavefront (the claim loop's
+    // trip count is the same for every lane)
     const int lane = tid & 63;
-    for (int it = 0; it < kSet / kThreads; ++it) {
-        const uint64_t key = lds[tid + it * kThreads];
+    constexpr int kRounds = kSet / kThreads;
+    uint16_t* wl = idx + (tid >> 6) * (kRounds * 64);
+    int n = 0;
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+        const int e = tid + it * kThreads;
+        const bool occ = lds[e] != kKeyEmpty;
+        const uint64_t bal = __ballot(occ);
+        if (occ) wl[n + (int)lanes_below(bal)] = (uint16_t)e;
+        n += __popcll(bal);
+    }
+    wave_lds_sync();
+    for (int r0 = 0; r0 < n; r0 += 64) {
+        const int r = r0 + lane;
         bool fresh = false;
         int gb = -1;
-        if (key != kKeyEmpty) {
+        if (r < n) {
+            const uint64_t key = lds[wl[r]];
             int bx, by, bz;
             unpack_key(key, bx, by, bz);
             gb = cand_claim(cd, v, key, bx, by, bz, fresh);

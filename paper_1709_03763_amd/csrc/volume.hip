@@ -120,11 +120,12 @@ __global__ void hash_lookup_kernel(VolDev v, const int32_t* xyz, int64_t n, int3
 __global__ __launch_bounds__(256) void cand_plain_kernel(OpDesc op, VolDev v, CandDev cd, int parity)
 {
     __shared__ uint64_t lds[CandCfg<kTilePlain, kCellPlain>::lds_set];
+    __shared__ uint16_t idx[CandCfg<kTilePlain, kCellPlain>::lds_set];
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         cd.counters[1 - parity] = 0u;
         cd.counters[2 + (1 - parity)] = 0u;
     }
-    cand_tile<kTilePlain, kCellPlain>(op, v, cd, cd.counters + parity, blockIdx.x, blockIdx.y, -1, lds);
+    cand_tile<kTilePlain, kCellPlain>(op, v, cd, cd.counters + parity, blockIdx.x, blockIdx.y, -1, lds, idx);
 }
 
 // Applies one operation to one candidate block with one wavefront, eight
