@@ -199,6 +199,35 @@ def test_chunked_batches_match(scene):
     vol.close()
 
 
+def test_widest_batch_matches_plain(scene):
+    """600 operations in one batch of a volume sized for the largest batch
+    (4096 operations, 64 mask words per candidate block): every operation's
+    bit, the count order and the per-voxel operation order hold at that
+    width, and the plain path gives the same bits."""
+    wl, kfs, R, t = scene
+    K = 300
+    idx = np.arange(K) % len(kfs)
+    Rk, tk = synth.perturb_all(R[idx], t[idx], 0.01, 0.5, 17)
+    Rn, tn = synth.perturb_all(Rk, tk, 0.01, 0.5, 18)
+    base = [_dev_kf(k) for k in kfs]
+    dks = [base[i] for i in idx]
+    got = []
+    for path in ("batched", "plain"):
+        _say(f"{K} keyframes, {2 * K} operations in one batch: {path}")
+        vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16, max_batch_ops=4096)
+        for k in range(K):
+            vol.integrate(dks[k], wl.intr, Rk[k], tk[k])
+        fn = vol.reintegrate_batch if path == "batched" else vol.reintegrate_plain
+        order, _ = fn(dks, wl.intr, (Rk, tk), (Rn, tn), K, scsurf.SEL_ALL_ORDERED)
+        assert sorted(order) == list(range(K))
+        vol.check_error()
+        got.append(vol.export_sorted())
+        vol.close()
+    assert (got[0]["W"] > 0).sum() > 10000
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(got[0][key], got[1][key])
+
+
 def test_autotune_leaves_volume_unchanged(scene):
     wl, kfs, R, t = scene
     Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 9)
