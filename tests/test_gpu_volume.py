@@ -210,3 +210,33 @@ def test_binding_rejects_mismatched_arguments(c1):
     # nothing reached the device
     assert vol.query() == (0, 0)
     vol.close()
+
+
+def test_empty_keyframe_touches_nothing(c1):
+    """A keyframe without a valid pixel allocates and changes nothing, alone
+    and as one of the operations of a batched update."""
+    wl, kf, T0, T1 = c1
+    _say("empty keyframe")
+    empty = {"depth": np.zeros_like(kf["depth"]), "weight": np.zeros_like(kf["weight"]),
+             "color": np.zeros_like(kf["color"])}
+    dk, de = _dev_kf(kf), _dev_kf(empty)
+    vol = scsurf.Volume(S, MU, 1 << 16, 1 << 15)
+    vol.integrate(de, wl.intr, *T0)
+    assert vol.query() == (0, 0)
+    vol.integrate(dk, wl.intr, *T0)
+    vol.integrate(de, wl.intr, *T1)
+    R = np.stack([T0[0], T1[0]])
+    t = np.stack([np.asarray(T0[1]), np.asarray(T1[1])])
+    Rn = np.stack([T1[0], T0[0]])
+    tn = np.stack([np.asarray(T1[1]), np.asarray(T0[1])])
+    order, _ = vol.reintegrate_batch([dk, de], wl.intr, (R, t), (Rn, tn), 2, scsurf.SEL_ALL_ORDERED)
+    assert sorted(order) == [0, 1]
+    vol.check_error()
+    ref = oracle.Volume(S, MU)
+    assert ref.integrate(kf, wl.intr, *T1) == oracle.OK
+    g = vol.export_sorted()
+    live = g["W"].reshape(len(g["blocks"]), -1).max(axis=1) > 0
+    r = ref.export()
+    np.testing.assert_array_equal(g["blocks"][live], r["blocks"])
+    compare_fields({k: v[live] for k, v in g.items()}, r)
+    vol.close()
