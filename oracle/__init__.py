@@ -9,6 +9,10 @@ The heavy per-voxel and per-pixel loops live in ``scsurf_oracle.c`` (plain C,
 FP64 values, FP32 decisions in a written order, ``-ffp-contract=off``);
 selection (Eq. 3) and the adjoint are NumPy (``selection.py``,
 ``adjoint.py``).
+
+Parity unpinned: ``blur`` (the blurriness w_b) reads an unresolved citation
+as the re-blur metric of Crete et al.; it is pinned by that metric's closed
+forms and invariants, not by a value of the paper.
 """
 from __future__ import annotations
 

@@ -888,6 +888,9 @@ void of_sharpen(const uint8_t* rgb, int W, int H, uint16_t* out)
  * a 1x9 box (kept as 9x sums so that every quantity is an exact integer):
  *   sF = sum 9|dY|, sV = sum max(0, 9|dY| - |dB|), blur = (sF - sV) / sF.
  * Returns blur = max(blur_h, blur_v) in [0,1]; sums[4] = sF_h, sV_h, sF_v, sV_v.
+ * Parity unpinned against the paper's own measure (which the text does not
+ * identify): the tests pin this reading by its closed forms and invariants
+ * only.
  */
 double of_blur(const uint8_t* rgb, int W, int H, int64_t* sums)
 {
