@@ -109,6 +109,15 @@ def test_kf_fuse_vga_kappa60():
     _check_fuse(wl, z, rgb, wl.R[60:120], wl.t[60:120])
 
 
+def test_kf_fuse_max_frames():
+    # the largest group one call takes: 64 frames (64 observations per
+    # keyframe pixel in the colour median)
+    _say("kf_fuse 64 frames (320x240)")
+    wl, z, rgb = _frames(3, np.arange(64))
+    ref = _check_fuse(wl, z, rgb, wl.R[:64], wl.t[:64])
+    assert (ref["weight"] > 0).mean() > 0.5
+
+
 def test_kf_fuse_reference_frame_and_empty_input(c1):
     wl, z, rgb = c1
     _say("kf_fuse ref=2 and empty frames")
