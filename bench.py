@@ -31,7 +31,8 @@ if ROOT not in sys.path:
 
 METRIC = "keyframes re-integrated/sec (de+re) and voxel updates/sec; % of HBM peak"
 HBM_PEAK_GBS = 8000.0
-VOXEL_BYTES = 16  # FP64 D + FP32 W + RGBA8 colour
+VOXEL_BYTES = 12  # the method's voxel: FP32 D + FP32 W + RGBA8 colour (algorithmic bytes)
+STORAGE_VOXEL_BYTES = 16  # the voxel as stored here: FP64 D + FP32 W + RGBA8 colour
 KF_PIXEL_BYTES = 12  # keyframe depth + weight + RGBA8 colour
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "voxel_pass_traffic_batched_reintegration.json")
 KERNEL_SOURCES = ["paper_1709_03763_amd/csrc/batch.hip", "paper_1709_03763_amd/csrc/kernels.hpp",
@@ -42,6 +43,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def source_digest():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -50,40 +63,70 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def build_workload(torch, scsurf, synth, n_kf, seed, pack=True):
-    wl = synth.workload(4)
-    groups = synth.keyframe_groups(wl)[:n_kf]
-    dev = torch.device("cuda")
-    log(f"rendering {n_kf * wl.kappa} frames at {wl.intr.width}x{wl.intr.height}")
+def render_groups(torch, synth, wl, groups, tag):
+    """Frames of keyframe groups rendered on the device, in chunks of 20
+    groups: list of (depth (kappa,H,W) f32, rgb (kappa,H,W,3) u8, frame
+    indices) on the host."""
+    out = []
     t0 = time.time()
-    frames = []
-    for g0 in range(0, n_kf, 20):
+    k = wl.kappa
+    for g0 in range(0, len(groups), 20):
         gs = groups[g0:g0 + 20]
-        idx = np.concatenate(gs)
-        z, rgb = synth.frames(wl, idx, device="cuda")
+        z, rgb = synth.frames(wl, np.concatenate(gs), device="cuda")
         for j, g in enumerate(gs):
-            frames.append((z[j * wl.kappa:(j + 1) * wl.kappa], rgb[j * wl.kappa:(j + 1) * wl.kappa], g))
-        log(f"  rendered {min(g0 + 20, n_kf)}/{n_kf} keyframe groups ({time.time() - t0:.0f} s)")
-    # keyframe fusion, timed as a stage
+            out.append((z[j * k:(j + 1) * k], rgb[j * k:(j + 1) * k], g))
+        log(f"  {tag}: rendered {min(g0 + 20, len(groups))}/{len(groups)} keyframe groups ({time.time() - t0:.0f} s)")
+    return out
+
+
+def gpu_keyframes(torch, scsurf, wl, frames, masks=None):
+    """Keyframes fused on the GPU (kf_fuse), each cut by its valid-pixel mask
+    when given; returns (keyframes, seconds spent in kf_fuse)."""
+    dev = torch.device("cuda")
     dz = [torch.from_numpy(f[0]).to(dev) for f in frames]
     dc = [torch.from_numpy(f[1]).to(dev) for f in frames]
     torch.cuda.synchronize()
-    kfs = []
     t0 = time.perf_counter()
-    for k, (z, rgb, g) in enumerate(frames):
-        kfs.append(scsurf.kf_fuse(dz[k], dc[k], wl.R[g], wl.t[g], wl.intr))
+    kfs = [scsurf.kf_fuse(dz[k], dc[k], wl.R[f[2]], wl.t[f[2]], wl.intr) for k, f in enumerate(frames)]
     torch.cuda.synchronize()
     fuse_s = time.perf_counter() - t0
-    del dz, dc
-    # uneven valid-pixel fractions
-    rng = np.random.default_rng(seed)
-    fracs = rng.uniform(0.4, 1.0, n_kf)
-    for k, kf in enumerate(kfs):
-        valid = kf.weight.cpu().numpy() > 0
-        keep = torch.from_numpy(synth.column_strip_mask(valid, fracs[k], rng)).to(dev)
-        kf.depth.mul_(keep)
-        kf.weight.mul_(keep)
-        kf.color.mul_(keep[..., None].to(torch.uint8))
+    if masks is not None:
+        for kf, m in zip(kfs, masks):
+            keep = torch.from_numpy(m).to(dev)
+            kf.depth.mul_(keep)
+            kf.weight.mul_(keep)
+            kf.color.mul_(keep[..., None].to(torch.uint8))
+    return kfs, fuse_s
+
+
+def oracle_keyframes(oracle, wl, frames, idx, masks=None):
+    """The oracle's own fusion of the frame groups `idx` (a thread pool over
+    keyframes), cut by the same masks: the CPU-baseline legs' keyframes."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(k):
+        z, rgb, g = frames[k]
+        kf = oracle.kf_fuse(z, rgb, wl.intr, wl.R[g], wl.t[g])
+        out = {"depth": kf["depth"], "weight": kf["weight"], "color": kf["color"]}
+        if masks is not None:
+            m = masks[k]
+            out = {"depth": np.where(m, out["depth"], 0).astype(np.float32),
+                   "weight": np.where(m, out["weight"], 0).astype(np.float32),
+                   "color": np.where(m[..., None], out["color"], 0).astype(np.uint8)}
+        return out
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return dict(zip(idx, ex.map(one, idx)))
+
+
+def build_workload(torch, scsurf, synth, n_kf, seed, pack=True):
+    wl = synth.workload(4)
+    groups = synth.keyframe_groups(wl)[:n_kf]
+    log(f"rendering {n_kf * wl.kappa} frames at {wl.intr.width}x{wl.intr.height}")
+    frames = render_groups(torch, synth, wl, groups, "batched workload")
+    # uneven valid-pixel fractions: column strips fixed by each group's reference frame
+    fracs, masks = synth.strip_masks([f[0][0] for f in frames], seed)
+    kfs, fuse_s = gpu_keyframes(torch, scsurf, wl, frames, masks)
     R = np.array([wl.R[g[0]] for g in groups])
     t = np.array([wl.t[g[0]] for g in groups])
     pack_s = None
@@ -94,7 +137,7 @@ def build_workload(torch, scsurf, synth, n_kf, seed, pack=True):
         kfs = [scsurf.keyframe_pack(k) for k in kfs]
         torch.cuda.synchronize()
         pack_s = time.perf_counter() - t0
-    return wl, kfs, R, t, fuse_s, fracs, pack_s
+    return wl, kfs, R, t, fuse_s, fracs, pack_s, frames, masks
 
 
 def cpu_baseline(oracle, kfs_np, intr, A, B, sample):
@@ -323,98 +366,124 @@ def _oracle_rate(oracle, kfs, intr, A, B, sample, threads, s, mu):
     return len(sample) / (time.perf_counter() - t0)
 
 
+def _pass_rates(vol, steps_ms_fn):
+    """Runs `steps_ms_fn()` with the voxel-pass events and counters on and
+    returns (its return value, total voxel-pass ms, counter deltas)."""
+    s0 = vol.stats()
+    vol.batch_timing(4096)
+    r = steps_ms_fn()
+    ms = vol.batch_timing_read()
+    vol.batch_timing(0)
+    s1 = vol.stats()
+    return r, float(np.sum(ms)), [b - a for a, b in zip(s0, s1)]
+
+
 def configs_stage(torch, scsurf, synth, oracle, log):
-    """Rates on the other workloads: plain tiny (one keyframe of five frames'
-    first frame at 320x240, a 1 cm / 0.5 deg perturbation), plain full
-    resolution (10 keyframes at 640x480, 5 mm voxels, N(0, 2 cm / 1 deg)),
-    and the corridor (600 keyframes at 640x480, 20 loop-closure updates of
-    the Eq. 3 window of 100).  Keyframes are the first rendered frame of each
-    group with the oracle's depth weight (seeded weights for the corridor).
-    GPU: plain per-keyframe and batched paths; oracle: FP64 on 1 and on all
-    host threads."""
+    """Rates on the other workloads, with keyframes fused at each one's kappa:
+    plain tiny (5 frames at 320x240 -> 1 keyframe, a 1 cm / 0.5 deg
+    perturbation), plain full resolution (600 frames at 640x480 -> 10
+    keyframes of 60, 5 mm voxels, N(0, 2 cm / 1 deg)), and the corridor (3000
+    frames -> 600 keyframes of 5, 20 loop-closure updates of the Eq. 3 window
+    of 100).  GPU keyframes come from kf_fuse, the oracle's from its own
+    fusion of the same frames.  GPU: plain per-keyframe and batched paths,
+    with the batched voxel pass's algorithmic fraction of HBM peak; oracle:
+    FP64 on 1 and on all host threads."""
     n_all = oracle.threads()
     out = {}
-
-    def dev(k):
-        return scsurf.Keyframe(torch.from_numpy(k["depth"]).cuda(), torch.from_numpy(k["weight"]).cuda(),
-                               torch.from_numpy(k["color"]).cuda())
-
     for cfg in (1, 2):
         wl = synth.workload(cfg)
-        first = np.array([g[0] for g in synth.keyframe_groups(wl)])
-        z, rgb = synth.frames(wl, first, device="cuda")
-        kfs = []
-        for k in range(len(first)):
-            w = oracle.depth_weight(z[k], wl.intr)
-            kfs.append({"depth": np.where(w > 0, z[k], 0).astype(np.float32), "weight": w, "color": _rgba(rgb[k])})
+        groups = synth.keyframe_groups(wl)
+        frames = render_groups(torch, synth, wl, groups, f"config {cfg}")
+        kfs, _ = gpu_keyframes(torch, scsurf, wl, frames)
+        first = np.array([g[0] for g in groups])
         A = (wl.R[first], wl.t[first])
         B = synth.perturb_all(A[0], A[1], 0.01, 0.5, 1) if cfg == 1 else synth.perturb_all(A[0], A[1], 0.02, 1.0, 2)
         s, mu = wl.volume.voxel_size, wl.volume.trunc
         nb = 1 << (16 if cfg == 1 else 20)
         vol = scsurf.Volume(s, mu, nb, nb // 2, scsurf.COLOR_RGBA8, max_batch_ops=64)
-        dks = [dev(k) for k in kfs]
+        kfs = [scsurf.keyframe_pack(k) for k in kfs]
         for k in range(len(kfs)):
-            vol.integrate(dks[k], wl.intr, A[0][k], A[1][k])
-        kset = scsurf.KeyframeSet(dks)
+            vol.integrate(kfs[k], wl.intr, A[0][k], A[1][k])
+        kset = scsurf.KeyframeSet(kfs)
         n = len(kfs)
         steps = 200 if cfg == 1 else 20
-        plain = _update_rates(torch, scsurf, vol, dks, wl.intr, A, B, n, scsurf.SEL_ALL_ORDERED,
+        plain = _update_rates(torch, scsurf, vol, kfs, wl.intr, A, B, n, scsurf.SEL_ALL_ORDERED,
                               vol.reintegrate_plain, steps)
-        batch = _update_rates(torch, scsurf, vol, kset, wl.intr, A, B, n, scsurf.SEL_ALL_ORDERED,
-                              vol.reintegrate_batch, steps)
+        (batch, pass_ms, d) = _pass_rates(vol, lambda: _update_rates(torch, scsurf, vol, kset, wl.intr, A, B, n,
+                                                                      scsurf.SEL_ALL_ORDERED, vol.reintegrate_batch,
+                                                                      steps))
+        H, Wd = wl.intr.height, wl.intr.width
+        n_pass = steps + (steps & 1) + 2  # the timed updates and the two untimed ones before them
+        alg = d[3] * 512 * 2 * VOXEL_BYTES + n_pass * 2 * n * H * Wd * KF_PIXEL_BYTES
         vol.close()
         sample = list(range(n))
-        o1 = _oracle_rate(oracle, kfs, wl.intr, A, B, sample[:3], 1, s, mu)
-        on = _oracle_rate(oracle, kfs, wl.intr, A, B, sample, n_all, s, mu)
+        okfs = oracle_keyframes(oracle, wl, frames, sample)
+        o1 = _oracle_rate(oracle, okfs, wl.intr, A, B, sample[:3], 1, s, mu)
+        on = _oracle_rate(oracle, okfs, wl.intr, A, B, sample, n_all, s, mu)
         per_update = batch[2]  # the batched pass counts its voxel updates; the plain path does the same work
-        out[f"config{cfg}"] = {"keyframes": n, "voxel_updates_per_update": int(per_update),
+        out[f"config{cfg}"] = {"keyframes": n, "kappa": wl.kappa, "voxel_updates_per_update": int(per_update),
                                "plain_kf_per_s": round(plain[0], 1),
                                "plain_voxel_updates_per_s": round(plain[1] * per_update, 1),
                                "batched_kf_per_s": round(batch[0], 1),
                                "batched_voxel_updates_per_s": round(batch[1] * per_update, 1),
+                               "batched_pass_hbm_frac": round(alg / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                "oracle_1core_kf_per_s": round(o1, 3), f"oracle_{n_all}core_kf_per_s": round(on, 3)}
         log(f"config {cfg}: {out[f'config{cfg}']}")
     # corridor
     wl = synth.workload(5)
-    first = np.array([g[0] for g in synth.keyframe_groups(wl)[:600]])
-    log("corridor: rendering 600 keyframes")
-    z, rgb = synth.frames(wl, first, device="cuda")
-    rng = np.random.default_rng(55)
-    kfs = []
-    for k in range(len(first)):
-        w = rng.integers(64, 4096, z[k].shape).astype(np.float32) / 1024.0
-        w = np.where(z[k] > 0, w, 0).astype(np.float32)
-        kfs.append({"depth": np.where(w > 0, z[k], 0).astype(np.float32), "weight": w, "color": _rgba(rgb[k])})
+    groups = synth.keyframe_groups(wl)[:600]
+    log("corridor: rendering 3000 frames")
+    frames = render_groups(torch, synth, wl, groups, "corridor")
+    kfs, _ = gpu_keyframes(torch, scsurf, wl, frames)
+    kfs = [scsurf.keyframe_pack(k) for k in kfs]
+    first = np.array([g[0] for g in groups])
     R, t = wl.R[first], wl.t[first]
-    vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, 1 << 21, scsurf.COLOR_RGBA8,
-                        max_batch_ops=256)
-    dks = [dev(k) for k in kfs]
-    for k in range(len(kfs)):
-        vol.integrate(dks[k], wl.intr, R[k], t[k])
-    kset = scsurf.KeyframeSet(dks)
     updates = list(synth.loop_closure_updates(R, t, 20, 5))
-    Ti = (R.copy(), t.copy())
-    vol.reintegrate_batch(kset, wl.intr, Ti, updates[0], 100, scsurf.SEL_EQ3)  # warm-up, then back
-    vol.reintegrate_batch(kset, wl.intr, updates[0], Ti, 100, scsurf.SEL_EQ3)
-    torch.cuda.synchronize()
-    s0 = vol.stats()
-    t0 = time.perf_counter()
-    n = 0
-    for Tn in updates:
-        order, Ti = vol.reintegrate_batch(kset, wl.intr, Ti, Tn, 100, scsurf.SEL_EQ3)
-        n += len(order)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    upd = vol.stats()[2] - s0[2]
-    nb = vol.check_error()
-    vol.close()
+    H, Wd = wl.intr.height, wl.intr.width
+    res = {}
+    for path in ("plain", "batched"):
+        vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, 1 << 21, scsurf.COLOR_RGBA8,
+                            max_batch_ops=256)
+        for k in range(len(kfs)):
+            vol.integrate(kfs[k], wl.intr, R[k], t[k])
+        kset = scsurf.KeyframeSet(kfs)
+        fn = vol.reintegrate_plain if path == "plain" else vol.reintegrate_batch
+        Ti = (R.copy(), t.copy())
+        fn(kset, wl.intr, Ti, updates[0], 100, scsurf.SEL_EQ3)  # warm-up, then back
+        fn(kset, wl.intr, updates[0], Ti, 100, scsurf.SEL_EQ3)
+
+        def run():
+            Tc = Ti
+            n = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for Tn in updates:
+                order, Tc = fn(kset, wl.intr, Tc, Tn, 100, scsurf.SEL_EQ3)
+                n += len(order)
+            torch.cuda.synchronize()
+            return n, time.perf_counter() - t0
+
+        (n, dt), pass_ms, d = _pass_rates(vol, run)
+        nb = vol.check_error()
+        vol.close()
+        res[path] = {"kf_per_s": n / dt, "reintegrated": n, "blocks": nb, "updates_per_s": d[2] / dt}
+        if path == "batched":
+            alg = d[3] * 512 * 2 * VOXEL_BYTES + 2 * n * H * Wd * KF_PIXEL_BYTES
+            res[path]["hbm_frac"] = alg / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+        log(f"corridor {path}: {res[path]}")
     sample = list(range(0, 600, 60))
+    okfs = oracle_keyframes(oracle, wl, frames, sample)
     A = (R, t)
     B = synth.perturb_all(R, t, 0.05, 1.5, 6)
-    o1 = _oracle_rate(oracle, kfs, wl.intr, A, B, sample[:3], 1, wl.volume.voxel_size, wl.volume.trunc)
-    on = _oracle_rate(oracle, kfs, wl.intr, A, B, sample, n_all, wl.volume.voxel_size, wl.volume.trunc)
-    out["config5"] = {"keyframes": 600, "updates": len(updates), "reintegrated": n, "blocks": int(nb),
-                      "batched_kf_per_s": round(n / dt, 1), "batched_voxel_updates_per_s": round(upd / dt, 1),
+    o1 = _oracle_rate(oracle, okfs, wl.intr, A, B, sample[:3], 1, wl.volume.voxel_size, wl.volume.trunc)
+    on = _oracle_rate(oracle, okfs, wl.intr, A, B, sample, n_all, wl.volume.voxel_size, wl.volume.trunc)
+    out["config5"] = {"keyframes": 600, "kappa": wl.kappa, "updates": len(updates),
+                      "reintegrated": res["batched"]["reintegrated"], "blocks": int(res["batched"]["blocks"]),
+                      "plain_kf_per_s": round(res["plain"]["kf_per_s"], 1),
+                      "batched_kf_per_s": round(res["batched"]["kf_per_s"], 1),
+                      "batched_speedup": round(res["batched"]["kf_per_s"] / res["plain"]["kf_per_s"], 2),
+                      "batched_voxel_updates_per_s": round(res["batched"]["updates_per_s"], 1),
+                      "batched_pass_hbm_frac": round(res["batched"]["hbm_frac"], 4),
                       "oracle_1core_kf_per_s": round(o1, 3), f"oracle_{n_all}core_kf_per_s": round(on, 3)}
     log(f"config 5: {out['config5']}")
     oracle.set_threads(n_all)
@@ -479,7 +548,8 @@ def main():
     torch.cuda.set_device(0)
     scsurf.lib()
     n_kf = args.keyframes
-    wl, kfs, R, t, fuse_s, fracs, pack_s = build_workload(torch, scsurf, synth, n_kf, seed=4, pack=not args.no_pack)
+    wl, kfs, R, t, fuse_s, fracs, pack_s, frames, masks = build_workload(torch, scsurf, synth, n_kf, seed=4,
+                                                                        pack=not args.no_pack)
     H, Wd = wl.intr.height, wl.intr.width
     log(f"fused {n_kf} keyframes in {fuse_s * 1e3:.1f} ms")
     A = (R, t)
@@ -559,20 +629,30 @@ def main():
         f"{n_blocks_after} blocks allocated")
     value = n_sel / (ms_per_step / 1e3)
     pass_ms = float(np.mean(main_ms))
-    alg_bytes = written * 512 * 2 * VOXEL_BYTES + n_ops * H * Wd * KF_PIXEL_BYTES
+    # algorithmic bytes of one pass: every written block read and written once at the method's 12 B per
+    # voxel, every operation's keyframe read once; the storage figure counts the FP64 D kept here
+    kf_bytes = n_ops * H * Wd * KF_PIXEL_BYTES
+    alg_bytes = written * 512 * 2 * VOXEL_BYTES + kf_bytes
+    storage_bytes = written * 512 * 2 * STORAGE_VOXEL_BYTES + kf_bytes
     achieved = alg_bytes / (pass_ms / 1e3) / 1e9
+    # the keyframes end integrated at the poses they were first integrated at, whatever the step count,
+    # so the plain-path steps and the mesh below start from that state
+    if state[0] is not A:
+        step(vol.reintegrate_batch)
+        torch.cuda.synchronize()
     digest = source_digest()
     variant = kernel_variant(sched)
     traffic = traffic_from_profile(digest, variant)
 
     plain = None
     if not args.no_plain and args.plain_steps > 0:
+        plain_steps = args.plain_steps + (args.plain_steps & 1)  # even: the volume returns to the first poses
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
+        for _ in range(plain_steps):
             step(vol.reintegrate_plain)
         torch.cuda.synchronize()
-        pms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+        pms = (time.perf_counter() - t0) * 1e3 / plain_steps
         vol.check_error()
         plain = {"ms_per_step": round(pms, 3), "keyframes_per_s": round(n_sel / (pms / 1e3), 1),
                  "batched_speedup": round(pms / ms_per_step, 2)}
@@ -606,10 +686,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         sample = sorted(np.random.default_rng(0).choice(n_kf, min(args.cpu_sample, n_kf), replace=False).tolist())
-        kfs_np = [{"depth": kfs[k].depth.cpu().numpy(), "weight": kfs[k].weight.cpu().numpy(),
-                   "color": kfs[k].color.cpu().numpy()} for k in range(n_kf)]
+        log(f"oracle: fusing the {len(sample)} sampled keyframes")
+        kfs_np = oracle_keyframes(oracle, wl, frames, sample, masks)
         rate, dt = cpu_baseline(oracle, kfs_np, wl.intr, A, B, sample)
         cpu = {"value": round(rate, 4), "unit": "keyframes/s", "cores": oracle.threads(), "kind": "oracle",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                "sample": f"{len(sample)} of the {n_kf} keyframes, each de-integrated at its integration pose and "
                          f"re-integrated at its new pose on a volume holding those {len(sample)} ({dt:.1f} s)"}
         log(f"oracle: {rate:.3f} keyframes/s on {oracle.threads()} threads")
@@ -659,6 +740,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": variant,
                      "kernel_ms": round(pass_ms, 4), "algorithmic_bytes": int(alg_bytes),
+                     "algorithmic_bytes_rule": "blocks written x 512 voxels x 2 x 12 B (FP32 D, FP32 W, RGBA8 C) "
+                                               "+ operations x H x W x 12 B (keyframe depth, weight, RGBA8)",
+                     "storage_bytes": int(storage_bytes),
+                     "storage_frac": round(storage_bytes / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "blocks_written": int(written), "candidate_blocks": int(cand), "block_op_pairs": int(pairs),
                      "source_digest": digest},
         "cpu_baseline": cpu,
@@ -669,12 +754,12 @@ def main():
                    "kf_fuse_hbm_frac": round(n_kf * H * Wd * (wl.kappa * 7 + 12) / fuse_s / 1e9 / HBM_PEAK_GBS, 5),
                    "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
                    # plain integration of the 200 keyframes into the empty volume: blocks written once
-                   # (read and write, 32 B per voxel) plus each keyframe read once
+                   # (read and write at the method's 12 B per voxel) plus each keyframe read once
                    "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)
                                                / integrate_s / 1e9 / HBM_PEAK_GBS, 5),
                    "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),
                    "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms, "online_loop": online_res,
-                   "mesh": mesh_res},
+                   "mesh": mesh_res, "mesh_poses": "the keyframes integrated at their first poses"},
     }
     if surface_res is not None:
         out["surface_study"] = surface_res

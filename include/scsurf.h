@@ -303,19 +303,30 @@ sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats);
 /* ---- adjoint of integration --------------------------------------------- */
 
 /* Backward of integrating n_kf keyframes at poses T_k Exp(xi_k) (xi at 0)
- * into the volume, with the pixel and band decisions of the forward held
- * fixed.  With a = w_k / W(v) per touched (voxel, keyframe):
+ * into a field with prior (D0, C0, W0) (Sec. 3 running weighted average;
+ * d and w of Sec. 4.3), with the pixel and band decisions of the forward held
+ * fixed.  With a = w_k / W(v) per touched (voxel, keyframe) and
+ * W0(v) = W(v) - sum_k w_k(v):
  *   dL/dZ_k(u)   += sum_{v -> u} a dL/dD(v)
  *   dL/dC_k(u)   += sum_{v -> u} a dL/dC(v)               (F32 colour only)
  *   dL/dxi_k     += sum_v a dL/dD(v) (0, 0, 1, p_y, -p_x, 0), p = T_k^-1 x_v
- * grad_D (device, n_blocks x 512) and grad_C (device, n_blocks x 3 x 512,
- * may be NULL) are indexed by pool slot; the volume must hold the field after
- * the forward.  Outputs are accumulated (callers zero them): grad_depth
- * (device n_kf x H x W), grad_color (device n_kf x H x W x 3, may be NULL),
- * grad_xi (device n_kf x 6, FP32). */
+ *   dL/dD0(v)     = (W0 / W) dL/dD(v), dL/dC0(v) = (W0 / W) dL/dC(v)
+ * (0 where W = 0).  The volume must hold the field after the forward, with
+ * no sticky error (returned as the status otherwise).  grad_D (device,
+ * n_blocks x 512) and grad_C (device, n_blocks x 3 x 512, may be NULL) are
+ * indexed by pool slot.  Accumulated outputs (callers zero them): grad_depth
+ * (device n_kf x H x W), grad_color (device n_kf x H x W x 3; NULL exactly
+ * when grad_C is; F32-colour volumes only), grad_xi (device n_kf x 6, FP32).
+ * Written outputs (may be NULL; grad_C0 needs grad_D0 and grad_C): grad_D0
+ * (device n_blocks x 512), grad_C0 (device n_blocks x 3 x 512), by pool
+ * slot.  The keyframes run in chunks of up to min(max_batch_ops, 512)
+ * through the batched candidate stage; each candidate block is visited once
+ * per chunk.  The order of the FP32 atomic additions into grad_depth and
+ * grad_color is not fixed.  SC_EINVAL for a missing required pointer,
+ * grad_color on an RGBA8 volume or bad intrinsics. */
 sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
                                   const sc_pose* T, const float* grad_D, const float* grad_C, float* grad_depth,
-                                  float* grad_color, float* grad_xi, void* stream);
+                                  float* grad_color, float* grad_xi, float* grad_D0, float* grad_C0, void* stream);
 
 /* ---- iso-surface and surface metrics (Sec. 3; Sec. 5 evaluation) -------- */
 

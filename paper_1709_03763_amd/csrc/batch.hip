@@ -316,16 +316,6 @@ __device__ inline void apply_op(const OpDesc& op, const VolDev& v, int bx, int b
     }
 }
 
-// Finishes a block: allocation flags, errors and clearing the candidate
-// entry; executed by every lane of one wavefront (branch-free).
-__device__ inline void retire_candidate(const CandDev& cd, const VolDev& v, uint32_t h, int all, int lane)
-{
-    if (all & 2) set_error(v.err, SC_ENOTALLOC);
-    if (all & 4) set_error(v.err, SC_EWEIGHT);
-    cd.mask[(size_t)h * cd.words + min(lane, cd.words - 1)] = 0ull;  // words <= 64
-    cd.keys[h] = kKeyEmpty;
-}
-
 // Persistent voxel pass, one wavefront per block (eight voxels per lane,
 // lane = x + 8 y, z in a loop); the wavefronts of a workgroup are independent.
 template <int CM>
@@ -584,24 +574,6 @@ __device__ inline PipeLds pipe_lds(unsigned char* wb)
     L.qc = reinterpret_cast<uint32_t*>(L.qz + 128);
     L.qvox = reinterpret_cast<uint16_t*>(L.qc + 128);
     return L;
-}
-
-// Operations of a block in bit order, read word by word from its mask.
-struct OpWalk {
-    const uint64_t* mask;
-    int words, w;
-    uint64_t m;
-};
-
-__device__ inline int walk_next(OpWalk& k)
-{
-    while (k.m == 0ull) {
-        if (++k.w >= k.words) return -1;
-        k.m = bcast64(k.mask[k.w]);
-    }
-    const int b = __ffsll((unsigned long long)k.m) - 1;
-    k.m &= k.m - 1;
-    return k.w * 64 + b;
 }
 
 // State of the pipelined pass within one block.  slot is the block's pool
@@ -1032,9 +1004,11 @@ static bool graphs_for(sc_volume* vol, hipGraphExec_t& pre, hipGraphExec_t& main
     return pre && main;
 }
 
-// Copies one chunk of staged operations to the device and runs it.  With
-// timing enabled, an event pair brackets the voxel pass on the stream.
-static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s)
+// Copies one chunk of staged operations to the device and runs the captured
+// candidate stage over them: afterwards the candidate table holds each
+// candidate block's operation mask and the work list orders the blocks by
+// operation count, heaviest first.
+sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s)
 {
     BatchHdr* hdr = stage_hdr(vol);
     hdr->n_ops = n_ops;
@@ -1046,9 +1020,20 @@ static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const s
     // the staging buffer may be refilled once these copies have run
     const sc_status st = stage_end(vol, s);
     if (st != SC_OK) return st;
+    if (!vol->graph_pre) vol->graph_pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, cs); });
+    if (!vol->graph_pre || hipGraphLaunch(vol->graph_pre, s) != hipSuccess) return SC_EDEVICE;
+    return SC_OK;
+}
+
+// Runs one chunk of staged operations: the candidate stage, then the voxel
+// pass.  With timing enabled, an event pair brackets the voxel pass on the
+// stream.
+static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s)
+{
+    const sc_status st = run_candidates(vol, ops, n_ops, in, s);
+    if (st != SC_OK) return st;
     hipGraphExec_t pre = nullptr, main = nullptr;
     if (!graphs_for(vol, pre, main)) return SC_EDEVICE;
-    if (hipGraphLaunch(pre, s) != hipSuccess) return SC_EDEVICE;
     const bool timed = vol->timing_n < vol->timing_cap;
     if (timed && hipEventRecord(vol->timing_ev[2 * vol->timing_n], s) != hipSuccess) return SC_EDEVICE;
     if (hipGraphLaunch(main, s) != hipSuccess) return SC_EDEVICE;

@@ -13,6 +13,9 @@ constexpr uint64_t kKeyEmpty = ~0ull;      // never a packed key (bit 63 is clea
 constexpr float kWeightScale = 1024.0f;    // sample weights live on the 2^-10 grid
 constexpr float kWeightLimit = 16384.0f;   // 2^14: sums stay exact in FP32 below this
 constexpr int kMaxBatchOps = 4096;
+// Keyframes per chunk of the integration backward: bounds its per-workgroup
+// LDS pose accumulators (3 doubles per keyframe).
+constexpr int kAdjChunk = 512;
 // Block record in the pool, in floats: D as FP64 at [0, 1024) (Eq. (2)
 // amplifies the rounding of a stored D by W / W' when most of a voxel's
 // weight is removed, so D is kept in FP64), W as FP32 at [1024, 1536), and
@@ -133,4 +136,5 @@ struct sc_volume {
     int n_cu;
     int cand_wgs;            // resident workgroups per CU of the batched candidate kernel
     int plain_wgs;           // resident workgroups per CU of the plain update kernel
+    double* adj_acc;         // device, 3 x kAdjChunk: pose terms of one backward chunk (zero between calls)
 };

@@ -14,6 +14,7 @@ OpDesc* stage_begin(sc_volume* vol);
 BatchHdr* stage_hdr(sc_volume* vol);
 sc_status stage_end(sc_volume* vol, hipStream_t s);
 int cand_batch_resident_wgs();
+sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s);
 sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
                    hipStream_t s);
 

@@ -414,6 +414,35 @@ __device__ inline int vol_insert_wave(const VolDev& v, uint64_t key, int bx, int
 // candidate blocks
 // ---------------------------------------------------------------------------
 
+// Operations of a block in bit order, read word by word from its mask.
+struct OpWalk {
+    const uint64_t* mask;
+    int words, w;
+    uint64_t m;
+};
+
+__device__ inline int walk_next(OpWalk& k)
+{
+    while (k.m == 0ull) {
+        if (++k.w >= k.words) return -1;
+        k.m = bcast64(k.mask[k.w]);
+    }
+    const int b = __ffsll((unsigned long long)k.m) - 1;
+    k.m &= k.m - 1;
+    return k.w * 64 + b;
+}
+
+// Finishes a block: allocation flags, errors and clearing the candidate
+// entry; executed by every lane of one wavefront (branch-free).
+__device__ inline void retire_candidate(const CandDev& cd, const VolDev& v, uint32_t h, int all, int lane)
+{
+    if (all & 2) set_error(v.err, SC_ENOTALLOC);
+    if (all & 4) set_error(v.err, SC_EWEIGHT);
+    cd.mask[(size_t)h * cd.words + min(lane, cd.words - 1)] = 0ull;  // words <= 64
+    cd.keys[h] = kKeyEmpty;
+}
+
+
 // Candidate generation works on square pixel tiles with one CELL x CELL pixel
 // cell per thread: 64 x 64 tiles of 4 x 4 cells for the batched path, where
 // many operations fill the GPU, and 32 x 32 tiles of 2 x 2 quads for the one

@@ -418,6 +418,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
+    ok &= hipMalloc(&vol->adj_acc, sizeof(double) * 3 * kAdjChunk) == hipSuccess;
     ok &= hipHostMalloc((void**)&vol->h_ops, 2 * sizeof(OpDesc) * p->max_batch_ops, hipHostMallocDefault) ==
           hipSuccess;
     ok &= hipMalloc(&vol->d_hdr, sizeof(BatchHdr)) == hipSuccess;
@@ -466,6 +467,7 @@ void sc_volume_destroy(sc_volume* vol)
     hipFree(vol->cand.counters);
     hipFree(vol->cand.bins);
     hipFree(vol->d_ops);
+    hipFree(vol->adj_acc);
     hipFree(vol->d_hdr);
     if (vol->h_ops) hipHostFree(vol->h_ops);
     if (vol->h_hdr) hipHostFree(vol->h_hdr);
@@ -490,6 +492,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
     fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
+    fill_u64(reinterpret_cast<uint64_t*>(vol->adj_acc), 0ull, 3 * kAdjChunk, s);
     vol->parity = 0;
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }

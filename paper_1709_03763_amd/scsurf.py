@@ -118,7 +118,7 @@ def lib():
     L.sc_mesh_table.argtypes = [P, P]
     L.sc_volume_import.argtypes = [P, P, P, P, P, P, i64]
     L.tsdf_integrate_backward.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
-                                          ctypes.POINTER(sc_pose), P, P, P, P, P, P]
+                                          ctypes.POINTER(sc_pose), P, P, P, P, P, P, P, P]
     for name in EXPORTS:
         if name != "sc_version" and name != "sc_volume_destroy":
             getattr(L, name).restype = i32
@@ -459,7 +459,12 @@ class Volume:
         check(lib().sc_volume_stats(self._h, stream_handle(stream), out), "sc_volume_stats")
         return tuple(int(x) for x in out)
 
-    def integrate_backward(self, kfs, intr, R, t, grad_D, grad_C, grad_depth, grad_color, grad_xi, stream=None):
+    def integrate_backward(self, kfs, intr, R, t, grad_D, grad_C, grad_depth, grad_color, grad_xi, grad_D0=None,
+                           grad_C0=None, stream=None):
+        """Adjoint of integrating `kfs` at (R, t) into the field the volume
+        holds (see tsdf_integrate_backward): accumulates into grad_depth,
+        grad_color and grad_xi; writes grad_D0 / grad_C0 (pool order) if
+        given."""
         kset = keyframes(kfs)
         T = poses(R, t)
         self._check_keyframes(kset, intr, T)
@@ -472,13 +477,19 @@ class Volume:
         if grad_color is not None:
             _check_shape(grad_color, (len(kset), H, W, 3), "grad_color")
         _check_shape(grad_xi, (len(kset), 6), "grad_xi")
-        karr = kset.arr
+        if grad_D0 is not None:
+            _check_shape(grad_D0, (n_blocks, 512), "grad_D0")
+        if grad_C0 is not None:
+            _check_shape(grad_C0, (n_blocks, 3, 512), "grad_C0")
+
+        def opt(x, what):
+            return dptr(x, torch.float32, what) if x is not None else None
+
         check(lib().tsdf_integrate_backward(
-            self._h, karr, len(kfs), ctypes.byref(intrinsics(intr)), T, dptr(grad_D, torch.float32, "grad_D"),
-            dptr(grad_C, torch.float32, "grad_C") if grad_C is not None else None,
-            dptr(grad_depth, torch.float32, "grad_depth"),
-            dptr(grad_color, torch.float32, "grad_color") if grad_color is not None else None,
-            dptr(grad_xi, torch.float32, "grad_xi"), stream_handle(stream)), "tsdf_integrate_backward")
+            self._h, kset.arr, len(kset), ctypes.byref(intrinsics(intr)), T, dptr(grad_D, torch.float32, "grad_D"),
+            opt(grad_C, "grad_C"), dptr(grad_depth, torch.float32, "grad_depth"), opt(grad_color, "grad_color"),
+            dptr(grad_xi, torch.float32, "grad_xi"), opt(grad_D0, "grad_D0"), opt(grad_C0, "grad_C0"),
+            stream_handle(stream)), "tsdf_integrate_backward")
 
 
 def select(T_int, T_new, m, mode=SEL_EQ3):

@@ -504,6 +504,17 @@ def column_strip_mask(valid: np.ndarray, frac: float, rng) -> np.ndarray:
     return keep
 
 
+def strip_masks(ref_depth, seed, lo=0.4, hi=1.0):
+    """Uneven keyframe sizes: valid-pixel fractions f_k ~ U(lo, hi) and, per
+    keyframe, the column-strip mask that keeps about f_k of its range-valid
+    pixels (those of its reference frame with a depth).  Depends on the
+    rendered frames only, so both the GPU path and the oracle apply the same
+    masks to the keyframes they fuse themselves."""
+    rng = np.random.default_rng(seed)
+    fracs = rng.uniform(lo, hi, len(ref_depth))
+    return fracs, [column_strip_mask(np.asarray(ref_depth[k]) > 0, fracs[k], rng) for k in range(len(ref_depth))]
+
+
 def perturb_all(R, t, sigma_rho, sigma_phi_deg, seed):
     """T' = Exp(delta) T with delta ~ N(0, sigma) per axis (world frame)."""
     rng = np.random.default_rng(seed)

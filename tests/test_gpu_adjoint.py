@@ -1,6 +1,11 @@
 """GPU adjoint of integration (tsdf_integrate_backward through
 torch.autograd) against the oracle's closed form and FP64 central finite
-differences with frozen decisions (eps = 1e-4 m / 1e-4 rad)."""
+differences with frozen decisions (eps = 1e-4 m / 1e-4 rad).
+
+Two setups: the differentiation configuration itself (all 16 keyframes of
+five frames at 320x240, xi = 0, empty prior), and four of its keyframes at a
+nonzero xi integrated onto a seeded prior field, which exercises the SE(3)
+right Jacobian and the prior-field gradients dL/dD0, dL/dC0."""
 import numpy as np
 import pytest
 import torch
@@ -20,113 +25,324 @@ def _say(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-@pytest.fixture(scope="module")
-def setup():
-    assert torch.cuda.is_available(), "GPU tests need a device"
-    wl = synth.workload(3)
-    groups = [np.arange(5) + 5 * k for k in (0, 3, 6, 9)]
+def _keys(a):
+    a = np.asarray(a, np.int64)
+    return (a[:, 0] + 2**20) * 2**42 + (a[:, 1] + 2**20) * 2**21 + (a[:, 2] + 2**20)
+
+
+def _block_voxels(blocks):
+    k = np.arange(512)
+    off = np.stack([k & 7, (k >> 3) & 7, k >> 6], 1)
+    return (8 * np.asarray(blocks, np.int64)[:, None, :] + off[None]).reshape(-1, 3)
+
+
+def _run(wl, groups, xi0, prior_seed=None):
+    """Forward + backward on the GPU; returns everything the checks need."""
+    xi0 = np.asarray(xi0, np.float32).astype(np.float64)  # the GPU side holds xi in FP32
     kfs = [as_f32_color(k) for k in oracle_keyframes(wl, groups)]
     R = np.array([wl.R[g[0]] for g in groups])
     t = np.array([wl.t[g[0]] for g in groups])
-    _say("adjoint forward")
-    vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16, color_mode=scsurf.COLOR_F32)
+    Rp = np.empty_like(R)
+    tp = np.empty_like(t)
+    for k in range(len(groups)):
+        Rp[k], tp[k] = oadj.right_perturb(R[k], t[k], xi0[k])
+    fz = oadj.FrozenIntegration(S, MU, kfs, wl.intr, Rp, tp)
+    prior = None
+    if prior_seed is not None:
+        # a seeded prior field on the touched blocks and a shell of others:
+        # W0 on the 2^-10 grid (a quarter of the voxels empty), D0 in [-mu, mu], C0 in [0, 1]
+        rng = np.random.default_rng(prior_seed)
+        tb = np.unique(np.floor_divide(fz.vox, 8), axis=0)
+        extra = tb[rng.choice(len(tb), len(tb) // 10, replace=False)] + np.array([0, 0, 4])
+        pb = np.unique(np.concatenate([tb[rng.random(len(tb)) < 0.8], extra]), axis=0).astype(np.int32)
+        n0 = len(pb)
+        W0 = rng.integers(1, 4096, (n0, 512)) / 1024.0
+        W0[rng.random((n0, 512)) < 0.25] = 0.0
+        D0 = np.where(W0 > 0, rng.uniform(-MU, MU, (n0, 512)), 0.0).astype(np.float32)
+        C0 = np.where(W0[:, None, :] > 0, rng.uniform(0, 1, (n0, 3, 512)), 0.0).astype(np.float32)
+        prior = {"blocks": pb, "D": D0, "W": W0.astype(np.float32), "C": C0}
+    vol = scsurf.Volume(S, MU, 1 << 18, 1 << 17, color_mode=scsurf.COLOR_F32)
     depth = torch.from_numpy(np.stack([k["depth"] for k in kfs])).cuda().requires_grad_(True)
     color = torch.from_numpy(np.stack([k["color"] for k in kfs])).cuda().requires_grad_(True)
     weight = torch.from_numpy(np.stack([k["weight"] for k in kfs])).cuda()
-    xi = torch.zeros((len(kfs), 6), dtype=torch.float32, device="cuda", requires_grad=True)
-    D, C, W = sca.integrate(depth, color, weight, xi, vol, wl.intr, R, t)
+    xi = torch.from_numpy(np.asarray(xi0, np.float32)).cuda().requires_grad_(True)
+    dprior = None
+    if prior is not None:
+        dprior = {"blocks": torch.from_numpy(prior["blocks"]).cuda(),
+                  "D": torch.from_numpy(prior["D"]).cuda().requires_grad_(True),
+                  "C": torch.from_numpy(prior["C"]).cuda().requires_grad_(True),
+                  "W": torch.from_numpy(prior["W"]).cuda()}
+    _say(f"adjoint forward: {len(kfs)} keyframes, prior {'yes' if prior else 'no'}")
+    D, C, W = sca.integrate(depth, color, weight, xi, vol, wl.intr, R, t, prior=dprior)
     blocks = vol.export()["blocks"].cpu().numpy().astype(np.int64)
-    k = np.arange(512)
-    off = np.stack([k & 7, (k >> 3) & 7, k >> 6], 1)
-    vox = (8 * blocks[:, None, :] + off[None]).reshape(-1, 3)
-    xv = np.float32(S).astype(np.float64) * vox
-    target = torch.from_numpy(np.clip(synth.scene_sdf(wl.scene, xv), -MU, MU).reshape(-1, 512)).float().cuda()
+    vox = _block_voxels(blocks)
+    target = torch.from_numpy(np.clip(synth.scene_sdf(wl.scene, float(np.float32(S)) * vox.astype(np.float64)),
+                                      -MU, MU).reshape(-1, 512)).float().cuda()
     live = (W > 0).float()
     cref = torch.full_like(C, 0.5)
     loss = (((D - target) ** 2) * live).sum() + LAM * (((C - cref) ** 2) * live[:, None, :]).sum()
     _say("adjoint backward")
     loss.backward()
     torch.cuda.synchronize()
-    fz = oadj.FrozenIntegration(S, MU, kfs, wl.intr, R, t)
-    # GPU voxel order -> oracle voxel order
-    keys = lambda a: (a[:, 0] + 2**20) * 2**42 + (a[:, 1] + 2**20) * 2**21 + (a[:, 2] + 2**20)
-    gk = keys(vox)
-    ok = keys(fz.vox)
-    pos = np.searchsorted(gk, ok, sorter=np.argsort(gk))
-    gidx = np.argsort(gk)[pos]
+    # GPU voxel order -> oracle voxel order (the oracle's recorded, touched voxels)
+    gk = _keys(vox)
+    srt = np.argsort(gk)
+    ok = _keys(fz.vox)
+    gidx = srt[np.searchsorted(gk, ok, sorter=srt)]
     assert np.array_equal(gk[gidx], ok)
-    return dict(wl=wl, kfs=kfs, R=R, t=t, vol=vol, D=D, C=C, W=W, depth=depth, color=color, xi=xi, fz=fz,
-                gidx=gidx, target=target, live=live, cref=cref)
+    out = dict(wl=wl, kfs=kfs, R=R, t=t, Rp=Rp, tp=tp, xi0=np.asarray(xi0, np.float64), vol=vol, D=D, C=C, W=W,
+               depth=depth, color=color, xi=xi, fz=fz, gidx=gidx, vox=vox, target=target, live=live, cref=cref,
+               prior=prior, dprior=dprior)
+    if prior is not None:
+        # the prior at the oracle's voxels (zero where the prior has no block)
+        pk = _keys(_block_voxels(prior["blocks"]))
+        ps = np.argsort(pk)
+        pos = np.searchsorted(pk, ok, sorter=ps)
+        pos = np.minimum(pos, len(pk) - 1)
+        hit = pk[ps[pos]] == ok
+        src = ps[pos]
+        D0 = np.where(hit, prior["D"].reshape(-1)[src], 0.0)
+        W0 = np.where(hit, prior["W"].reshape(-1)[src], 0.0)
+        C0 = np.where(hit[:, None], prior["C"].transpose(0, 2, 1).reshape(-1, 3)[src], 0.0)
+        out["oprior"] = (D0.astype(np.float64), C0.astype(np.float64), W0.astype(np.float64))
+    return out
 
 
-def test_forward_field_matches_oracle(setup):
-    s = setup
-    fz = s["fz"]
-    Do, Co, Wo = fz.field([k["depth"] for k in s["kfs"]], [k["color"] for k in s["kfs"]], s["R"], s["t"])
+@pytest.fixture(scope="module")
+def c3():
+    """The differentiation configuration: 16 keyframes, xi = 0, no prior."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(3)
+    groups = synth.keyframe_groups(wl)
+    assert len(groups) == 16
+    s = _run(wl, groups, np.zeros((16, 6)))
+    yield s
+    s["vol"].close()
+
+
+@pytest.fixture(scope="module")
+def c3_prior():
+    """Four keyframes at a nonzero xi, onto a seeded prior field."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(3)
+    groups = [np.arange(5) + 5 * k for k in (0, 3, 6, 9)]
+    rng = np.random.default_rng(31)
+    xi0 = np.concatenate([rng.normal(0, 0.01, (4, 3)), rng.normal(0, 0.015, (4, 3))], 1)
+    s = _run(wl, groups, xi0, prior_seed=32)
+    yield s
+    s["vol"].close()
+
+
+def _gpu_at_oracle_voxels(s):
     Dg = s["D"].detach().cpu().numpy().reshape(-1)[s["gidx"]]
     Wg = s["W"].detach().cpu().numpy().reshape(-1)[s["gidx"]]
     Cg = s["C"].detach().cpu().numpy().transpose(0, 2, 1).reshape(-1, 3)[s["gidx"]]
+    return Dg, Cg, Wg
+
+
+def _check_forward(s):
+    fz = s["fz"]
+    Do, Co, Wo = fz.field([k["depth"] for k in s["kfs"]], [k["color"] for k in s["kfs"]], s["Rp"], s["tp"],
+                          prior=s.get("oprior"))
+    Dg, Cg, Wg = _gpu_at_oracle_voxels(s)
     np.testing.assert_array_equal(Wg.astype(np.float64), Wo)
     assert np.abs(Dg - Do).max() <= 1e-5
     assert np.abs(Cg - Co).max() <= 1e-5
-    # every live GPU voxel is one of the oracle's touched voxels
-    assert int((s["W"] > 0).sum()) == fz.V
 
 
-def test_gradients_match_oracle_closed_form(setup):
-    """Same upstream gradient on both sides: the GPU adjoint equals the FP64
-    closed form to FP32 accumulation error."""
-    s = setup
+def _closed_form(s):
     fz = s["fz"]
     gD = (2 * (s["D"] - s["target"]) * s["live"]).detach().cpu().numpy().reshape(-1)[s["gidx"]].astype(np.float64)
     gC = (2 * LAM * (s["C"] - s["cref"]) * s["live"][:, None, :]).detach().cpu().numpy()
     gC = gC.transpose(0, 2, 1).reshape(-1, 3)[s["gidx"]].astype(np.float64)
     Wg = s["W"].detach().cpu().numpy().reshape(-1)[s["gidx"]].astype(np.float64)
-    ref = fz.grad(gD, gC, s["R"], s["t"], Wg)
-    gz = s["depth"].grad.cpu().numpy().astype(np.float64)
-    gc = s["color"].grad.cpu().numpy().astype(np.float64)
-    gx = s["xi"].grad.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(gz - ref["depth"]) <= 1e-5 * np.linalg.norm(ref["depth"])
-    assert np.linalg.norm(gc - ref["color"]) <= 1e-5 * np.linalg.norm(ref["color"])
-    for k in range(len(s["kfs"])):
-        assert np.linalg.norm(gx[k] - ref["xi"][k]) <= 1e-5 * np.linalg.norm(ref["xi"][k]) + 1e-8
+    W0 = s["oprior"][2] if s.get("oprior") else None
+    return fz.grad(gD, gC, s["Rp"], s["tp"], Wg, W0=W0), gD, gC, Wg
 
 
-def test_pose_and_depth_gradients_match_finite_differences(setup):
-    """FP64 central differences of the oracle's frozen-decision loss."""
-    s = setup
-    fz, kfs, R, t = s["fz"], s["kfs"], s["R"], s["t"]
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _fd_pose(s, keyframes, wrt_xi):
+    """Central differences of the frozen-decision loss (FP64): with respect to
+    a right perturbation at the integrated pose (wrt_xi False), or to xi
+    itself through T Exp(xi) (wrt_xi True).  Only keyframe k's terms are
+    recomputed per difference."""
+    fz, kfs = s["fz"], s["kfs"]
     target = np.clip(synth.scene_sdf(s["wl"].scene, fz.xv), -MU, MU)
     cref = np.full((fz.V, 3), 0.5)
+    prior = s.get("oprior")
+    V = fz.V
+    if prior is None:
+        numD0, numC0, den0 = np.zeros(V), np.zeros((V, 3)), np.zeros(V)
+    else:
+        numD0, numC0, den0 = prior[2] * prior[0], prior[2][:, None] * prior[1], prior[2].copy()
 
-    def loss(Rx, tx, depths=None):
-        depths = depths if depths is not None else [k["depth"] for k in kfs]
-        D, C, W = fz.field(depths, [k["color"] for k in kfs], Rx, tx)
+    def contrib(k, Rk, tk):
+        p = fz.camera_points(k, Rk, tk)
+        z = kfs[k]["depth"].astype(np.float64).reshape(-1)[fz.pix[k]]
+        c = kfs[k]["color"].astype(np.float64).reshape(-1, 3)[fz.pix[k]]
+        w = fz.w[k]
+        nd = np.bincount(fz.vid[k], w * (z - p[:, 2]), minlength=V)
+        nc = np.stack([np.bincount(fz.vid[k], w * c[:, ch], minlength=V) for ch in range(3)], 1)
+        return nd, nc
+
+    parts = [contrib(k, s["Rp"][k], s["tp"][k]) for k in range(fz.K)]
+    den = den0.copy()
+    for k in range(fz.K):
+        den += np.bincount(fz.vid[k], fz.w[k], minlength=V)
+    numD = numD0 + sum(p[0] for p in parts)
+    numC = numC0 + sum(p[1] for p in parts)
+
+    def loss(k, Rk, tk):
+        nd, nc = contrib(k, Rk, tk)
+        D = (numD - parts[k][0] + nd) / den
+        C = (numC - parts[k][1] + nc) / den[:, None]
         return oadj.sdf_loss(D, C, target, cref, LAM)[0]
 
-    gx = s["xi"].grad.cpu().numpy().astype(np.float64)
-    fd = np.zeros_like(gx)
-    for k in range(len(kfs)):
+    fd = np.zeros((len(keyframes), 6))
+    for i, k in enumerate(keyframes):
         for j in range(6):
             e = np.zeros(6)
             e[j] = EPS
-            Rp, tp = R.copy(), t.copy()
-            Rp[k], tp[k] = oadj.right_perturb(R[k], t[k], e)
-            Lp = loss(Rp, tp)
-            Rp[k], tp[k] = oadj.right_perturb(R[k], t[k], -e)
-            fd[k, j] = (Lp - loss(Rp, tp)) / (2 * EPS)
-    rel = np.linalg.norm(gx - fd) / np.linalg.norm(fd)
-    print(f"pose gradient vs FD: relative error {rel:.2e}", flush=True)
+            if wrt_xi:
+                Lp = loss(k, *oadj.right_perturb(s["R"][k], s["t"][k], s["xi0"][k] + e))
+                Lm = loss(k, *oadj.right_perturb(s["R"][k], s["t"][k], s["xi0"][k] - e))
+            else:
+                Lp = loss(k, *oadj.right_perturb(s["Rp"][k], s["tp"][k], e))
+                Lm = loss(k, *oadj.right_perturb(s["Rp"][k], s["tp"][k], -e))
+            fd[i, j] = (Lp - Lm) / (2 * EPS)
+    return fd
+
+
+def test_forward_field_matches_oracle(c3):
+    _check_forward(c3)
+    # every live GPU voxel is one of the oracle's touched voxels
+    assert int((c3["W"] > 0).sum()) == c3["fz"].V
+
+
+def test_gradients_match_oracle_closed_form(c3):
+    """Same upstream gradient on both sides: the GPU adjoint equals the FP64
+    closed form to FP32 accumulation error, for all 16 keyframes."""
+    s = c3
+    ref = _closed_form(s)[0]
+    gz = s["depth"].grad.cpu().numpy().astype(np.float64)
+    gc = s["color"].grad.cpu().numpy().astype(np.float64)
+    gx = s["xi"].grad.cpu().numpy().astype(np.float64)
+    assert _rel(gz, ref["depth"]) <= 1e-5
+    assert _rel(gc, ref["color"]) <= 1e-5
+    for k in range(16):
+        assert np.linalg.norm(gx[k] - ref["xi"][k]) <= 1e-5 * np.linalg.norm(ref["xi"][k]) + 1e-8, k
+
+
+def test_pose_gradients_match_finite_differences(c3):
+    """All 16 keyframes x 6 pose components against FP64 central differences."""
+    s = c3
+    gx = s["xi"].grad.cpu().numpy().astype(np.float64)
+    fd = _fd_pose(s, range(16), wrt_xi=False)
+    rel = _rel(gx, fd)
+    _say(f"16-keyframe pose gradient vs FD: relative error {rel:.2e}")
     assert rel <= 1e-4
+
+
+def test_depth_gradients_match_finite_differences(c3):
+    s = c3
+    fz, kfs = s["fz"], s["kfs"]
+    target = np.clip(synth.scene_sdf(s["wl"].scene, fz.xv), -MU, MU)
+    cref = np.full((fz.V, 3), 0.5)
+
+    def loss(depths):
+        D, C, W = fz.field(depths, [k["color"] for k in kfs], s["Rp"], s["tp"])
+        return oadj.sdf_loss(D, C, target, cref, LAM)[0]
+
     gz = s["depth"].grad.cpu().numpy()
     rng = np.random.default_rng(0)
     h = 1e-2  # the loss is quadratic in depth: central differences are exact up to rounding
-    for k in range(len(kfs)):
+    for k in rng.choice(16, 3, replace=False):
         flat = gz[k].reshape(-1)
-        for p in rng.choice(np.flatnonzero(flat != 0), 5, replace=False):
+        for p in rng.choice(np.flatnonzero(flat != 0), 2, replace=False):
             dp = [x["depth"].astype(np.float64).copy() for x in kfs]
             dp[k].reshape(-1)[p] += h
-            Lp = loss(R, t, dp)
+            Lp = loss(dp)
             dp[k].reshape(-1)[p] -= 2 * h
-            fdz = (Lp - loss(R, t, dp)) / (2 * h)
+            fdz = (Lp - loss(dp)) / (2 * h)
             assert abs(flat[p] - fdz) <= 1e-4 * abs(fdz) + 1e-7
+
+
+def test_prior_forward_matches_oracle(c3_prior):
+    _check_forward(c3_prior)
+
+
+def test_prior_gradients_match_closed_form(c3_prior):
+    """Depth, colour and prior gradients at the oracle's voxels equal the
+    closed form; outside them dL/dD0 = dL/dD where W0 > 0 (no keyframe
+    touches the voxel) and 0 where the prior voxel is empty."""
+    s = c3_prior
+    ref, gD, gC, Wg = _closed_form(s)
+    gz = s["depth"].grad.cpu().numpy().astype(np.float64)
+    gc = s["color"].grad.cpu().numpy().astype(np.float64)
+    assert _rel(gz, ref["depth"]) <= 1e-5
+    assert _rel(gc, ref["color"]) <= 1e-5
+    # prior gradients, in the prior's own block order
+    p = s["prior"]
+    gD0 = s["dprior"]["D"].grad.cpu().numpy().astype(np.float64)
+    gC0 = s["dprior"]["C"].grad.cpu().numpy().astype(np.float64)
+    pk = _keys(_block_voxels(p["blocks"]))
+    ok = _keys(s["fz"].vox)
+    inter, ip, io = np.intersect1d(pk, ok, return_indices=True)
+    assert len(inter) > 10000
+    np.testing.assert_allclose(gD0.reshape(-1)[ip], ref["D0"][io], rtol=1e-5, atol=1e-9)
+    W0o = s["oprior"][2]
+    np.testing.assert_allclose(gC0.transpose(0, 2, 1).reshape(-1, 3)[ip],
+                               gC[io] * (W0o[io] / Wg[io])[:, None], rtol=1e-5, atol=1e-9)
+    # prior voxels no keyframe touches: dL/dD0 = dL/dD there (W = W0), zero if empty
+    rest = np.setdiff1d(np.arange(len(pk)), ip)
+    gk = _keys(s["vox"])
+    srt = np.argsort(gk)
+    gpos = srt[np.searchsorted(gk, pk[rest], sorter=srt)]
+    assert np.array_equal(gk[gpos], pk[rest])
+    gDg = (2 * (s["D"] - s["target"]) * s["live"]).detach().cpu().numpy().reshape(-1)[gpos]
+    W0r = p["W"].reshape(-1)[rest]
+    np.testing.assert_array_equal(gD0.reshape(-1)[rest], np.where(W0r > 0, gDg, 0.0))
+
+
+def test_prior_pose_gradient_wrt_xi_matches_finite_differences(c3_prior):
+    """At xi != 0 the gradient with respect to xi (through T Exp(xi), with
+    the right Jacobian) equals central differences in xi itself."""
+    s = c3_prior
+    gx = s["xi"].grad.cpu().numpy().astype(np.float64)
+    fd = _fd_pose(s, range(4), wrt_xi=True)
+    rel = _rel(gx, fd)
+    _say(f"pose gradient at xi != 0 vs FD in xi: relative error {rel:.2e}")
+    assert rel <= 1e-4
+    # the right-perturbation gradient alone (no Jacobian) would miss by O(|xi|)
+    fd_right = _fd_pose(s, range(4), wrt_xi=False)
+    assert _rel(fd_right, fd) > 1e-3
+
+
+def test_prior_d0_gradient_matches_finite_differences(c3_prior):
+    """dL/dD0 on sampled prior voxels against central differences of the
+    frozen-decision loss in D0 (quadratic, so exact up to rounding)."""
+    s = c3_prior
+    fz = s["fz"]
+    target = np.clip(synth.scene_sdf(s["wl"].scene, fz.xv), -MU, MU)
+    cref = np.full((fz.V, 3), 0.5)
+    D0, C0, W0 = s["oprior"]
+    gD0 = s["dprior"]["D"].grad.cpu().numpy().reshape(-1)
+    pk = _keys(_block_voxels(s["prior"]["blocks"]))
+    ok = _keys(fz.vox)
+    inter, ip, io = np.intersect1d(pk, ok, return_indices=True)
+    rng = np.random.default_rng(5)
+    h = 1e-3
+    for j in rng.choice(np.flatnonzero(W0[io] > 0), 6, replace=False):
+        v = io[j]
+        Dp = D0.copy()
+        Dp[v] += h
+        Lp = oadj.sdf_loss(*fz.field([k["depth"] for k in s["kfs"]], [k["color"] for k in s["kfs"]], s["Rp"],
+                                     s["tp"], prior=(Dp, C0, W0))[:2], target, cref, LAM)[0]
+        Dp[v] -= 2 * h
+        Lm = oadj.sdf_loss(*fz.field([k["depth"] for k in s["kfs"]], [k["color"] for k in s["kfs"]], s["Rp"],
+                                     s["tp"], prior=(Dp, C0, W0))[:2], target, cref, LAM)[0]
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(gD0[ip[j]] - fd) <= 1e-4 * abs(fd) + 1e-7

@@ -14,6 +14,8 @@ import oracle
 from oracle import selection as osel
 from paper_1709_03763_amd import scsurf, synth
 
+from tests.helpers import compare_fields
+
 pytestmark = pytest.mark.gpu
 
 S, MU, N_KF = 0.01, 0.04, 200
@@ -122,6 +124,13 @@ def oracle_field(full):
         rc = ref.integrate(kfs[k], wl.intr, R, t) if sign > 0 else ref.deintegrate(kfs[k], wl.intr, R, t)
         assert rc == oracle.OK
     return ref.export()
+
+
+def test_whole_field_matches_oracle(full, oracle_field):
+    """The whole field after the 600 operations: the allocated-block set
+    bit-exact as a set, W and RGBA8 colour exact, D within 1e-5 m."""
+    wl, kfs, field, ops, vol = full
+    compare_fields(vol.export_sorted(), oracle_field)
 
 
 def _anchor_blocks(keys):

@@ -1,0 +1,119 @@
+"""The benchmark's timed path checked whole against the oracle.
+
+Batched re-integration configuration: 1000 frames at 640x480 of the large
+room fused five per keyframe into 200 keyframes (the GPU by kf_fuse, the
+oracle by its own fusion of the same rendered frames), each keyframe cut to
+a seeded valid-pixel fraction in [0.4, 1.0] of its reference frame's pixels
+by a contiguous column strip (the benchmark's seed and rule), packed, integrated, then one pose-graph
+update moving every pose by N(0, 3 cm / 1.5 deg) applied in all-ordered
+selection with the benchmark's voxel-pass schedule, and a second update back.
+After each update the whole field is compared: the allocated-block set
+bit-exact as a set, W and RGBA8 colour exact, D within 1e-5 m.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import selection as osel
+from paper_1709_03763_amd import scsurf, synth
+
+from tests.helpers import compare_fields
+
+pytestmark = pytest.mark.gpu
+
+S, MU, N_KF = 0.01, 0.04, 200
+SCHEDULE = (8, 2, 8, 3)  # the voxel-pass schedule the benchmark's autotuner picks on this workload
+STRIP_SEED = 4  # the benchmark's seed for the valid-pixel fractions and strips
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def headline():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(4)
+    groups = synth.keyframe_groups(wl)[:N_KF]
+    _say("rendering 1000 frames at 640x480")
+    z, rgb = synth.frames(wl, np.concatenate(groups), device="cuda")
+    k = wl.kappa
+    _say("fusing 200 keyframes on the GPU")
+    gkf = []
+    for j, g in enumerate(groups):
+        gkf.append(scsurf.kf_fuse(torch.from_numpy(z[j * k:(j + 1) * k]).cuda(),
+                                  torch.from_numpy(rgb[j * k:(j + 1) * k]).cuda(), wl.R[g], wl.t[g], wl.intr))
+    torch.cuda.synchronize()
+    _say("fusing 200 keyframes in the oracle")
+
+    def fuse(j):
+        g = groups[j]
+        return oracle.kf_fuse(z[j * k:(j + 1) * k], rgb[j * k:(j + 1) * k], wl.intr, wl.R[g], wl.t[g])
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        okf = list(ex.map(fuse, range(N_KF)))
+    # the benchmark's uneven keyframe sizes: column strips fixed by each group's reference frame
+    fracs, masks = synth.strip_masks([z[j * k] for j in range(N_KF)], STRIP_SEED)
+    del z, rgb
+    kfs, dks = [], []
+    for j in range(N_KF):
+        o = okf[j]
+        keep = masks[j]
+        kfs.append({"depth": np.where(keep, o["depth"], 0).astype(np.float32),
+                    "weight": np.where(keep, o["weight"], 0).astype(np.float32),
+                    "color": np.where(keep[..., None], o["color"], 0).astype(np.uint8)})
+        g = gkf[j]
+        kt = torch.from_numpy(keep).cuda()
+        g.depth.mul_(kt)
+        g.weight.mul_(kt)
+        g.color.mul_(kt[..., None].to(torch.uint8))
+        dks.append(scsurf.keyframe_pack(g))
+    del okf
+    R = np.array([wl.R[g[0]] for g in groups])
+    t = np.array([wl.t[g[0]] for g in groups])
+    Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 4)
+    vol = scsurf.Volume(S, MU, 1 << 21, 1 << 21, scsurf.COLOR_RGBA8, max_batch_ops=512)
+    vol.set_schedule(*SCHEDULE)
+    for j in range(N_KF):
+        vol.integrate(dks[j], wl.intr, R[j], t[j])
+    vol.check_error()
+    yield wl, kfs, dks, vol, (R, t), (Rn, tn)
+    vol.close()
+
+
+def test_fused_keyframes_equal_oracle(headline):
+    """kf_fuse at the benchmark's size: all 200 keyframes, as the voxel passes
+    read them (after the strips), equal the oracle's fusion bit for bit."""
+    wl, kfs, dks, vol, A, B = headline
+    for j in range(N_KF):
+        np.testing.assert_array_equal(dks[j].depth.cpu().numpy(), kfs[j]["depth"], err_msg=f"keyframe {j} depth")
+        np.testing.assert_array_equal(dks[j].weight.cpu().numpy(), kfs[j]["weight"], err_msg=f"keyframe {j} weight")
+        np.testing.assert_array_equal(dks[j].color.cpu().numpy(), kfs[j]["color"], err_msg=f"keyframe {j} colour")
+    fr = np.array([(k["weight"] > 0).mean() for k in kfs])
+    _say(f"valid-pixel fractions of the keyframes: {fr.min():.3f} .. {fr.max():.3f}")
+
+
+def test_whole_field_after_updates(headline):
+    """Two batched updates (A -> B, then B -> A) with the benchmark's schedule
+    and packed keyframes; after each, the whole field equals the oracle's
+    after the same operation sequence."""
+    wl, kfs, dks, vol, A, B = headline
+    assert vol.get_schedule() == SCHEDULE
+    ref = oracle.Volume(S, MU)
+    _say("oracle: 200 integrations")
+    for j in range(N_KF):
+        assert ref.integrate(kfs[j], wl.intr, A[0][j], A[1][j]) == oracle.OK
+    kset = scsurf.KeyframeSet(dks)
+    for step, (Ti, Tn) in enumerate(((A, B), (B, A))):
+        order, _ = vol.reintegrate_batch(kset, wl.intr, Ti, Tn, N_KF, scsurf.SEL_ALL_ORDERED)
+        assert order == osel.select(osel.distances(Ti[0], Ti[1], Tn[0], Tn[1]), N_KF, osel.ALL_ORDERED)
+        n = vol.check_error()
+        _say(f"update {step}: {n} blocks on the GPU; oracle: 400 operations")
+        for j in order:
+            assert ref.deintegrate(kfs[j], wl.intr, Ti[0][j], Ti[1][j]) == oracle.OK
+        for j in order:
+            assert ref.integrate(kfs[j], wl.intr, Tn[0][j], Tn[1][j]) == oracle.OK
+        compare_fields(vol.export_sorted(), ref.export())
