@@ -311,8 +311,10 @@ sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats);
  *   dL/dC_k(u)   += sum_{v -> u} a dL/dC(v)               (F32 colour only)
  *   dL/dxi_k     += sum_v a dL/dD(v) (0, 0, 1, p_y, -p_x, 0), p = T_k^-1 x_v
  *   dL/dD0(v)     = (W0 / W) dL/dD(v), dL/dC0(v) = (W0 / W) dL/dC(v)
- * (0 where W = 0).  The volume must hold the field after the forward, with
- * no sticky error (returned as the status otherwise).  grad_D (device,
+ * (0 where W = 0; W0 is formed exactly on the 2^-10 weight grid before
+ * the one division, so a small W0 / W keeps its relative precision).  The
+ * volume must hold the field after the forward, with no sticky error
+ * (returned as the status otherwise).  grad_D (device,
  * n_blocks x 512) and grad_C (device, n_blocks x 3 x 512, may be NULL) are
  * indexed by pool slot.  Accumulated outputs (callers zero them): grad_depth
  * (device n_kf x H x W), grad_color (device n_kf x H x W x 3; NULL exactly

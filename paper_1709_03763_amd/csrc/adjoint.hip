@@ -108,20 +108,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const OpDesc* __restrict__
             double* dst = (lane < 3) ? s_acc + 3 * o + lane : s_acc + 3 * n_ops + lane;
             atomicAdd(dst, val);
         }
-        // dL/dD0 = dL/dD (W - sum_k w_k) / W, accumulated over chunks as
-        // dL/dD0 -= dL/dD (sum_chunk w_k) / W on top of dL/dD
+        // dL/dD0 = dL/dD (W - sum_k w_k) / W: grad_D0 first collects
+        // sum_k w_k over the chunks (exact in FP32 on the 2^-10 weight grid
+        // below 2^14, one wavefront per block and launch), and the final
+        // kernel forms W0 = W - sum_k w_k exactly before one division, so a
+        // small W0 / W is not the difference of two nearly equal products
         if (slot >= 0 && grad_D0) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int x = lane + 64 * j;
-                if (sw[j] > 0.0f) {
-                    const float f = sw[j] / Wv[j];
-                    grad_D0[sb * kBlockVox + x] -= g[j] * f;
-                    if (CM == SC_COLOR_F32 && grad_C0) {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) grad_C0[(sb * 3 + c) * kBlockVox + x] -= gc[c][j] * f;
-                    }
-                }
+                if (sw[j] > 0.0f) grad_D0[sb * kBlockVox + x] += sw[j];
             }
         }
         retire_candidate(cd, v, h, 0, lane);
@@ -131,19 +127,29 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const OpDesc* __restrict__
         if (s_acc[i] != 0.0) atomicAdd(acc_xi + i, s_acc[i]);
 }
 
-// dL/dD0 (and dL/dC0) start as dL/dD where W > 0 and 0 elsewhere (an empty
-// voxel stays empty whatever D0 holds).
-__global__ void adjoint_prior_init_kernel(VolDev v, int64_t n_blocks, const float* gD, const float* gC,
-                                          float* grad_D0, float* grad_C0)
+// grad_D0 holds sum_k w_k per voxel while the chunks run; it starts at 0.
+__global__ void adjoint_prior_init_kernel(int64_t n_blocks, float* grad_D0)
+{
+    const int64_t b = blockIdx.x;
+    for (int x = threadIdx.x; x < kBlockVox; x += blockDim.x) grad_D0[b * kBlockVox + x] = 0.0f;
+}
+
+// dL/dD0 = dL/dD W0 / W and dL/dC0 = dL/dC W0 / W with W0 = W - sum_k w_k
+// (exact), where W > 0; 0 elsewhere (an empty voxel stays empty whatever D0
+// holds).
+__global__ void adjoint_prior_final_kernel(VolDev v, int64_t n_blocks, const float* gD, const float* gC,
+                                           float* grad_D0, float* grad_C0)
 {
     const int64_t b = blockIdx.x;
     const float* blk = v.pool + (size_t)b * v.stride;
     for (int x = threadIdx.x; x < kBlockVox; x += blockDim.x) {
-        const bool live = blk[kPoolW + x] > 0.0f;
-        grad_D0[b * kBlockVox + x] = live ? gD[b * kBlockVox + x] : 0.0f;
+        const float W = blk[kPoolW + x];
+        const bool live = W > 0.0f;
+        const float f = live ? (W - grad_D0[b * kBlockVox + x]) / W : 0.0f;
+        grad_D0[b * kBlockVox + x] = live ? gD[b * kBlockVox + x] * f : 0.0f;
         if (grad_C0)
             for (int c = 0; c < 3; ++c)
-                grad_C0[(b * 3 + c) * kBlockVox + x] = (live && gC) ? gC[(b * 3 + c) * kBlockVox + x] : 0.0f;
+                grad_C0[(b * 3 + c) * kBlockVox + x] = (live && gC) ? gC[(b * 3 + c) * kBlockVox + x] * f : 0.0f;
     }
 }
 
@@ -181,8 +187,7 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
     sc_status st = sc_volume_query(vol, s, &nb, &sticky);
     if (st != SC_OK) return st;
     if (sticky != SC_OK) return sticky;
-    if (grad_D0 && nb > 0)
-        adjoint_prior_init_kernel<<<(unsigned)nb, 256, 0, s>>>(vol->dev, nb, grad_D, grad_C, grad_D0, grad_C0);
+    if (grad_D0 && nb > 0) adjoint_prior_init_kernel<<<(unsigned)nb, 256, 0, s>>>(nb, grad_D0);
     const int chunk = std::min(vol->p.max_batch_ops, kAdjChunk);
     const bool f32 = vol->p.color_mode == SC_COLOR_F32;
     for (int k0 = 0; k0 < n_kf; k0 += chunk) {
@@ -204,6 +209,8 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
                                                                 cnt);
         xi_final_kernel<<<(3 * cnt + 255) / 256, 256, 0, s>>>(vol->adj_acc, 3 * cnt, grad_xi + 6 * (size_t)k0);
     }
+    if (grad_D0 && nb > 0)
+        adjoint_prior_final_kernel<<<(unsigned)nb, 256, 0, s>>>(vol->dev, nb, grad_D, grad_C, grad_D0, grad_C0);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
