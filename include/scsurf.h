@@ -57,6 +57,7 @@ typedef int32_t sc_status;
 #define SC_EDEVICE (-7)    /* a HIP runtime call failed */
 #define SC_ENOLIB (-8)     /* no usable gfx950 device */
 #define SC_ERANGE (-9)     /* sticky: a keyframe pixel's frustum cell spans more than 16 blocks per axis */
+#define SC_ESCRATCH (-10)  /* the input needs more than the fixed scratch of an allocation-free entry point */
 
 #define SC_COLOR_RGBA8 0 /* voxel colour 4 x uint8 (RGB + pad); keyframe colour uint8 H x W x 4 */
 #define SC_COLOR_F32 1   /* keyframe colour float H x W x 3 in [0,1]; voxel colour held as 3 x double
@@ -198,6 +199,22 @@ sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int
 sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames, int32_t ref,
                   const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth, float* kf_weight,
                   uint8_t* kf_rgba, void* stream);
+
+/* kf_fuse for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results, with every intermediate buffer (per-frame weights,
+ * sharpened colour, fixed-point accumulators, colour-prep partials, relative
+ * poses) in one fixed 64 MiB device array per device, held until the process
+ * ends.  Relative poses travel as kernel arguments, so no host staging or
+ * copy is enqueued either.  The array needs about
+ * 16 H W + 10 H W n_frames bytes (640 x 480 fits up to 20 frames); a larger
+ * input returns SC_ESCRATCH with nothing enqueued.  Every call on a device
+ * shares that device's array, so calls that overlap on one device (two
+ * streams, or two host threads) race and must be ordered by the caller.
+ * The first call on a device looks up the array's address there. */
+sc_status kf_fuse_noalloc(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames,
+                          int32_t ref, const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth,
+                          float* kf_weight, uint8_t* kf_rgba, void* stream);
 
 /* ---- voxel blocks (Sec. 3 "SDF volume") --------------------------------- */
 

@@ -593,12 +593,115 @@ static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& 
     depth_weight_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(depth, n, in, p, tiles_x, tiles, out);
 }
 
-static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, double* wb, hipStream_t s)
+static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, long long* parts, double* wb,
+                              hipStream_t s)
 {
     const int tiles = prep_tiles(W, H);
     color_prep_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp,
-                                                                        g_ws.parts);
-    blur_final_kernel<<<n, 256, 0, s>>>(g_ws.parts, n, tiles, wb);
+                                                                        parts);
+    blur_final_kernel<<<n, 256, 0, s>>>(parts, n, tiles, wb);
+}
+
+// Device buffers of one fusion: per-frame weights, sharpened colour, the
+// fixed-point accumulators, colour-prep partials, w_b and the relative poses.
+struct FuseBufs {
+    float* wz;
+    uint16_t* cs;
+    unsigned long long* acc;
+    long long* parts;
+    double* wb;
+    FuseFrames* fr;
+};
+
+// The fusion kernels of one keyframe, on buffers whose relative poses are
+// already in place (or enqueued before on the same stream).
+static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rgb, int n_frames,
+                        const sc_intrinsics& in, const sc_fuse_params& params, float* kf_depth, float* kf_weight,
+                        uint8_t* kf_rgba, hipStream_t s)
+{
+    const int64_t np = (int64_t)in.width * in.height;
+    // depth
+    launch_depth_weight(depth, n_frames, in, params, b.wz, s);
+    fill_u64(reinterpret_cast<uint64_t*>(b.acc), 0ull, 2 * (size_t)np, s);
+    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
+    warp_kernel<<<grid, 256, 0, s>>>(depth, b.wz, n_frames, in, b.fr, b.acc, b.acc + np);
+    depth_final_kernel<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(b.acc, b.acc + np, np, kf_depth, kf_weight);
+    // colour
+    launch_color_prep(rgb, n_frames, in.width, in.height, b.cs, b.parts, b.wb, s);
+    int threads = 256;
+    while (threads > 64 && (size_t)threads * n_frames * sizeof(Obs) > 48 * 1024) threads >>= 1;
+    const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
+    color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
+        depth, b.wz, b.cs, b.wb, n_frames, in, params.occ_rel, b.fr, kf_depth, kf_weight, kf_rgba);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free fusion: every buffer in one fixed device array
+// ---------------------------------------------------------------------------
+
+// Scratch of kf_fuse_noalloc.  In host code `scratch` names a host-side
+// stand-in, never device memory: its device address is looked up once per
+// device with hipGetSymbolAddress and only that address is passed on.  Every
+// call on a device shares that device's copy, so calls that overlap on one
+// device race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_dev[kMaxDevices];
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (with the device current).
+static sc_status scratch_address(unsigned char** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SC_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SC_EDEVICE;
+        g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SC_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Places the fusion buffers of np pixels x frames frames in one region
+// starting at base (may be null to measure); returns the bytes used.
+static size_t fuse_layout(unsigned char* base, size_t np, size_t frames, size_t parts, FuseBufs& b)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base ? base + off : nullptr;
+        off = align256(off + bytes);
+        return p;
+    };
+    b.fr = reinterpret_cast<FuseFrames*>(take(sizeof(FuseFrames)));
+    b.wb = reinterpret_cast<double*>(take(sizeof(double) * kMaxFrames));
+    b.acc = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2 * np));
+    b.parts = reinterpret_cast<long long*>(take(sizeof(long long) * parts));
+    b.wz = reinterpret_cast<float*>(take(sizeof(float) * np * frames));
+    b.cs = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * 3 * np * frames));
+    return off;
+}
+
+// Relative poses passed by value, kStageFrames frames per launch, so that no
+// host staging buffer is needed.
+constexpr int kStageFrames = 32;
+struct PoseChunk {
+    float Rf[kStageFrames][12];
+    float Rb[kStageFrames][12];
+};
+
+__global__ void stage_poses_kernel(PoseChunk c, int first, int count, FuseFrames* fr)
+{
+    for (int i = threadIdx.x; i < count * 12; i += blockDim.x) {
+        fr->Rf[first + i / 12][i % 12] = c.Rf[i / 12][i % 12];
+        fr->Rb[first + i / 12][i % 12] = c.Rb[i / 12][i % 12];
+    }
 }
 
 }  // namespace sc
@@ -625,7 +728,7 @@ sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int
     const sc_status st =
         ws_reserve((size_t)width * height, (size_t)n_frames, 4 * (size_t)prep_tiles(width, height) * n_frames);
     if (st != SC_OK) return st;
-    launch_color_prep(rgb, n_frames, width, height, sharp_out, wb_out, (hipStream_t)stream);
+    launch_color_prep(rgb, n_frames, width, height, sharp_out, g_ws.parts, wb_out, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
@@ -650,19 +753,38 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
     if (hipMemcpyAsync(g_ws.d_fr, g_ws.h_fr, sizeof(FuseFrames), hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
     if (hipEventRecord(g_ws.staged, s) != hipSuccess) return SC_EDEVICE;
-    // depth
-    launch_depth_weight(depth, n_frames, in, *params, g_ws.wz, s);
-    fill_u64(reinterpret_cast<uint64_t*>(g_ws.acc), 0ull, 2 * (size_t)np, s);
-    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
-    warp_kernel<<<grid, 256, 0, s>>>(depth, g_ws.wz, n_frames, in, g_ws.d_fr, g_ws.acc, g_ws.acc + np);
-    depth_final_kernel<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(g_ws.acc, g_ws.acc + np, np, kf_depth, kf_weight);
-    // colour
-    launch_color_prep(rgb, n_frames, in.width, in.height, g_ws.cs, g_ws.wb, s);
-    int threads = 256;
-    while (threads > 64 && (size_t)threads * n_frames * sizeof(Obs) > 48 * 1024) threads >>= 1;
-    const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
-    color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
-        depth, g_ws.wz, g_ws.cs, g_ws.wb, n_frames, in, params->occ_rel, g_ws.d_fr, kf_depth, kf_weight, kf_rgba);
+    const FuseBufs b{g_ws.wz, g_ws.cs, g_ws.acc, g_ws.parts, g_ws.wb, g_ws.d_fr};
+    launch_fuse(b, depth, rgb, n_frames, in, *params, kf_depth, kf_weight, kf_rgba, s);
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
+sc_status kf_fuse_noalloc(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames, int32_t ref,
+                          const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth, float* kf_weight,
+                          uint8_t* kf_rgba, void* stream)
+{
+    if (!depth || !rgb || !poses || n_frames <= 0 || n_frames > kMaxFrames || ref < 0 || ref >= n_frames ||
+        !intr_valid(intr) || !params || !kf_depth || !kf_weight || !kf_rgba)
+        return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const sc_intrinsics in = *intr;
+    const size_t np = (size_t)in.width * in.height;
+    const size_t parts = 4 * (size_t)prep_tiles(in.width, in.height) * n_frames;
+    FuseBufs b;
+    if (fuse_layout(nullptr, np, (size_t)n_frames, parts, b) > kScratchBytes) return SC_ESCRATCH;
+    unsigned char* base = nullptr;
+    const sc_status st = scratch_address(&base);
+    if (st != SC_OK) return st;
+    fuse_layout(base, np, (size_t)n_frames, parts, b);
+    for (int i0 = 0; i0 < n_frames; i0 += kStageFrames) {
+        const int cnt = std::min(kStageFrames, n_frames - i0);
+        PoseChunk c;
+        for (int j = 0; j < cnt; ++j) {
+            rel_pose(poses[ref], poses[i0 + j], c.Rf[j]);
+            rel_pose(poses[i0 + j], poses[ref], c.Rb[j]);
+        }
+        stage_poses_kernel<<<1, 256, 0, s>>>(c, i0, cnt, b.fr);
+    }
+    launch_fuse(b, depth, rgb, n_frames, in, *params, kf_depth, kf_weight, kf_rgba, s);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 

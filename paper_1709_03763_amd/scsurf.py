@@ -20,9 +20,10 @@ LIB_PATH = os.path.join(HERE, "libscsurf.so")
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EHASHFULL, SC_EPOOLFULL, SC_ENOTALLOC, SC_EWEIGHT, SC_EDEVICE, SC_ENOLIB = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-SC_ERANGE = -9
+SC_ERANGE, SC_ESCRATCH = -9, -10
 STATUS = {0: "SC_OK", -1: "SC_EINVAL", -2: "SC_ENOMEM", -3: "SC_EHASHFULL", -4: "SC_EPOOLFULL",
-          -5: "SC_ENOTALLOC", -6: "SC_EWEIGHT", -7: "SC_EDEVICE", -8: "SC_ENOLIB", -9: "SC_ERANGE"}
+          -5: "SC_ENOTALLOC", -6: "SC_EWEIGHT", -7: "SC_EDEVICE", -8: "SC_ENOLIB", -9: "SC_ERANGE",
+          -10: "SC_ESCRATCH"}
 COLOR_RGBA8, COLOR_F32 = 0, 1
 SEL_EQ3, SEL_TOPM, SEL_ALL_ORDERED = 0, 1, 2
 
@@ -63,7 +64,7 @@ class sc_schedule(ctypes.Structure):
 
 
 EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
-           "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "hash_alloc", "tsdf_integrate",
+           "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "kf_fuse_noalloc", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
@@ -91,8 +92,9 @@ def lib():
     L.sc_volume_export.argtypes = [P, P, P, P, P, P, i64, ctypes.POINTER(i64)]
     L.sc_depth_weight.argtypes = [P, i32, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_fuse_params), P, P]
     L.sc_color_prep.argtypes = [P, i32, i32, i32, P, P, P]
-    L.kf_fuse.argtypes = [P, P, ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_intrinsics),
-                          ctypes.POINTER(sc_fuse_params), P, P, P, P]
+    for f in (L.kf_fuse, L.kf_fuse_noalloc):
+        f.argtypes = [P, P, ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_intrinsics),
+                      ctypes.POINTER(sc_fuse_params), P, P, P, P]
     L.hash_alloc.argtypes = [P, P, i64, P, P]
     for f in (L.tsdf_integrate, L.tsdf_deintegrate):
         f.argtypes = [P, ctypes.POINTER(sc_keyframe), ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), P]
@@ -562,8 +564,7 @@ def color_prep(rgb: torch.Tensor, stream=None):
     return sharp, wb
 
 
-def kf_fuse(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref=0, stream=None) -> Keyframe:
-    """Fuses frames (n,H,W) / (n,H,W,3) at poses (R, t) into one keyframe."""
+def _fuse(entry: str, depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params, ref, stream, out) -> Keyframe:
     if depth.dim() != 3:
         raise ValueError("depth must be (n, H, W)")
     n, H, W = depth.shape
@@ -573,11 +574,30 @@ def kf_fuse(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref
     if len(T) != n:
         raise ValueError(f"{len(T)} poses for {n} frames")
     dev = depth.device
-    kd = torch.empty((H, W), dtype=torch.float32, device=dev)
-    kw = torch.empty((H, W), dtype=torch.float32, device=dev)
-    kc = torch.empty((H, W, 4), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = Keyframe(torch.empty((H, W), dtype=torch.float32, device=dev),
+                       torch.empty((H, W), dtype=torch.float32, device=dev),
+                       torch.empty((H, W, 4), dtype=torch.uint8, device=dev))
+    _check_shape(out.depth, (H, W), "out.depth")
+    _check_shape(out.weight, (H, W), "out.weight")
+    _check_shape(out.color, (H, W, 4), "out.color")
     p = params or fuse_params()
-    check(lib().kf_fuse(dptr(depth, torch.float32, "depth"), dptr(rgb, torch.uint8, "rgb"), T, n, ref,
-                        ctypes.byref(intrinsics(intr)), ctypes.byref(p), kd.data_ptr(), kw.data_ptr(), kc.data_ptr(),
-                        stream_handle(stream)), "kf_fuse")
-    return Keyframe(kd, kw, kc)
+    check(getattr(lib(), entry)(dptr(depth, torch.float32, "depth"), dptr(rgb, torch.uint8, "rgb"), T, n, ref,
+                                ctypes.byref(intrinsics(intr)), ctypes.byref(p),
+                                dptr(out.depth, torch.float32, "out.depth"),
+                                dptr(out.weight, torch.float32, "out.weight"),
+                                dptr(out.color, torch.uint8, "out.color"), stream_handle(stream)), entry)
+    return out
+
+
+def kf_fuse(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref=0, stream=None, out=None) -> Keyframe:
+    """Fuses frames (n,H,W) / (n,H,W,3) at poses (R, t) into one keyframe."""
+    return _fuse("kf_fuse", depth, rgb, R, t, intr, params, ref, stream, out)
+
+
+def kf_fuse_noalloc(depth: torch.Tensor, rgb: torch.Tensor, R, t, intr, params=None, ref=0, stream=None,
+                    out=None) -> Keyframe:
+    """kf_fuse whose library side allocates nothing (fixed per-device
+    scratch); pass `out` (a Keyframe of preallocated tensors) for a call that
+    allocates nothing on the Python side either."""
+    return _fuse("kf_fuse_noalloc", depth, rgb, R, t, intr, params, ref, stream, out)

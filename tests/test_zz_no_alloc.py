@@ -1,0 +1,73 @@
+"""The allocation-free fusion entry point, kf_fuse_noalloc, against kf_fuse:
+bit-identical keyframes on two consecutive calls that share its fixed
+per-device scratch (the second call smaller than the first, so stale
+contents of the larger one are present), preallocated outputs fully
+written, and an input beyond the scratch rejected with SC_ESCRATCH."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_03763_amd import scsurf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _garbage(H, W):
+    # outputs prefilled with values no fusion produces, so an unwritten
+    # pixel shows up in the comparison
+    return scsurf.Keyframe(torch.full((H, W), float("nan"), device="cuda"),
+                           torch.full((H, W), -1.0, device="cuda"),
+                           torch.full((H, W, 4), 7, dtype=torch.uint8, device="cuda"))
+
+
+def _equal(a, b):
+    assert torch.equal(a.weight, b.weight)
+    assert torch.equal(a.depth, b.depth)
+    assert torch.equal(a.color, b.color)
+
+
+def test_noalloc_equals_kf_fuse_on_two_calls():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    # first call: 20 frames at 640x480, the largest group the scratch holds
+    wl_a = synth.workload(2)
+    ia = np.arange(40, 60)
+    za, ca = synth.frames(wl_a, ia)
+    # second call: 5 frames at 320x240
+    wl_b = synth.workload(1)
+    zb, cb = synth.frames(wl_b, np.arange(5))
+    za_d, ca_d, zb_d, cb_d = _cuda(za), _cuda(ca), _cuda(zb), _cuda(cb)
+    _say("kf_fuse references: 20 frames 640x480, 5 frames 320x240")
+    ref_a = scsurf.kf_fuse(za_d, ca_d, wl_a.R[ia], wl_a.t[ia], wl_a.intr)
+    ref_b = scsurf.kf_fuse(zb_d, cb_d, wl_b.R[:5], wl_b.t[:5], wl_b.intr)
+    _say("kf_fuse_noalloc: 20 frames 640x480, then 5 frames 320x240")
+    out_a = scsurf.kf_fuse_noalloc(za_d, ca_d, wl_a.R[ia], wl_a.t[ia], wl_a.intr, out=_garbage(480, 640))
+    out_b = scsurf.kf_fuse_noalloc(zb_d, cb_d, wl_b.R[:5], wl_b.t[:5], wl_b.intr, out=_garbage(240, 320))
+    torch.cuda.synchronize()
+    _equal(out_a, ref_a)
+    _equal(out_b, ref_b)
+    assert (ref_a.weight > 0).float().mean().item() > 0.3
+    # the smaller keyframe also equals the oracle's
+    o = oracle.kf_fuse(zb, cb, wl_b.intr, wl_b.R[:5], wl_b.t[:5])
+    np.testing.assert_array_equal(out_b.weight.cpu().numpy(), o["weight"])
+    np.testing.assert_array_equal(out_b.depth.cpu().numpy(), o["depth"])
+    np.testing.assert_array_equal(out_b.color.cpu().numpy(), o["color"])
+
+
+def test_noalloc_rejects_input_beyond_scratch():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(2)
+    n = 21  # 640x480: 16 HW + 10 HW n bytes exceed 64 MiB from 21 frames on
+    z = torch.zeros((n, 480, 640), device="cuda")
+    c = torch.zeros((n, 480, 640, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(scsurf.ScError) as e:
+        scsurf.kf_fuse_noalloc(z, c, wl.R[:n], wl.t[:n], wl.intr)
+    assert e.value.status == scsurf.SC_ESCRATCH
