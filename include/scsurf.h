@@ -250,6 +250,13 @@ int32_t sc_select(const sc_pose* T, const sc_pose* T_new, int32_t K, int32_t m, 
 /* The same selection from given distances (host, K). */
 int32_t sc_select_dist(const double* dist, int32_t K, int32_t m, int32_t mode, int32_t* out);
 
+/* Motion of a frame pose T relative to a keyframe's first pose T_kf, the
+ * quantities of the distance keyframe strategy (Sec. 4.2): *trans = |d| and
+ * *angle = atan2(sin, cos) of the rotation of T_kf^-1 T = (A, d), with
+ * A - A^T = 2 sin [axis]x and trace A = 1 + 2 cos (radians, [0, pi]).
+ * Host only, FP64.  SC_EINVAL on a null pointer. */
+sc_status sc_relative_motion(const sc_pose* T_kf, const sc_pose* T, double* trans, double* angle);
+
 /* Applies one pose-graph update in a single batched pass: selects keyframes
  * (mode, m), de-integrates each selected keyframe at its integration pose
  * and re-integrates it at its new pose (all de-integrations first, then all

@@ -90,6 +90,26 @@ int32_t sc_select_dist(const double* dist, int32_t K, int32_t m, int32_t mode, i
     return n;
 }
 
+sc_status sc_relative_motion(const sc_pose* T_kf, const sc_pose* T, double* trans, double* angle)
+{
+    if (!T_kf || !T || !trans || !angle) return SC_EINVAL;
+    // A = R_kf^T R, d = R_kf^T (t - t_kf)
+    double A[9], d[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            A[3 * r + c] = T_kf->R[r] * T->R[c] + T_kf->R[3 + r] * T->R[3 + c] + T_kf->R[6 + r] * T->R[6 + c];
+        d[r] = T_kf->R[r] * (T->t[0] - T_kf->t[0]) + T_kf->R[3 + r] * (T->t[1] - T_kf->t[1]) +
+               T_kf->R[6 + r] * (T->t[2] - T_kf->t[2]);
+    }
+    // R - R^T = 2 sin(theta) [axis]x and trace(R) = 1 + 2 cos(theta)
+    const double sx = A[7] - A[5], sy = A[2] - A[6], sz = A[3] - A[1];
+    const double s2 = sqrt(sx * sx + sy * sy + sz * sz) / 2.0;
+    const double c2 = (A[0] + A[4] + A[8] - 1.0) / 2.0;
+    *trans = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    *angle = atan2(s2, c2);
+    return SC_OK;
+}
+
 int32_t sc_select(const sc_pose* T, const sc_pose* T_new, int32_t K, int32_t m, int32_t mode, int32_t* out,
                   double* dist_out)
 {

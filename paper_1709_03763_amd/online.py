@@ -29,16 +29,6 @@ from . import scsurf
 MAX_FRAMES = 64  # frames one keyframe may fuse
 
 
-def relative_motion(R_kf, t_kf, R, t):
-    """(translation norm, rotation angle in radians) of T_kf^-1 T, the angle
-    as atan2 of sin and cos (R - R^T = 2 sin [axis]x, trace = 1 + 2 cos)."""
-    A = np.asarray(R_kf, np.float64).T @ np.asarray(R, np.float64)
-    d = np.asarray(R_kf, np.float64).T @ (np.asarray(t, np.float64) - np.asarray(t_kf, np.float64))
-    s = np.sqrt((A[2, 1] - A[1, 2]) ** 2 + (A[0, 2] - A[2, 0]) ** 2 + (A[1, 0] - A[0, 1]) ** 2) / 2.0
-    c = (np.trace(A) - 1.0) / 2.0
-    return float(np.sqrt(d @ d)), float(np.arctan2(s, c))
-
-
 class OnlineSession:
     def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None,
                  strategy: str = "const", max_trans: float = 0.1, max_rot: float = 0.0873,
@@ -70,7 +60,7 @@ class OnlineSession:
         if len(self._depth) >= MAX_FRAMES:
             return True
         if self.strategy == "dist":
-            dt, dr = relative_motion(self._R[0], self._t[0], R, t)
+            dt, dr = scsurf.relative_motion(self._R[0], self._t[0], R, t)
             return dt > self.max_trans or dr > self.max_rot
         if self.strategy == "overlap":
             valid, visible = scsurf.overlap(depth, self.intr, R, t, self._R[0], self._t[0], self.z_min, self.z_max,

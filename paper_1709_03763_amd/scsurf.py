@@ -65,7 +65,8 @@ class sc_schedule(ctypes.Structure):
 
 EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "kf_fuse_noalloc", "hash_alloc", "tsdf_integrate",
-           "tsdf_deintegrate", "sc_select", "sc_select_dist", "reintegrate_batch", "reintegrate_plain",
+           "tsdf_deintegrate", "sc_select", "sc_select_dist", "sc_relative_motion", "reintegrate_batch",
+           "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
            "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table",
@@ -100,6 +101,8 @@ def lib():
         f.argtypes = [P, ctypes.POINTER(sc_keyframe), ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), P]
     L.sc_select.argtypes = [ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, i32, P, P]
     L.sc_select_dist.argtypes = [P, i32, i32, i32, P]
+    L.sc_relative_motion.argtypes = [ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     for f in (L.reintegrate_batch, L.reintegrate_plain):
         f.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose),
                       ctypes.POINTER(sc_pose), i32, i32, P, ctypes.POINTER(i32), P]
@@ -492,6 +495,15 @@ class Volume:
             opt(grad_C, "grad_C"), dptr(grad_depth, torch.float32, "grad_depth"), opt(grad_color, "grad_color"),
             dptr(grad_xi, torch.float32, "grad_xi"), opt(grad_D0, "grad_D0"), opt(grad_C0, "grad_C0"),
             stream_handle(stream)), "tsdf_integrate_backward")
+
+
+def relative_motion(R_kf, t_kf, R, t):
+    """(translation norm, rotation angle in radians) of T_kf^-1 T, computed by
+    the library (the distance keyframe strategy, Sec. 4.2)."""
+    tr, ang = ctypes.c_double(), ctypes.c_double()
+    check(lib().sc_relative_motion(ctypes.byref(pose(R_kf, t_kf)), ctypes.byref(pose(R, t)), ctypes.byref(tr),
+                                   ctypes.byref(ang)), "sc_relative_motion")
+    return float(tr.value), float(ang.value)
 
 
 def select(T_int, T_new, m, mode=SEL_EQ3):

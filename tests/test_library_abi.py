@@ -64,3 +64,31 @@ def test_library_mesh_table_matches_oracle():
     loops, ntri = surface.mesh_table()
     assert loops == [[(list(l), bool(c)) for l, c in M.LOOPS[k]] for k in range(256)]
     assert ntri == [len(M.TABLE[k]) for k in range(256)]
+
+
+def _rot(axis, ang):
+    c, s = np.cos(ang), np.sin(ang)
+    R = np.eye(3)
+    i, j = [(1, 2), (0, 2), (0, 1)][axis]
+    R[i, i], R[i, j], R[j, i], R[j, j] = c, -s, s, c
+    return R
+
+
+def test_library_relative_motion():
+    """The distance strategy's quantities (Sec. 4.2) from the library: closed
+    forms (a rotation about one axis after a fixed keyframe rotation, and a
+    translation of length 0.5 in the keyframe frame), and agreement with the
+    oracle's own computation on random poses."""
+    from oracle import strategies
+    Rk, tk = _rot(2, 0.4), np.array([1.0, 2.0, 0.5])
+    for axis, ang in ((0, 0.1), (1, 1.2), (2, 3.0), (0, 1e-9), (1, np.pi)):
+        R = Rk @ _rot(axis, ang)
+        t = tk + Rk @ np.array([0.3, 0.0, 0.4])
+        dt, dr = scsurf.relative_motion(Rk, tk, R, t)
+        assert abs(dt - 0.5) < 1e-12
+        assert abs(dr - ang) < 1e-7
+    wl = synth.workload(5)
+    for f in range(0, 300, 7):
+        a = scsurf.relative_motion(wl.R[f], wl.t[f], wl.R[f + 9], wl.t[f + 9])
+        b = strategies.relative_motion(wl.R[f], wl.t[f], wl.R[f + 9], wl.t[f + 9])
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)

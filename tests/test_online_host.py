@@ -2,7 +2,7 @@
 pose-graph correction used by the online loop's tests and benchmark."""
 import numpy as np
 
-from paper_1709_03763_amd import online, synth
+from paper_1709_03763_amd import scsurf, online, synth
 
 
 def _poses(n, seed=0):
@@ -100,7 +100,7 @@ def test_relative_motion_closed_forms():
         Ra, ta = synth.se3_exp(np.array([0.1, 0.2, 0.3, 0.4, -0.2, 0.9]))
         dR, dt = synth.se3_exp(np.concatenate([[0, 0, 0], ang * axis]))
         Rb, tb = synth.compose(Ra, ta, dR, np.array([0.3, 0.0, -0.4]))
-        d, a = online.relative_motion(Ra, ta, Rb, tb)
+        d, a = scsurf.relative_motion(Ra, ta, Rb, tb)
         assert abs(d - 0.5) < 1e-12 and abs(a - ang) < 1e-9
 
 
