@@ -191,6 +191,8 @@ def kernel_variant(sched):
     """Name of the voxel-pass kernel a schedule (vpl, waves_per_wg, wgs_per_cu,
     compact) launches."""
     vpl, _, _, compact = sched
+    if compact == 4:
+        return "batch_ring_kernel<RGBA8,packed>"
     if compact == 3:
         return "batch_pipe_kernel<RGBA8>"
     if compact:

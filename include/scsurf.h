@@ -92,9 +92,11 @@ typedef struct {
 /* A fused keyframe (Sec. 4.1): depth Z*, fusion weight W*, colour C*.
  * `packed` is optional (NULL: not used): a device copy of the same keyframe
  * interleaved for the voxel passes, H x W records of 16 bytes
- * {float depth, float weight, uint32 RGBA8 colour, uint32 0}, 16-byte
- * aligned, as written by sc_keyframe_pack.  Volumes in RGBA8 mode then read
- * every keyframe sample from it (one 16-byte gather per voxel instead of
+ * {float depth', float q(weight), uint32 RGBA8 colour, uint32 0} with
+ * q(w) = rint(w 2^10) / 2^10 and depth' = depth where q(weight) > 0, -inf
+ * elsewhere (so the band test alone rejects a pixel without weight),
+ * 16-byte aligned, as written by sc_keyframe_pack.  Volumes in RGBA8 mode
+ * then read every keyframe sample from it (one gather per voxel instead of
  * three); FP32-colour volumes ignore it.  It must hold the packing of this
  * keyframe's depth, weight and colour, and is owned by the caller. */
 typedef struct {
@@ -114,8 +116,8 @@ typedef struct {
 typedef struct sc_volume sc_volume;
 
 /* Writes the interleaved copy of an RGBA8 keyframe used by the voxel passes:
- * packed[i] = {depth[i], weight[i], color[i], 0} for the width * height
- * pixels.  `packed` is a caller-owned device buffer of width * height * 16
+ * packed[i] = {q(weight[i]) > 0 ? depth[i] : -inf, q(weight[i]), color[i], 0}
+ * for the width * height pixels (q as in sc_keyframe).  `packed` is a caller-owned device buffer of width * height * 16
  * bytes, 16-byte aligned.  SC_EINVAL on a null pointer, a misaligned buffer
  * or a non-positive size; asynchronous on `stream`. */
 sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream);
@@ -288,7 +290,10 @@ sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
  *                an LDS queue and updated by all 64 lanes together; 2 tests
  *                a lane's voxels four at a time (fewer registers); 3 does as
  *                2 and issues the keyframe gathers of the next four voxels
- *                (or the next operation) before updating the current ones.
+ *                (or the next operation) before updating the current ones;
+ *                4 does as 3 with the touched voxels of an operation
+ *                collected in a ring and updated 64 at a time, and the block
+ *                geometry computed once per (block, operation).
  * Every schedule gives identical bits.  sc_set_schedule validates and stores
  * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back. */
 typedef struct {

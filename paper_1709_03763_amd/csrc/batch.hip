@@ -790,6 +790,327 @@ __global__ __launch_bounds__(256) void batch_pipe_kernel(const OpDesc* __restric
     stat_add(cd, 3, worker, n_written, lane);
 }
 
+// ---------------------------------------------------------------------------
+// ring-queue voxel pass (schedule compact = 4)
+//
+// As the pipelined pass, with four changes that cut its instructions per
+// voxel test: the touched voxels of an operation collect in a 128-entry LDS
+// ring that is updated 64 entries at a time (the pipelined pass updates each
+// pair of z-slices separately, so most of its update rounds run half
+// empty); the block origin and each lane's column base are computed once per
+// (block, operation) instead of once per part; the pixel coordinate uses
+// pixel_coord_fast; and the gathers of packed keyframes (pre-quantised
+// weight, depth masked to -inf) need no weight test.  The gathers of the
+// next step are issued as global (not flat) loads on every step, so the
+// wait for the current step's samples leaves them in flight.
+// ---------------------------------------------------------------------------
+
+// A block's geometry under one operation: the lane's FP32 camera point of
+// voxel (x, y, 0) of its column, and the camera z of the block origin in FP64.
+struct RingGeom {
+    float base[3];
+    double qz;
+};
+
+__device__ inline void ring_geom(const OpDesc& o, const VolDev& v, const PipeBlock& pb, int lane, RingGeom& g)
+{
+    float q[3];
+    block_origin(o, v.s, pb.bx, pb.by, pb.bz, q, g.qz);
+    const float kx = (float)(lane & 7), ky = (float)(lane >> 3);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) g.base[r] = (q[r] + kx * o.a[0][r]) + ky * o.a[1][r];
+}
+
+typedef __attribute__((address_space(1))) const unsigned char GlobalBytes;
+typedef __attribute__((address_space(1))) const float GlobalF32;
+typedef __attribute__((address_space(1))) const uint32_t GlobalU32;
+
+// Element `i` of a keyframe array through a 32-bit byte offset from a
+// uniform base (a global load with a scalar base and a vector offset).
+template <class T, class G>
+__device__ inline T kf_load(const void* base, uint32_t i)
+{
+    return *(G*)((GlobalBytes*)base + i * (uint32_t)sizeof(T));
+}
+
+// Projections of the lane's voxels in z-slices kz0 .. kz0 + 3 and their
+// keyframe gathers (voxels outside the image read pixel 0): one record per
+// voxel from a packed keyframe, else depth, weight and (RGBA8) colour.
+template <int CM, bool kPacked>
+__device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, VoxFetch<CM, 4>& f)
+{
+    f.in = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float fz = (float)(kz0 + j);
+        const float px = g.base[0] + fz * o.a[2][0];
+        const float py = g.base[1] + fz * o.a[2][1];
+        const float pz = g.base[2] + fz * o.a[2][2];
+        int p = 0;
+        const bool in = nearest_pixel_fast(o, px, py, pz, p);
+        f.in |= in ? (1u << j) : 0u;
+        f.pix[j] = in ? p : 0;
+        f.pz[j] = pz;
+    }
+    if (kPacked) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // the record's first three words, adjacent: one 12-byte load
+            const uint32_t i = 4u * (uint32_t)f.pix[j];
+            f.z[j] = __uint_as_float(kf_load<uint32_t, GlobalU32>(o.packed, i));
+            f.wr[j] = __uint_as_float(kf_load<uint32_t, GlobalU32>(o.packed, i + 1u));
+            f.c[j] = kf_load<uint32_t, GlobalU32>(o.packed, i + 2u);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            f.wr[j] = kf_load<float, GlobalF32>(o.weight, (uint32_t)f.pix[j]);
+            f.z[j] = kf_load<float, GlobalF32>(o.depth, (uint32_t)f.pix[j]);
+            f.c[j] = (CM == SC_COLOR_RGBA8) ? kf_load<uint32_t, GlobalU32>(o.color, (uint32_t)f.pix[j]) : 0u;
+        }
+    }
+}
+
+// Touched decisions of fetched voxels; with kPacked the weight is already
+// quantised and the depth of a pixel without weight is -inf.
+template <int CM, bool kPacked>
+__device__ inline uint32_t ring_decide(const VoxFetch<CM, 4>& f, float mu, float w[4])
+{
+    uint32_t hit = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        w[j] = kPacked ? f.wr[j] : qweight(f.wr[j]);
+        const bool t = ((f.in >> j) & 1u) && (kPacked || w[j] > 0.0f) && fabsf(f.z[j] - f.pz[j]) <= mu;
+        hit |= t ? (1u << j) : 0u;
+    }
+    return hit;
+}
+
+// The operations of a block in bit order, its mask words held one per lane
+// (loaded once per block, so the walk issues no load that a wait could
+// confuse with the keyframe gathers in flight).  words <= 64.
+struct LaneWalk {
+    uint64_t mine;  // mask word `lane`
+    uint64_t nz;    // words not yet visited that hold a bit
+    uint64_t m;     // remaining bits of the current word
+    int w;
+};
+
+__device__ inline void lanewalk_init(LaneWalk& k, const uint64_t* mask, int words, int lane)
+{
+    k.mine = (lane < words) ? mask[lane] : 0ull;
+    k.nz = __ballot(k.mine != 0ull);
+    k.m = 0ull;
+    k.w = 0;
+}
+
+__device__ inline int lanewalk_next(LaneWalk& k)
+{
+    while (k.m == 0ull) {
+        if (k.nz == 0ull) return -1;
+        k.w = __ffsll((unsigned long long)k.nz) - 1;
+        k.nz &= k.nz - 1;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)k.mine, k.w);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(k.mine >> 32), k.w);
+        k.m = ((uint64_t)hi << 32) | lo;
+    }
+    const int b = __ffsll((unsigned long long)k.m) - 1;
+    k.m &= k.m - 1;
+    return k.w * 64 + b;
+}
+
+// Ring positions of the queue (uniform): entries [head, tail), modulo 128.
+struct Ring {
+    uint32_t head, tail;
+};
+
+// Updates the n <= 64 oldest queue entries, one per lane (the voxels are
+// distinct: they belong to one operation).
+template <int CM>
+__device__ inline void ring_flush(const OpDesc& op, double qz, Ring& ring, uint32_t n, PipeBlock& pb, int lane,
+                                  const PipeLds& L)
+{
+    wave_lds_sync();
+    if ((uint32_t)lane < n) {
+        const uint32_t e = (ring.head + (uint32_t)lane) & 127u;
+        const int x = L.qvox[e];
+        const double pz64 =
+            ((qz + (double)(x & 7) * op.az[0]) + (double)((x >> 3) & 7) * op.az[1]) + (double)(x >> 6) * op.az[2];
+        const double d = distance(L.qz[e], pz64);
+        const float wq = L.qw[e];
+        double D = L.sD[x];
+        float W = L.sW[x];
+        if (CM == SC_COLOR_RGBA8) {
+            uint32_t C = L.sC[x];
+            pb.e_w |= !update_rgba8(D, W, C, d, wq, L.qc[e], op.sign);
+            L.sC[x] = C;
+        } else {
+            GlobalF32* cp = (GlobalF32*)op.color + 3 * (size_t)L.qc[e];
+            const float c[3] = {cp[0], cp[1], cp[2]};
+            double C3[3] = {L.sCf[x], L.sCf[512 + x], L.sCf[1024 + x]};
+            pb.e_w |= !update_f32(D, W, C3, d, wq, c, op.sign);
+            L.sCf[x] = C3[0];
+            L.sCf[512 + x] = C3[1];
+            L.sCf[1024 + x] = C3[2];
+        }
+        L.sD[x] = D;
+        L.sW[x] = W;
+    }
+    ring.head += n;
+    wave_lds_sync();
+}
+
+// One step of the ring pass: geometry and gathers of the next (operation,
+// part) first, then the decisions of the current one, its touched voxels
+// appended slice by slice to the ring, 64 updated whenever 64 are waiting,
+// and the rest when the operation's second part is done.  Returns false
+// when the block has no further step.
+template <int CM, bool kPacked>
+__device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v, LaneWalk& walk, PipeBlock& pb,
+                                 VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, RingGeom& gc, int& op_c, int& part_c,
+                                 int lane, const PipeLds& L, Ring& ring)
+{
+    int op_n, part_n;
+    if (part_c == 0) {
+        op_n = op_c;
+        part_n = 1;
+    } else {
+        op_n = lanewalk_next(walk);
+        part_n = 0;
+    }
+    RingGeom gn = gc;
+    if (part_n == 0 && op_n >= 0) ring_geom(ops[op_n], v, pb, lane, gn);
+    // issued on every step (a block's last step fetches its own part again),
+    // so the number of loads in flight is the same on every path
+    ring_fetch<CM, kPacked>(ops[op_n >= 0 ? op_n : op_c], gn, 4 * (op_n >= 0 ? part_n : part_c), nxt);
+    const OpDesc& op = ops[op_c];
+    pb.pairs += (part_c == 0) ? 1u : 0u;
+    float w[4];
+    const uint32_t hit = ring_decide<CM, kPacked>(cur, v.mu, w);
+    const bool any = __ballot(hit != 0u) != 0ull;
+    if (any && op.sign < 0 && pb.slot < 0) {
+        pb.e_na = true;
+    } else if (any) {
+        if (op.sign > 0) pb.re_touch = true;
+        pb.touched |= hit << (part_c * 4);
+        pb.n_upd += __popc(hit);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool t = (hit >> j) & 1u;
+            const uint64_t bal = __ballot(t);
+            if (t) {
+                const uint32_t pos = (ring.tail + lanes_below(bal)) & 127u;
+                L.qvox[pos] = (uint16_t)(lane + 64 * (part_c * 4 + j));
+                L.qw[pos] = w[j];
+                L.qz[pos] = cur.z[j];
+                L.qc[pos] = (CM == SC_COLOR_RGBA8) ? cur.c[j] : (uint32_t)cur.pix[j];
+            }
+            ring.tail += (uint32_t)__popcll(bal);
+            if (ring.tail - ring.head >= 64u) ring_flush<CM>(op, gc.qz, ring, 64u, pb, lane, L);
+        }
+    }
+    if (part_c == 1 && ring.tail != ring.head) ring_flush<CM>(op, gc.qz, ring, ring.tail - ring.head, pb, lane, L);
+    if (op_n < 0) return false;
+    op_c = op_n;
+    part_c = part_n;
+    gc = gn;
+    return true;
+}
+
+// Persistent voxel pass with the ring queue: one wavefront per block, block
+// state in LDS, the same LDS footprint as the pipelined pass.  kPacked: every
+// operation's keyframe carries its packed copy (RGBA8 volumes).
+template <int CM, bool kPacked>
+__global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)bcast(threadIdx.x >> 6);
+    const PipeLds L = pipe_lds<CM>(smem + (size_t)wave * pipe_wave_bytes<CM>());
+    const uint32_t n = cd.counters[4];
+    const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
+    const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
+    WorkCursor cur;
+    cursor_init(cur, worker);
+    uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
+    for (;;) {
+        const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
+        if (i >= n) break;
+        const uint32_t h = bcast(cd.sorted[i]);
+        const uint64_t key = bcast64(cd.skey[i]);
+        PipeBlock pb;
+        pb.slot = (int)bcast((uint32_t)cd.sslot[i]);
+        unpack_key(key, pb.bx, pb.by, pb.bz);
+        pb.touched = pb.n_upd = pb.pairs = 0u;
+        pb.re_touch = pb.e_na = pb.e_w = false;
+        {
+            const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
+            const bool have = pb.slot >= 0;
+#pragma unroll 4
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                L.sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+                L.sW[x] = have ? blk[kPoolW + x] : 0.0f;
+                if (CM == SC_COLOR_RGBA8) {
+                    L.sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
+                } else {
+                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
+                    L.sCf[x] = have ? Cd[x] : 0.0;
+                    L.sCf[512 + x] = have ? Cd[512 + x] : 0.0;
+                    L.sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
+                }
+            }
+        }
+        wave_lds_sync();
+        LaneWalk walk;
+        lanewalk_init(walk, cd.mask + (size_t)h * cd.words, cd.words, lane);
+        int op_c = lanewalk_next(walk);
+        if (op_c >= 0) {
+            VoxFetch<CM, 4> f0, f1;
+            RingGeom gc;
+            Ring ring;
+            ring.head = ring.tail = 0u;
+            int part_c = 0;
+            ring_geom(ops[op_c], v, pb, lane, gc);
+            ring_fetch<CM, kPacked>(ops[op_c], gc, 0, f0);
+            for (;;) {
+                if (!ring_step<CM, kPacked>(ops, v, walk, pb, f0, f1, gc, op_c, part_c, lane, L, ring)) break;
+                if (!ring_step<CM, kPacked>(ops, v, walk, pb, f1, f0, gc, op_c, part_c, lane, L, ring)) break;
+            }
+        }
+        n_pairs += pb.pairs;
+        n_upd += pb.n_upd;
+        const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
+        int slot = pb.slot;
+        if (slot < 0 && (all & 1)) slot = vol_insert_wave(v, key, pb.bx, pb.by, pb.bz, lane);
+        if (slot >= 0) {
+            float* blk = v.pool + (size_t)slot * v.stride;
+#pragma unroll 2
+            for (int j = 0; j < 8; ++j) {
+                if (!((pb.touched >> j) & 1u)) continue;
+                const int x = lane + 64 * j;
+                reinterpret_cast<double*>(blk)[x] = L.sD[x];
+                blk[kPoolW + x] = L.sW[x];
+                if (CM == SC_COLOR_RGBA8) {
+                    reinterpret_cast<uint32_t*>(blk + kPoolC)[x] = L.sC[x];
+                } else {
+                    double* Cd = reinterpret_cast<double*>(blk + kPoolC);
+                    Cd[x] = L.sCf[x];
+                    Cd[512 + x] = L.sCf[512 + x];
+                    Cd[1024 + x] = L.sCf[1024 + x];
+                }
+            }
+        }
+        const bool wrote = __ballot(pb.touched != 0) != 0;
+        n_written += (slot >= 0 && wrote) ? 1u : 0u;
+        retire_candidate(cd, v, h, all, lane);
+        wave_lds_sync();
+    }
+    stat_add(cd, 1, worker, n_pairs, lane);
+    stat_add(cd, 2, worker, wave_sum(n_upd), lane);
+    stat_add(cd, 3, worker, n_written, lane);
+}
+
 // Persistent voxel pass, one workgroup of G = 8 / VPL wavefronts per block
 // (wavefront w owns z in [w VPL, (w+1) VPL)).  Wavefront 0 pops and
 // allocates; the others learn the results through LDS after a barrier.  The
@@ -871,7 +1192,7 @@ __global__ __launch_bounds__(512) void batch_main_group_kernel(const OpDesc* __r
 static bool schedule_ok(const sc_schedule& s)
 {
     if (s.vpl != 8 && s.vpl != 4 && s.vpl != 2 && s.vpl != 1) return false;
-    if (s.compact < 0 || s.compact > 3) return false;
+    if (s.compact < 0 || s.compact > 4) return false;
     if (s.compact && (s.vpl != 8 || (s.waves_per_wg != 1 && s.waves_per_wg != 2 && s.waves_per_wg != 4)))
         return false;
     return s.wgs_per_cu >= 1 && s.wgs_per_cu <= 32;
@@ -890,15 +1211,26 @@ static void launch_candidates(sc_volume* vol, hipStream_t s)
     scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, vol->dev, n_bins);
 }
 
-// The persistent voxel pass with schedule `sch`.
-static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, hipStream_t s)
+// The persistent voxel pass with schedule `sch`; `packed`: every operation
+// of the chunk has a packed keyframe (RGBA8 volumes).
+static void launch_voxel_pass(sc_volume* vol, const sc_schedule& sch, bool packed, hipStream_t s)
 {
     const bool rgba = vol->p.color_mode == SC_COLOR_RGBA8;
     const int grid = vol->n_cu * sch.wgs_per_cu;
     if (sch.compact) {
         const int threads = 64 * sch.waves_per_wg;
         const size_t w = sch.waves_per_wg;
-        if (sch.compact == 3) {
+        if (sch.compact == 4) {
+            if (rgba && packed)
+                batch_ring_kernel<SC_COLOR_RGBA8, true><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_RGBA8>(), s>>>(
+                    vol->d_ops, vol->dev, vol->cand);
+            else if (rgba)
+                batch_ring_kernel<SC_COLOR_RGBA8, false><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_RGBA8>(), s>>>(
+                    vol->d_ops, vol->dev, vol->cand);
+            else
+                batch_ring_kernel<SC_COLOR_F32, false><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_F32>(), s>>>(
+                    vol->d_ops, vol->dev, vol->cand);
+        } else if (sch.compact == 3) {
             if (rgba)
                 batch_pipe_kernel<SC_COLOR_RGBA8><<<grid, threads, w * pipe_wave_bytes<SC_COLOR_RGBA8>(), s>>>(
                     vol->d_ops, vol->dev, vol->cand);
@@ -984,11 +1316,11 @@ static hipGraphExec_t capture(sc_volume* vol, F&& launch)
 }
 
 // Returns the candidate-stage graph and the voxel-pass graph for the current
-// schedule, capturing each on first use.
-static bool graphs_for(sc_volume* vol, hipGraphExec_t& pre, hipGraphExec_t& main)
+// schedule and keyframe form, capturing each on first use.
+static bool graphs_for(sc_volume* vol, bool packed, hipGraphExec_t& pre, hipGraphExec_t& main)
 {
     if (!vol->graph_pre) vol->graph_pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, cs); });
-    const int vi = sched_index(vol->sched);
+    const int vi = sched_index(vol->sched) + (packed ? 4 : 0);
     const int key = (vol->sched.compact * 8 + vol->sched.waves_per_wg) * 64 + vol->sched.wgs_per_cu;
     if (vol->graph_main[vi] && vol->graph_keys[vi] != key) {
         (void)hipGraphExecDestroy(vol->graph_main[vi]);
@@ -996,7 +1328,7 @@ static bool graphs_for(sc_volume* vol, hipGraphExec_t& pre, hipGraphExec_t& main
     }
     if (!vol->graph_main[vi]) {
         const sc_schedule sch = vol->sched;
-        vol->graph_main[vi] = capture(vol, [&](hipStream_t cs) { launch_voxel_pass(vol, sch, cs); });
+        vol->graph_main[vi] = capture(vol, [&](hipStream_t cs) { launch_voxel_pass(vol, sch, packed, cs); });
         vol->graph_keys[vi] = key;
     }
     pre = vol->graph_pre;
@@ -1032,8 +1364,10 @@ static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const s
 {
     const sc_status st = run_candidates(vol, ops, n_ops, in, s);
     if (st != SC_OK) return st;
+    bool packed = vol->p.color_mode == SC_COLOR_RGBA8;
+    for (int i = 0; i < n_ops && packed; ++i) packed = ops[i].packed != nullptr;
     hipGraphExec_t pre = nullptr, main = nullptr;
-    if (!graphs_for(vol, pre, main)) return SC_EDEVICE;
+    if (!graphs_for(vol, packed, pre, main)) return SC_EDEVICE;
     const bool timed = vol->timing_n < vol->timing_cap;
     if (timed && hipEventRecord(vol->timing_ev[2 * vol->timing_n], s) != hipSuccess) return SC_EDEVICE;
     if (hipGraphLaunch(main, s) != hipSuccess) return SC_EDEVICE;
@@ -1211,7 +1545,8 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     static const sc_schedule cands[] = {{8, 4, 2, 0}, {8, 4, 4, 0}, {8, 4, 8, 0}, {4, 2, 8, 0}, {4, 2, 16, 0},
                                         {2, 4, 4, 0}, {2, 4, 8, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {8, 4, 2, 1},
                                         {8, 4, 4, 1}, {8, 2, 4, 1},  {8, 2, 8, 1},  {8, 1, 16, 1}, {8, 4, 4, 2},
-                                        {8, 2, 8, 2}, {8, 1, 16, 2}, {8, 4, 4, 3},  {8, 2, 8, 3},  {8, 1, 16, 3}};
+                                        {8, 2, 8, 2}, {8, 1, 16, 2}, {8, 4, 4, 3},  {8, 2, 8, 3},  {8, 1, 16, 3},
+                                        {8, 4, 4, 4}, {8, 2, 8, 4},  {8, 1, 16, 4}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         sc_volume_destroy(tmp);

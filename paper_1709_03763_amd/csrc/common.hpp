@@ -128,8 +128,8 @@ struct sc_volume {
     hipEvent_t staged[2];    // recorded after each staging buffer's descriptors were copied to the device
     int stage;               // staging buffer the next chunk fills
     hipGraphExec_t graph_pre;   // captured candidate stage (init, candidates, histogram, scan, scatter)
-    hipGraphExec_t graph_main[4]; // captured voxel pass per voxels-per-lane choice
-    int graph_keys[4];       // schedule the voxel-pass graph of each slot was captured with
+    hipGraphExec_t graph_main[8]; // captured voxel pass per voxels-per-lane choice, unpacked / packed keyframes
+    int graph_keys[8];       // schedule the voxel-pass graph of each slot was captured with
     hipEvent_t* timing_ev;   // optional per-launch event pairs (2 * timing_cap)
     int timing_cap, timing_n;
     sc_schedule sched;

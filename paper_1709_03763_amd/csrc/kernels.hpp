@@ -150,6 +150,39 @@ __device__ inline float pixel_coord(float a, float z, float r, float c, float li
     return floorf(((a / z) + c) + 0.5f);
 }
 
+// The same pixel coordinate with one rounding test instead of two: with
+// tq = fl32(a r), |tq - t| <= |tq| 2^-22 (one ulp of rcp and two roundings),
+// and the two additions of the convention round by at most one ulp of their
+// results on either side, so the convention's f = fl32(fl32(t + c) + 1/2)
+// and fq = fl32(yq + 1/2), yq = fl32(tq + c), differ by at most
+// |tq| 2^-22 + |yq| 2^-22 + 2^-24.  yq - floor(fq) equals fq - floor(fq) - 1/2
+// to within |yq| 2^-24 + 2^-24, so when it lies inside (-1/2, 1/2) by more
+// than m = (|tq| + |yq|) 2^-21 + 2^-21 (which covers both terms), f and fq
+// have the same floor.  The rare lanes nearer a half-integer take the
+// interval test of pixel_coord.
+__device__ inline float pixel_coord_fast(float a, float z, float r, float c, float limit)
+{
+    const float tq = a * r;
+    const float yq = tq + c;
+    const float fl = floorf(yq + 0.5f);
+    const float inner = fmaf(fabsf(tq) + fabsf(yq), -0x1p-21f, 0.5f - 0x1p-21f);
+    if (fabsf(yq - fl) < inner) return fl;
+    return pixel_coord(a, z, r, c, limit);
+}
+
+// nearest_pixel with pixel_coord_fast.
+__device__ inline bool nearest_pixel_fast(const OpDesc& op, float px, float py, float pz, int& pix)
+{
+    if (!(pz > 0.0f)) return false;
+    const float r = __builtin_amdgcn_rcpf(pz);
+    const float wl = (float)(op.width - 1), hl = (float)(op.height - 1);
+    const float fu = pixel_coord_fast(op.fx * px, pz, r, op.cx, wl);
+    const float fv = pixel_coord_fast(op.fy * py, pz, r, op.cy, hl);
+    if (!(fu >= 0.0f && fu <= wl && fv >= 0.0f && fv <= hl)) return false;
+    pix = (int)fv * op.width + (int)fu;
+    return true;
+}
+
 // Nearest pixel of the FP32 camera point (px, py, pz); false if behind the
 // camera or outside the image.
 __device__ inline bool nearest_pixel(const OpDesc& op, float px, float py, float pz, int& pix)

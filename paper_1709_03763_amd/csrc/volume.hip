@@ -258,10 +258,15 @@ __global__ void export_kernel(VolDev v, int64_t n, int32_t* xyz, float* D, float
     }
 }
 
+// Packed record of a pixel: the quantised weight, and the depth only where
+// that weight is positive (-inf elsewhere, which fails every band test).
 __global__ void pack_kernel(const float* depth, const float* weight, const uint32_t* color, uint4* out, int64_t n)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = make_uint4(__float_as_uint(depth[i]), __float_as_uint(weight[i]), color[i], 0u);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float w = qweight(weight[i]);
+        const float z = (w > 0.0f) ? depth[i] : -__builtin_inff();
+        out[i] = make_uint4(__float_as_uint(z), __float_as_uint(w), color[i], 0u);
+    }
 }
 
 // ---------------------------------------------------------------------------

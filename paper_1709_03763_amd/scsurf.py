@@ -530,8 +530,10 @@ def select_dist(dist, m, mode=SEL_EQ3):
 
 
 def keyframe_pack(kf: Keyframe, stream=None) -> Keyframe:
-    """The keyframe with its interleaved {depth, weight, RGBA8, 0} copy
-    attached (RGBA8 keyframes; the voxel passes then gather from it)."""
+    """The keyframe with its interleaved {depth', q(weight), RGBA8, 0} copy
+    attached (RGBA8 keyframes; the voxel passes then gather from it): the
+    weight quantised to 2^-10 and the depth replaced by -inf where that weight
+    is not positive."""
     H, W = kf.depth.shape
     if kf.color.dtype != torch.uint8 or tuple(kf.color.shape) != (H, W, 4):
         raise ValueError("keyframe_pack needs an RGBA8 keyframe")

@@ -84,7 +84,8 @@ def test_batch_matches_oracle_and_plain(scene, f32, mode):
 
 
 @pytest.mark.parametrize("sched", [(8, 4, 4), (8, 4, 1), (4, 2, 8), (2, 4, 4), (1, 8, 2), (8, 4, 4, 1), (8, 2, 8, 1),
-                                   (8, 1, 3, 1), (8, 4, 4, 2), (8, 1, 5, 2), (8, 4, 4, 3), (8, 1, 5, 3)])
+                                   (8, 1, 3, 1), (8, 4, 4, 2), (8, 1, 5, 2), (8, 4, 4, 3), (8, 1, 5, 3),
+                                   (8, 4, 4, 4), (8, 2, 8, 4), (8, 1, 5, 4)])
 def test_every_schedule_gives_identical_bits(scene, sched):
     wl, kfs, R, t = scene
     Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 5)
@@ -98,7 +99,7 @@ def test_every_schedule_gives_identical_bits(scene, sched):
     vol.close()
 
 
-@pytest.mark.parametrize("sched", [(8, 2, 4, 1), (8, 2, 4, 2), (8, 2, 4, 3), (4, 2, 8)])
+@pytest.mark.parametrize("sched", [(8, 2, 4, 1), (8, 2, 4, 2), (8, 2, 4, 3), (8, 2, 4, 4), (8, 1, 7, 4), (4, 2, 8)])
 def test_fp32_colour_schedules(scene, sched):
     """FP32-colour volumes under the compacting and the multi-wavefront
     passes."""
@@ -118,15 +119,16 @@ def test_keyframe_pack_layout(scene):
     wl, kfs, R, t = scene
     kf = scsurf.keyframe_pack(_dev_kf(kfs[0]))
     rec = kf.packed.cpu().numpy()
-    np.testing.assert_array_equal(rec[..., 0].view(np.float32), kfs[0]["depth"])
-    np.testing.assert_array_equal(rec[..., 1].view(np.float32), kfs[0]["weight"])
+    q = (np.rint(kfs[0]["weight"] * np.float32(1024)) / np.float32(1024)).astype(np.float32)
+    np.testing.assert_array_equal(rec[..., 1].view(np.float32), q)
+    np.testing.assert_array_equal(rec[..., 0].view(np.float32), np.where(q > 0, kfs[0]["depth"], -np.inf))
     np.testing.assert_array_equal(rec[..., 2].view(np.uint32), kfs[0]["color"].view(np.uint32)[..., 0])
     assert not rec[..., 3].any()
     with pytest.raises(ValueError):
         scsurf.keyframe_pack(_dev_kf(as_f32_color(kfs[0]), f32=True))
 
 
-@pytest.mark.parametrize("sched", [(8, 4, 4), (8, 2, 8, 1), (8, 2, 8, 3), (4, 2, 8)])
+@pytest.mark.parametrize("sched", [(8, 4, 4), (8, 2, 8, 1), (8, 2, 8, 3), (8, 2, 8, 4), (8, 4, 4, 4), (4, 2, 8)])
 def test_packed_keyframes_give_identical_bits(scene, sched):
     """Gathering from the interleaved keyframe copy changes no bit, in the
     batched and the plain path."""
@@ -154,7 +156,8 @@ def test_packed_keyframes_give_identical_bits(scene, sched):
 
 def test_schedule_validation(scene):
     vol = scsurf.Volume(S, MU, 1 << 10, 1 << 8, color_mode=scsurf.COLOR_F32)
-    for bad in [(3, 4, 4), (8, 4, 0), (8, 4, 33), (4, 2, 8, 1), (8, 3, 4, 1), (8, 4, 4, 1), (8, 4, 4, 4)]:
+    for bad in [(3, 4, 4), (8, 4, 0), (8, 4, 33), (4, 2, 8, 1), (8, 3, 4, 1), (8, 4, 4, 1), (8, 4, 4, 4), (8, 2, 4, 5),
+                (4, 2, 8, 4)]:
         with pytest.raises(scsurf.ScError):
             vol.set_schedule(*bad)
     vol.set_schedule(8, 2, 4, 1)
