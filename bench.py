@@ -671,6 +671,8 @@ def main():
         log(f"online loop (corridor, {online_res['frames']} frames): {online_res['frames_per_s']} frames/s, "
             f"{online_res['reintegrated_keyframes']} keyframe re-integrations incl. a final pass of "
             f"{online_res['final_pass_keyframes']}")
+        online_res["streaming"] = online_stage(torch, scsurf, synth, stream_radius=3.0, pool_frac=0.25)
+        log(f"online loop with streaming (pool of a quarter of the field, 3 m sphere): {online_res['streaming']}")
 
     adj_ms = None
     if not args.no_adjoint:

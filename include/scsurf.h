@@ -329,6 +329,45 @@ sc_status sc_batch_timing_read(sc_volume* vol, float* ms, int32_t* n);
  * Synchronises `stream`. */
 sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats);
 
+/* ---- memory-capped streaming (Sec. 3 "SDF volume", Sec. 4.3) ------------ */
+
+/* Streaming mode: the device pool (max_blocks) holds the blocks near the
+ * camera, the others live in a host store.  With enable != 0 every
+ * tsdf_integrate, tsdf_deintegrate, reintegrate_batch and reintegrate_plain
+ * first streams in, from the host store, exactly those of its candidate
+ * blocks the store holds (one synchronisation per operation or batch chunk),
+ * so every operation sees every block it may touch and the field equals,
+ * bit for bit, the one a resident volume would hold.  A stream-in that does
+ * not fit the pool sets the sticky SC_EPOOLFULL.  Disabling fails
+ * (SC_EINVAL) while the host store holds blocks.  hash_alloc,
+ * sc_volume_import and tsdf_integrate_backward return SC_EINVAL while it
+ * does; export, mesh and stats see the device blocks only.  The host store
+ * is emptied by sc_volume_reset and freed with the volume. */
+sc_status sc_stream_enable(sc_volume* vol, int32_t enable);
+
+/* Streams out (to the host store) every device block whose centre
+ * s (8 b + 3.5) lies farther than `radius` metres from center (host
+ * double[3], world frame) and compacts the pool; the streaming sphere of
+ * Sec. 3 around the camera position.  Synchronises `stream`.  SC_EINVAL
+ * outside streaming mode or for a negative radius. */
+sc_status sc_stream_out(sc_volume* vol, const double* center, double radius, void* stream);
+
+/* Streams every host-held block back in (SC_EPOOLFULL, sticky, if they do
+ * not fit).  Synchronises `stream`. */
+sc_status sc_stream_in_all(sc_volume* vol, void* stream);
+
+/* The blocks the host store holds, in sc_volume_export's layout but into
+ * HOST buffers (any may be NULL): block_xyz int32 n x 3, D and W float
+ * n x 512, C uint32 n x 512 (RGBA8) or float n x 3 x 512 (FP32 colour); at
+ * most cap blocks are written, *n_out receives their number.  With
+ * sc_volume_export it gives the whole field of a streamed volume. */
+sc_status sc_stream_export(sc_volume* vol, int32_t* block_xyz, float* D, float* W, void* C, int64_t cap,
+                           int64_t* n_out);
+
+/* Host int64[6]: device blocks, host blocks, blocks streamed out and in so
+ * far, and the same in bytes.  Synchronises `stream`. */
+sc_status sc_stream_stats(sc_volume* vol, void* stream, int64_t* stats);
+
 /* ---- adjoint of integration --------------------------------------------- */
 
 /* Backward of integrating n_kf keyframes at poses T_k Exp(xi_k) (xi at 0)

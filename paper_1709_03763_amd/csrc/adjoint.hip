@@ -179,6 +179,7 @@ sc_status tsdf_integrate_backward(sc_volume* vol, const sc_keyframe* kfs, int32_
     if ((grad_C != nullptr) != (grad_color != nullptr)) return SC_EINVAL;
     if (grad_C0 && (!grad_D0 || !grad_C)) return SC_EINVAL;
     if (grad_color && vol->p.color_mode != SC_COLOR_F32) return SC_EINVAL;
+    if (stream_host_blocks(vol) > 0) return SC_EINVAL;  // the forward's blocks must all be on the device
     for (int i = 0; i < n_kf; ++i)
         if (!keyframe_ok(&kfs[i])) return SC_EINVAL;
     hipStream_t s = (hipStream_t)stream;

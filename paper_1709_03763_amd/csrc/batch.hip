@@ -15,6 +15,7 @@
 //      (the touched test decides per voxel), allocates the block if a
 //      re-integration touched it, writes it back once, and clears its
 //      candidate entry.
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -28,12 +29,62 @@
 
 namespace sc {
 
-__global__ void batch_init_kernel(CandDev cd, int n_bins)
+__global__ void batch_init_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr, CandDev cd, int n_bins)
 {
     for (int i = threadIdx.x; i < 8; i += blockDim.x) cd.counters[4 + i] = 0u;
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) cd.bins[i] = 0u;
+    // integrations that record their touched blocks start an empty record
+    for (int o = threadIdx.x; o < hdr->n_ops; o += blockDim.x)
+        if (ops[o].rec_mode == 1) *ops[o].rec_count = 0u;
 }
 
+// A de-integration whose touched-block record is complete takes its
+// candidates from the record instead of from frustum cells.
+__device__ inline bool uses_record(const OpDesc& op)
+{
+    return op.rec_mode == 2 && *op.rec_count <= (uint32_t)op.rec_cap;
+}
+
+// Candidate blocks of de-integrations from their records: every recorded
+// block is claimed in the candidate table and marked with the operation's
+// bit.  Workgroup (x, y) takes operations y, y + gridDim.y, ... and, of each,
+// the keys x * 256 + threadIdx.x + k * gridDim.x * 256.  A record that
+// overflowed its capacity is not used: the operation's frustum-cell tiles
+// are generated here instead, tile x, x + gridDim.x, ...
+__global__ __launch_bounds__(256) void cand_record_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr,
+                                                          VolDev v, CandDev cd)
+{
+    __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    const int n_ops = hdr->n_ops;
+    const int tiles = hdr->tiles_x * hdr->tiles_y;
+    for (int o = blockIdx.y; o < n_ops; o += gridDim.y) {
+        const OpDesc& op = ops[o];
+        if (op.rec_mode != 2) continue;
+        if (!uses_record(op)) {
+            for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+                const int ty = tile / hdr->tiles_x;
+                const int tx = tile - ty * hdr->tiles_x;
+                cand_tile<kTileBatch, kCellBatch>(op, v, cd, nullptr, tx, ty, o, lds, idx);
+                __syncthreads();
+            }
+            continue;
+        }
+        const uint32_t n = *op.rec_count;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const uint64_t key = op.rec_keys[i];
+            int bx, by, bz;
+            unpack_key(key, bx, by, bz);
+            bool fresh;
+            const int gb = cand_claim(cd, v, key, bx, by, bz, fresh);
+            if (gb >= 0) cand_mark(cd, gb, o);
+        }
+    }
+}
+
+// Frustum-cell candidates of the operations without a record, one (operation,
+// 64 x 64 tile) item at a time.
+constexpr int kCandPop = 2;
 __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr,
                                                          VolDev v, CandDev cd)
 {
@@ -41,21 +92,29 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
     __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
     __shared__ int next;
     const int tiles = hdr->tiles_x * hdr->tiles_y;
-    const int items = hdr->n_ops * tiles;
-    // first item static, then one pop per item from the batch's tile cursor:
-    // tiles differ widely in cost (grazing surfaces give large cell boxes),
-    // so a static stride leaves a tail of workgroups with heavy tiles
-    int it = blockIdx.x;
-    while (it < items) {
-        const int o = it / tiles;
-        const int tile = it - o * tiles;
+    const int items = hdr->n_tile_ops * tiles;
+    // first item static, then kCandPop items per pop from the batch's tile
+    // cursor: tiles differ widely in cost (grazing surfaces give large cell
+    // boxes), so a static stride leaves a tail of workgroups with heavy
+    // tiles, while the cursor's atomics are serviced one at a time
+    int it = blockIdx.x, end = it + 1;
+    for (;;) {
+        if (it >= end) {
+            __syncthreads();
+            if (threadIdx.x == 0) next = (int)gridDim.x + kCandPop * (int)atomicAdd(cd.counters + 6, 1u);
+            __syncthreads();
+            it = next;
+            end = it + kCandPop;
+        }
+        if (it >= items) break;
+        const int k = it / tiles;
+        const int o = hdr->tile_ops[k];
+        const int tile = it - k * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
         cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
         __syncthreads();
-        if (threadIdx.x == 0) next = (int)gridDim.x + (int)atomicAdd(cd.counters + 6, 1u);
-        __syncthreads();
-        it = next;
+        ++it;
     }
 }
 
@@ -582,7 +641,22 @@ struct PipeBlock {
     int bx, by, bz, slot;
     uint32_t touched, n_upd, pairs;
     bool re_touch, e_na, e_w;
+    bool pair_any;   // the current operation touched a voxel of the block (ring pass)
+    uint32_t n_rec;  // recording integrations that touched the block, not yet appended
+    int rec_op;      // lane i < n_rec: the i-th of them
 };
+
+// Appends the block to the records of the integrations listed in lanes
+// 0 .. n_rec - 1, one atomic per lane on that operation's counter.
+__device__ inline void record_flush(const OpDesc* __restrict__ ops, PipeBlock& pb, int lane)
+{
+    if ((uint32_t)lane < pb.n_rec) {
+        const OpDesc& o = ops[pb.rec_op];
+        const uint32_t pos = atomicAdd(o.rec_count, 1u);
+        if (pos < (uint32_t)o.rec_cap) o.rec_keys[pos] = pack_key(pb.bx, pb.by, pb.bz);
+    }
+    pb.n_rec = 0u;
+}
 
 // Issues the keyframe gathers of (operation `o`, part `part`: z-slices
 // 4 part .. 4 part + 3) into `f` and returns the camera z of the block origin
@@ -988,6 +1062,7 @@ __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v
     float w[4];
     const uint32_t hit = ring_decide<CM, kPacked>(cur, v.mu, w);
     const bool any = __ballot(hit != 0u) != 0ull;
+    pb.pair_any = (part_c == 0) ? any : (pb.pair_any || any);
     if (any && op.sign < 0 && pb.slot < 0) {
         pb.e_na = true;
     } else if (any) {
@@ -1010,6 +1085,17 @@ __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v
         }
     }
     if (part_c == 1 && ring.tail != ring.head) ring_flush<CM>(op, gc.qz, ring, ring.tail - ring.head, pb, lane, L);
+    if (part_c == 1 && op.rec_mode == 1 && pb.pair_any) {
+        // the integration touched the block: lane n_rec remembers the
+        // operation, and the block's record appends are issued together
+        // when the block is done (no atomic waits while gathers are in
+        // flight); a 65th operation flushes the list first
+        if (pb.n_rec == 64u) {
+            record_flush(ops, pb, lane);
+        }
+        pb.rec_op = (lane == (int)pb.n_rec) ? op_c : pb.rec_op;
+        pb.n_rec += 1u;
+    }
     if (op_n < 0) return false;
     op_c = op_n;
     part_c = part_n;
@@ -1043,6 +1129,8 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
         unpack_key(key, pb.bx, pb.by, pb.bz);
         pb.touched = pb.n_upd = pb.pairs = 0u;
         pb.re_touch = pb.e_na = pb.e_w = false;
+        pb.n_rec = 0u;
+        pb.rec_op = 0;
         {
             const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
             const bool have = pb.slot >= 0;
@@ -1078,6 +1166,7 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
                 if (!ring_step<CM, kPacked>(ops, v, walk, pb, f1, f0, gc, op_c, part_c, lane, L, ring)) break;
             }
         }
+        if (pb.n_rec) record_flush(ops, pb, lane);
         n_pairs += pb.pairs;
         n_upd += pb.n_upd;
         const int all = (__ballot(pb.re_touch) ? 1 : 0) | (__ballot(pb.e_na) ? 2 : 0) | (__ballot(pb.e_w) ? 4 : 0);
@@ -1203,9 +1292,11 @@ static bool schedule_ok(const sc_schedule& s)
 static void launch_candidates(sc_volume* vol, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
-    batch_init_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
+    batch_init_kernel<<<1, 1024, 0, s>>>(vol->d_ops, vol->d_hdr, vol->cand, n_bins);
     cand_batch_kernel<<<vol->n_cu * vol->cand_wgs, CandCfg<kTileBatch, kCellBatch>::threads, 0, s>>>(
         vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
+    cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(vol->d_ops, vol->d_hdr,
+                                                                                           vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, vol->dev, n_bins);
@@ -1346,8 +1437,12 @@ sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_
     hdr->n_ops = n_ops;
     hdr->tiles_x = (in->width + kTileBatch - 1) / kTileBatch;
     hdr->tiles_y = (in->height + kTileBatch - 1) / kTileBatch;
+    hdr->n_tile_ops = 0;
+    for (int o = 0; o < n_ops; ++o)
+        if (ops[o].rec_mode != 2) hdr->tile_ops[hdr->n_tile_ops++] = (int16_t)o;
+    const size_t hdr_bytes = offsetof(BatchHdr, tile_ops) + sizeof(int16_t) * (size_t)std::max(hdr->n_tile_ops, 1);
     if (hipMemcpyAsync(vol->d_ops, ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(vol->d_hdr, hdr, sizeof(BatchHdr), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(vol->d_hdr, hdr, hdr_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         return SC_EDEVICE;
     // the staging buffer may be refilled once these copies have run
     const sc_status st = stage_end(vol, s);
@@ -1362,7 +1457,9 @@ sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_
 // stream.
 static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s)
 {
-    const sc_status st = run_candidates(vol, ops, n_ops, in, s);
+    sc_status st = run_candidates(vol, ops, n_ops, in, s);
+    if (st != SC_OK) return st;
+    st = stream_in_batch(vol, s);
     if (st != SC_OK) return st;
     bool packed = vol->p.color_mode == SC_COLOR_RGBA8;
     for (int i = 0; i < n_ops && packed; ++i) packed = ops[i].packed != nullptr;
@@ -1397,15 +1494,22 @@ sc_status batch_update(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, con
         for (int j = 0; j < cnt; ++j) {
             const int g = done + j;
             const int k = order[g < ns ? g : g - ns];
-            if (g < ns)
+            if (g < ns) {
                 make_op(vol, &kfs[k], in, &T_int[k], -1, k, &ops[j]);
-            else
+                rec_for_deintegration(vol, &kfs[k], in, &T_int[k], &ops[j]);
+            } else {
                 make_op(vol, &kfs[k], in, &T_new[k], +1, k, &ops[j]);
+                rec_for_integration(vol, &kfs[k], in, &T_new[k], vol->sched.compact == 4, &ops[j]);
+            }
         }
         const sc_status st = run_chunk(vol, ops, cnt, in, s);
-        if (st != SC_OK) return st;
+        if (st != SC_OK) {
+            rec_commit(vol);
+            return st;
+        }
         done += cnt;
     }
+    rec_commit(vol);
     return SC_OK;
 }
 

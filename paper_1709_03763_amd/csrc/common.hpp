@@ -64,6 +64,15 @@ struct OpDesc {
     double az[3];         // s * R[axis][2] in FP64: camera-z step per voxel for the continuous distance
     int32_t sign;         // +1 integrate, -1 de-integrate
     int32_t kf;           // keyframe index within the call (for gradients)
+    // Touched-block record of this (keyframe, pose): an integration with
+    // rec_mode 1 appends every block it touches; a de-integration with
+    // rec_mode 2 takes those blocks as its candidates (the same keyframe at
+    // the same pose touches the same blocks) when the record did not
+    // overflow; rec_mode 0: no record.
+    uint64_t* rec_keys;   // rec_cap keys
+    uint32_t* rec_count;  // appended so far (may exceed rec_cap: overflowed)
+    int32_t rec_mode;
+    int32_t rec_cap;
 };
 
 // Device view of a volume.
@@ -105,7 +114,8 @@ struct CandDev {
 struct BatchHdr {
     int32_t n_ops;
     int32_t tiles_x, tiles_y;
-    int32_t pad;
+    int32_t n_tile_ops;              // operations whose candidates come from frustum cells
+    int16_t tile_ops[kMaxBatchOps];  // their indices (the others take a touched-block record)
 };
 
 inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -137,4 +147,6 @@ struct sc_volume {
     int cand_wgs;            // resident workgroups per CU of the batched candidate kernel
     int plain_wgs;           // resident workgroups per CU of the plain update kernel
     double* adj_acc;         // device, 3 x kAdjChunk: pose terms of one backward chunk (zero between calls)
+    struct RecordRegistry* rec;  // touched-block records of integrations (host index, device lists)
+    struct StreamStore* stream;  // host store of streamed-out blocks (streaming mode)
 };

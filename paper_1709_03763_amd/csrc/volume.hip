@@ -5,6 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -147,6 +150,11 @@ __device__ void block_one_op(const OpDesc& op, const VolDev& v, uint64_t key, in
     test_voxels<CM, 8>(op, v.mu, base, 0, hv);
     const uint32_t tmask = hv.hit;
     if (__ballot(tmask != 0) == 0) return;
+    if (op.rec_mode == 1 && lane == 0) {
+        // the integration's touched-block record: one append by one lane
+        const uint32_t pos = atomicAdd(op.rec_count, 1u);
+        if (pos < (uint32_t)op.rec_cap) op.rec_keys[pos] = key;
+    }
     const int slot = (op.sign > 0) ? vol_insert_wave(v, key, bx, by, bz, lane) : (int)bcast((uint32_t)vol_find(v, key, bx, by, bz));
     if (slot < 0) {
         if (op.sign < 0) set_error(v.err, SC_ENOTALLOC);
@@ -328,21 +336,188 @@ bool keyframe_ok(const sc_keyframe* kf)
     return kf && kf->depth && kf->weight && kf->color && ((uintptr_t)kf->packed & 15u) == 0u;
 }
 
+// ---------------------------------------------------------------------------
+// touched-block records
+//
+// A keyframe integrated at a pose touches a set of blocks that depends only
+// on the keyframe and the pose; de-integrating it at that pose (Eq. 2)
+// touches exactly the same set.  Integrations therefore append the blocks
+// they touch to a record keyed by (keyframe buffers, intrinsics, pose), and
+// a later de-integration of the same key takes the record as its candidate
+// blocks instead of generating frustum candidates.  A record is dropped when
+// as many de-integrations as integrations of its key have been applied, on
+// reset and on import; a record that overflowed its capacity is ignored on
+// the device (frustum candidates are generated instead).
+// ---------------------------------------------------------------------------
+
+}  // namespace sc
+
+struct RecordRegistry {
+    struct Entry {
+        int slot;
+        int refs;
+    };
+    std::unordered_map<std::string, Entry> map;
+    std::vector<int> free_slots;
+    std::vector<int> pending;  // slots released by de-integrations of the call in flight
+    uint64_t* d_keys = nullptr;
+    uint32_t* d_count = nullptr;
+    int slots = 0, cap = 0;
+    bool failed = false;
+};
+
+namespace sc {
+
+constexpr int kRecSlots = 1024;   // records held at once
+constexpr int kRecCap = 16384;    // blocks per record
+constexpr int kRecCountStride = 32;  // one record counter per 128 bytes, so appends to different records do not meet
+
+static std::string rec_fingerprint(const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T)
+{
+    std::string f;
+    f.reserve(4 * sizeof(void*) + sizeof(sc_intrinsics) + sizeof(sc_pose));
+    const void* ptrs[4] = {kf->depth, kf->weight, kf->color, kf->packed};
+    f.append(reinterpret_cast<const char*>(ptrs), sizeof(ptrs));
+    f.append(reinterpret_cast<const char*>(in), sizeof(*in));
+    f.append(reinterpret_cast<const char*>(T), sizeof(*T));
+    return f;
+}
+
+static bool rec_ready(sc_volume* vol)
+{
+    if (!vol->rec) vol->rec = new (std::nothrow) RecordRegistry();
+    RecordRegistry* r = vol->rec;
+    if (!r || r->failed) return false;
+    if (r->d_keys) return true;
+    const int cap = (int)std::min<int64_t>(kRecCap, vol->p.max_blocks);
+    if (hipMalloc(&r->d_keys, sizeof(uint64_t) * (size_t)kRecSlots * cap) != hipSuccess ||
+        hipMalloc(&r->d_count, kRecCountStride * sizeof(uint32_t) * kRecSlots) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(r->d_keys);
+        r->d_keys = nullptr;
+        r->failed = true;
+        return false;
+    }
+    r->slots = kRecSlots;
+    r->cap = cap;
+    r->free_slots.clear();
+    for (int i = kRecSlots - 1; i >= 0; --i) r->free_slots.push_back(i);
+    return true;
+}
+
+void rec_clear(sc_volume* vol)
+{
+    RecordRegistry* r = vol->rec;
+    if (!r || !r->d_keys) return;
+    r->map.clear();
+    r->pending.clear();
+    r->free_slots.clear();
+    for (int i = r->slots - 1; i >= 0; --i) r->free_slots.push_back(i);
+}
+
+void rec_destroy(sc_volume* vol)
+{
+    RecordRegistry* r = vol->rec;
+    if (!r) return;
+    hipFree(r->d_keys);
+    hipFree(r->d_count);
+    delete r;
+    vol->rec = nullptr;
+}
+
+// An integration of kf at T: with `records` (the kernel that will run
+// appends the touched blocks) the op appends to the key's record (rec_mode
+// 1; its count is cleared on the device before the pass).  Without, an
+// existing record of the key only gains a reference: the same keyframe at
+// the same pose touches the same blocks, so the record still holds them.
+void rec_for_integration(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T,
+                         bool records, OpDesc* op)
+{
+    if (!rec_ready(vol)) return;
+    RecordRegistry* r = vol->rec;
+    const std::string f = rec_fingerprint(kf, in, T);
+    auto it = r->map.find(f);
+    if (!records) {
+        if (it != r->map.end()) it->second.refs += 1;
+        return;
+    }
+    int slot;
+    if (it != r->map.end()) {
+        slot = it->second.slot;
+        it->second.refs += 1;
+    } else {
+        if (r->free_slots.empty()) return;
+        slot = r->free_slots.back();
+        r->free_slots.pop_back();
+        r->map.emplace(f, RecordRegistry::Entry{slot, 1});
+    }
+    op->rec_keys = r->d_keys + (size_t)slot * r->cap;
+    op->rec_count = r->d_count + (size_t)kRecCountStride * slot;
+    op->rec_cap = r->cap;
+    op->rec_mode = 1;
+}
+
+// A de-integration of kf at T: takes the key's record when there is one
+// (rec_mode 2) and releases one reference to it; the slot becomes free once
+// the call's work is enqueued (rec_commit).
+void rec_for_deintegration(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T,
+                           OpDesc* op)
+{
+    RecordRegistry* r = vol->rec;
+    if (!r || !r->d_keys) return;
+    auto it = r->map.find(rec_fingerprint(kf, in, T));
+    if (it == r->map.end()) return;
+    const int slot = it->second.slot;
+    op->rec_keys = r->d_keys + (size_t)slot * r->cap;
+    op->rec_count = r->d_count + (size_t)kRecCountStride * slot;
+    op->rec_cap = r->cap;
+    op->rec_mode = 2;
+    if (--it->second.refs == 0) {
+        r->pending.push_back(slot);
+        r->map.erase(it);
+    }
+}
+
+// Frees the slots released during a call, once all its work is enqueued:
+// later work on the stream runs after it.
+void rec_commit(sc_volume* vol)
+{
+    RecordRegistry* r = vol->rec;
+    if (!r) return;
+    for (int slot : r->pending) r->free_slots.push_back(slot);
+    r->pending.clear();
+}
+
 sc_status plain_op(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T, int sign,
                    hipStream_t s)
 {
     if (!vol || !keyframe_ok(kf) || !intr_ok(in) || !T) return SC_EINVAL;
     OpDesc op;
     make_op(vol, kf, in, T, sign, 0, &op);
+    if (sign > 0) {
+        rec_for_integration(vol, kf, in, T, true, &op);
+        if (op.rec_mode == 1) fill_u32(op.rec_count, 0u, 1, s);
+    } else {
+        // the plain de-integration generates its own candidates: only the
+        // reference is released
+        OpDesc tmp = op;
+        rec_for_deintegration(vol, kf, in, T, &tmp);
+    }
     const int p = vol->parity;
     vol->parity ^= 1;
     dim3 tiles((in->width + kTilePlain - 1) / kTilePlain, (in->height + kTilePlain - 1) / kTilePlain);
     cand_plain_kernel<<<tiles, CandCfg<kTilePlain, kCellPlain>::threads, 0, s>>>(op, vol->dev, vol->cand, p);
+    const sc_status sst = stream_in_plain(vol, p, s);
+    if (sst != SC_OK) {
+        rec_commit(vol);
+        return sst;
+    }
     const int grid = vol->n_cu * vol->plain_wgs;  // resident at once: the first items are assigned statically
     if (vol->p.color_mode == SC_COLOR_RGBA8)
         update_plain_kernel<SC_COLOR_RGBA8><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
     else
         update_plain_kernel<SC_COLOR_F32><<<grid, 256, 0, s>>>(op, vol->dev, vol->cand, p);
+    rec_commit(vol);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
@@ -479,6 +654,8 @@ void sc_volume_destroy(sc_volume* vol)
     if (vol->cap_stream) hipStreamDestroy(vol->cap_stream);
     for (hipEvent_t e : vol->staged)
         if (e) hipEventDestroy(e);
+    rec_destroy(vol);
+    stream_destroy(vol);
     delete vol;
 }
 
@@ -499,6 +676,8 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
     fill_u64(reinterpret_cast<uint64_t*>(vol->adj_acc), 0ull, 3 * kAdjChunk, s);
     vol->parity = 0;
+    rec_clear(vol);
+    stream_clear(vol);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
@@ -535,7 +714,8 @@ sc_status sc_volume_export(sc_volume* vol, void* stream, int32_t* block_xyz, flo
 sc_status sc_volume_import(sc_volume* vol, void* stream, const int32_t* block_xyz, const float* D, const float* W,
                            const void* C, int64_t n)
 {
-    if (!vol || n < 0 || (n > 0 && !block_xyz) || n > vol->p.max_blocks) return SC_EINVAL;
+    if (!vol || n < 0 || (n > 0 && !block_xyz) || n > vol->p.max_blocks || stream_host_blocks(vol) > 0)
+        return SC_EINVAL;
     if (n == 0) return SC_OK;
     hipStream_t s = (hipStream_t)stream;
     int32_t* slots = nullptr;
@@ -568,7 +748,7 @@ sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height,
 
 sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_t* slots_out, void* stream)
 {
-    if (!vol || n < 0 || (n > 0 && !block_xyz)) return SC_EINVAL;
+    if (!vol || n < 0 || (n > 0 && !block_xyz) || stream_host_blocks(vol) > 0) return SC_EINVAL;
     if (n == 0) return SC_OK;
     hipStream_t s = (hipStream_t)stream;
     const unsigned grid = (unsigned)((n + 255) / 256);

@@ -32,7 +32,8 @@ MAX_FRAMES = 64  # frames one keyframe may fuse
 class OnlineSession:
     def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None,
                  strategy: str = "const", max_trans: float = 0.1, max_rot: float = 0.0873,
-                 min_overlap: float = 0.8, z_min: float = 0.3, z_max: float = 4.0):
+                 min_overlap: float = 0.8, z_min: float = 0.3, z_max: float = 4.0,
+                 stream_radius: float | None = None):
         if kappa < 1 or m < 1:
             raise ValueError("kappa and m must be positive")
         if strategy not in ("const", "dist", "overlap"):
@@ -40,6 +41,11 @@ class OnlineSession:
         self.vol, self.intr, self.kappa, self.m, self.mode, self.stream = vol, intr, kappa, m, mode, stream
         self.strategy, self.max_trans, self.max_rot, self.min_overlap = strategy, max_trans, max_rot, min_overlap
         self.z_min, self.z_max = z_min, z_max
+        # streaming sphere (Sec. 3): blocks farther than this from the camera
+        # are kept on the host; every operation streams in what it needs
+        self.stream_radius = stream_radius
+        if stream_radius is not None:
+            vol.stream_enable(True)
         self.keyframe_sizes: list[int] = []
         self._depth, self._rgb, self._R, self._t = [], [], [], []
         self.keyframes: list[scsurf.Keyframe] = []
@@ -100,6 +106,8 @@ class OnlineSession:
         kf = scsurf.keyframe_pack(kf, stream=self.stream)
         self.keyframe_sizes.append(len(R))
         self._depth, self._rgb, self._R, self._t = [], [], [], []
+        if self.stream_radius is not None:
+            self.vol.stream_out(t[0], self.stream_radius, stream=self.stream)
         self.vol.integrate(kf, self.intr, R[0], t[0], stream=self.stream)
         self.keyframes.append(kf)
         self._kset = None
@@ -125,6 +133,12 @@ class OnlineSession:
         self.R_new, self.t_new = R.copy(), t.copy()
         if self.n_keyframes == 0:
             return []
+        if self.stream_radius is not None:
+            # Sec. 4.3: the sphere around the first selected keyframe's
+            # integration pose; what the update needs beyond it streams in
+            sel, _ = scsurf.select((self.R_int, self.t_int), (self.R_new, self.t_new), self.m, self.mode)
+            if sel:
+                self.vol.stream_out(self.t_int[sel[0]], self.stream_radius, stream=self.stream)
         order, (Ri, ti) = self.vol.reintegrate_batch(self._keyframe_set(), self.intr, (self.R_int, self.t_int),
                                                       (self.R_new, self.t_new), self.m, self.mode, self.stream)
         self.R_int, self.t_int = Ri, ti

@@ -70,7 +70,8 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
            "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table",
-           "sc_volume_import"]
+           "sc_volume_import", "sc_stream_enable", "sc_stream_out", "sc_stream_in_all", "sc_stream_stats",
+           "sc_stream_export"]
 
 _lib = None
 
@@ -101,6 +102,11 @@ def lib():
         f.argtypes = [P, ctypes.POINTER(sc_keyframe), ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), P]
     L.sc_select.argtypes = [ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, i32, P, P]
     L.sc_select_dist.argtypes = [P, i32, i32, i32, P]
+    L.sc_stream_enable.argtypes = [P, i32]
+    L.sc_stream_out.argtypes = [P, P, ctypes.c_double, P]
+    L.sc_stream_in_all.argtypes = [P, P]
+    L.sc_stream_stats.argtypes = [P, P, P]
+    L.sc_stream_export.argtypes = [P, P, P, P, P, i64, ctypes.POINTER(i64)]
     L.sc_relative_motion.argtypes = [ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     for f in (L.reintegrate_batch, L.reintegrate_plain):
@@ -358,10 +364,28 @@ class Volume:
             raise ScError(SC_EDEVICE, "sc_volume_mesh: triangle count changed between calls")
         return xyz[:T], keys[:T]
 
-    def export_sorted(self, stream=None):
+    def stream_export(self):
+        """Blocks held by the host store (streaming mode): dict of NumPy
+        arrays in export's layout."""
+        n = ctypes.c_int64()
+        check(lib().sc_stream_export(self._h, None, None, None, None, 0, ctypes.byref(n)), "sc_stream_export")
+        m = int(n.value)
+        xyz = np.zeros((m, 3), np.int32)
+        D = np.zeros((m, 512), np.float32)
+        W = np.zeros((m, 512), np.float32)
+        C = np.zeros((m, 512, 4), np.uint8) if self.color_mode == COLOR_RGBA8 else np.zeros((m, 3, 512), np.float32)
+        check(lib().sc_stream_export(self._h, xyz.ctypes.data, D.ctypes.data, W.ctypes.data, C.ctypes.data, m,
+                                     ctypes.byref(n)), "sc_stream_export")
+        return {"blocks": xyz, "D": D, "W": W, "C": C}
+
+    def export_sorted(self, stream=None, with_host=False):
         """Allocated blocks sorted by (x, y, z) as NumPy arrays; colour as
-        (n, 512, 3) in RGB order."""
+        (n, 512, 3) in RGB order.  with_host: also the blocks the host store
+        holds (streaming mode), i.e. the whole field."""
         f = {k: v.cpu().numpy() for k, v in self.export(stream).items()}
+        if with_host:
+            h = self.stream_export()
+            f = {k: np.concatenate([f[k], h[k]]) for k in f}
         b = f["blocks"].astype(np.int64)
         order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
         C = f["C"][order]
@@ -457,6 +481,26 @@ class Volume:
         n = ctypes.c_int32()
         check(lib().sc_batch_timing_read(self._h, ms, ctypes.byref(n)), "sc_batch_timing_read")
         return list(ms[:n.value])
+
+    def stream_enable(self, enable=True):
+        """Streaming mode (Sec. 3): operations stream in the host-held blocks
+        among their candidates before running."""
+        check(lib().sc_stream_enable(self._h, int(bool(enable))), "sc_stream_enable")
+
+    def stream_out(self, center, radius: float, stream=None):
+        """Moves the device blocks outside the sphere (center, radius) to the
+        host store."""
+        c = (ctypes.c_double * 3)(*[float(x) for x in np.asarray(center, np.float64).reshape(3)])
+        check(lib().sc_stream_out(self._h, c, float(radius), stream_handle(stream)), "sc_stream_out")
+
+    def stream_in_all(self, stream=None):
+        check(lib().sc_stream_in_all(self._h, stream_handle(stream)), "sc_stream_in_all")
+
+    def stream_stats(self, stream=None):
+        """(device blocks, host blocks, blocks out, blocks in, bytes out, bytes in)."""
+        out = (ctypes.c_int64 * 6)()
+        check(lib().sc_stream_stats(self._h, stream_handle(stream), out), "sc_stream_stats")
+        return tuple(int(x) for x in out)
 
     def stats(self, stream=None):
         """(candidate blocks, block-operation pairs, voxel updates, blocks written), cumulative."""

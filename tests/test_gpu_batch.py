@@ -304,3 +304,55 @@ def test_pass_counters_and_timing(scene):
     assert pairs >= n_pairs and cand >= written and written <= n_blocks
     assert len(ms) == 1 and ms[0] > 0
     vol.close()
+
+
+@pytest.mark.parametrize("sched", [(8, 2, 8, 4), (8, 2, 8, 3)])
+def test_recorded_deintegration_candidates(scene, sched):
+    """A de-integration of a keyframe at the pose it was integrated at takes
+    the blocks that integration recorded as its candidates: exactly the
+    touched blocks, so fewer (block, operation) pairs, and the same bits as
+    the frustum candidates.  The keyframes are integrated unpacked in one
+    volume (records keyed by those buffers) and packed in the other, whose
+    update then finds no record (different buffers) and generates frustum
+    candidates; a second update (B -> A) then uses, in both volumes, the
+    records the first update's re-integrations wrote (ring pass) or finds
+    none (other passes)."""
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 9)
+    _say(f"recorded de-integration candidates, schedule {sched}")
+    dks = [_dev_kf(k) for k in kfs]
+    pks = [scsurf.keyframe_pack(k) for k in dks]
+    vols, pairs = [], []
+    for integ, upd in ((pks, pks), (dks, pks)):
+        vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+        vol.set_schedule(*sched)
+        for k in range(len(kfs)):
+            vol.integrate(integ[k], wl.intr, R[k], t[k])
+        vol.check_error()
+        before = vol.stats()
+        vol.reintegrate_batch(upd, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+        mid = vol.stats()
+        vol.reintegrate_batch(upd, wl.intr, (Rn, tn), (R, t), 8, scsurf.SEL_ALL_ORDERED)
+        vol.check_error()
+        after = vol.stats()
+        pairs.append((mid[1] - before[1], after[1] - mid[1]))
+        vols.append(vol)
+    a, b = vols[0].export_sorted(), vols[1].export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(a[key], b[key])
+    _say(f"(block, op) pairs with records {pairs[0]}, without {pairs[1]}")
+    assert pairs[0][0] < pairs[1][0]
+    # second update: both volumes hold the same records (those of the first
+    # update's re-integrations with the ring pass, none otherwise)
+    assert pairs[0][1] == pairs[1][1]
+    # the oracle agrees
+    ref = oracle.Volume(S, MU)
+    for k in range(len(kfs)):
+        assert ref.integrate(kfs[k], wl.intr, R[k], t[k]) == oracle.OK
+    order = osel.select(osel.distances(R, t, Rn, tn), 8, osel.ALL_ORDERED)
+    _oracle_update(ref, kfs, wl, R, t, Rn, tn, order)
+    order = osel.select(osel.distances(Rn, tn, R, t), 8, osel.ALL_ORDERED)
+    _oracle_update(ref, kfs, wl, Rn, tn, R, t, order)
+    compare_fields(a, ref.export())
+    for v in vols:
+        v.close()

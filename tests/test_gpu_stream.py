@@ -1,0 +1,191 @@
+"""Memory-capped streaming (Sec. 3, "SDF volume": only the blocks near the
+camera stay in GPU memory, the rest are streamed to the host; Sec. 4.3: the
+blocks around the poses a re-integration works at are streamed in first).
+A streamed volume whose pool holds a fraction of the field must end with
+the field of a resident volume, bit for bit, over plain and batched
+updates; the host store and the device pool together hold it."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import selection as osel
+from paper_1709_03763_amd import online, scsurf, synth
+from tests.helpers import compare_fields, oracle_keyframes
+
+pytestmark = pytest.mark.gpu
+
+S, MU = 0.01, 0.04
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _dev_kf(kf):
+    return scsurf.Keyframe(torch.from_numpy(np.ascontiguousarray(kf["depth"])).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(kf["weight"])).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(kf["color"])).cuda())
+
+
+def _equal(a, b):
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+
+
+@pytest.fixture(scope="module")
+def room():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(3)
+    groups = [np.arange(5) + 5 * k for k in range(16)]
+    kfs = oracle_keyframes(wl, groups)
+    R = np.array([wl.R[g[0]] for g in groups])
+    t = np.array([wl.t[g[0]] for g in groups])
+    Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 21)
+    return wl, kfs, R, t, Rn, tn
+
+
+def _session(vol, wl, dks, R, t, Rn, tn, radius=None):
+    """Integrations, a batched update (A -> B) and a plain update (B -> A),
+    streaming the sphere around each camera first when a radius is given."""
+    for k in range(len(dks)):
+        if radius is not None:
+            vol.stream_out(t[k], radius)
+        vol.integrate(dks[k], wl.intr, R[k], t[k])
+    vol.check_error()
+    if radius is not None:
+        sel, _ = scsurf.select((R, t), (Rn, tn), len(dks), scsurf.SEL_ALL_ORDERED)
+        vol.stream_out(t[sel[0]], radius)
+    vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), len(dks), scsurf.SEL_ALL_ORDERED)
+    vol.check_error()
+    if radius is not None:
+        vol.stream_out(tn[0], radius)
+    vol.reintegrate_plain(dks, wl.intr, (Rn, tn), (R, t), len(dks), scsurf.SEL_ALL_ORDERED)
+    vol.check_error()
+
+
+@pytest.mark.parametrize("sched", [(8, 2, 8, 4), (8, 2, 8, 3)])
+def test_streamed_room_equals_resident(room, sched):
+    wl, kfs, R, t, Rn, tn = room
+    dks = [scsurf.keyframe_pack(_dev_kf(k)) for k in kfs]
+    res = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+    res.set_schedule(*sched)
+    _session(res, wl, dks, R, t, Rn, tn)
+    ref = res.export_sorted()
+    total = len(ref["blocks"])
+    res.close()
+    # the pool holds 70 % of the field: enough for the candidate blocks of
+    # two operations, the batch chunk used here
+    cap = int(total * 0.7)
+    _say(f"{total} blocks; streamed volume with a pool of {cap}, schedule {sched}")
+    vol = scsurf.Volume(S, MU, 1 << 17, cap, max_batch_ops=2)
+    vol.set_schedule(*sched)
+    vol.stream_enable(True)
+    _session(vol, wl, dks, R, t, Rn, tn, radius=1.0)
+    st = vol.stream_stats()
+    _say(f"device {st[0]}, host {st[1]}, out {st[2]} blocks ({st[4] / 1e6:.1f} MB), in {st[3]} ({st[5] / 1e6:.1f} MB)")
+    assert st[0] <= cap and st[1] > 0 and st[2] > 0 and st[3] > 0
+    assert st[0] + st[1] == total
+    _equal(vol.export_sorted(with_host=True), ref)
+    # the oracle agrees (sequential operations in the same order)
+    o = oracle.Volume(S, MU)
+    for k in range(len(kfs)):
+        assert o.integrate(kfs[k], wl.intr, R[k], t[k]) == oracle.OK
+    for (Ta, Tb) in (((R, t), (Rn, tn)), ((Rn, tn), (R, t))):
+        order = osel.select(osel.distances(Ta[0], Ta[1], Tb[0], Tb[1]), len(kfs), osel.ALL_ORDERED)
+        for k in order:
+            assert o.deintegrate(kfs[k], wl.intr, Ta[0][k], Ta[1][k]) == oracle.OK
+        for k in order:
+            assert o.integrate(kfs[k], wl.intr, Tb[0][k], Tb[1][k]) == oracle.OK
+    compare_fields(vol.export_sorted(with_host=True), o.export())
+    vol.close()
+
+
+def test_stream_errors(room):
+    wl, kfs, R, t, Rn, tn = room
+    dks = [_dev_kf(k) for k in kfs[:2]]
+    vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+    with pytest.raises(scsurf.ScError):
+        vol.stream_out(t[0], 1.0)  # not in streaming mode
+    vol.stream_enable(True)
+    vol.integrate(dks[0], wl.intr, R[0], t[0])
+    n = vol.check_error()
+    vol.stream_out(t[0] + 100.0, 1.0)  # everything to the host
+    assert vol.stream_stats()[:2] == (0, n)
+    with pytest.raises(scsurf.ScError):
+        vol.stream_enable(False)  # blocks still on the host
+    with pytest.raises(scsurf.ScError):
+        vol.hash_alloc(torch.zeros((1, 3), dtype=torch.int32, device="cuda"))
+    vol.stream_in_all()
+    assert vol.stream_stats()[:2] == (n, 0)
+    vol.stream_enable(False)
+    vol.close()
+    # a pool smaller than one keyframe's candidate blocks: sticky SC_EPOOLFULL
+    small = scsurf.Volume(S, MU, 1 << 17, 500)
+    small.stream_enable(True)
+    with pytest.raises(scsurf.ScError):
+        small.integrate(dks[0], wl.intr, R[0], t[0])
+    assert small.query()[1] == scsurf.SC_EPOOLFULL
+    small.reset()
+    assert small.query() == (0, scsurf.SC_OK)
+    small.close()
+
+
+N_FRAMES, EVERY, M = 1000, 20, 20
+
+
+def test_streamed_corridor_session_equals_resident():
+    """The corridor online session (1000 frames fused five per keyframe, an
+    Eq. 3 update of 20 keyframes every 20, the final pass) with a device pool
+    of a quarter of the final field and a 3 m streaming sphere, against the
+    same session fully resident."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    wl = synth.workload(5)
+    groups = synth.keyframe_groups(wl)[: N_FRAMES // wl.kappa]
+    first = np.array([g[0] for g in groups])
+    Rk, tk = wl.R[first], wl.t[first]
+    drift = online.drifting_estimates(Rk, tk, seed=55)
+    Re, te = online.corrected(Rk, tk, drift, 1.0)
+    poses = []
+    for k, g in enumerate(groups):
+        A = Re[k] @ Rk[k].T
+        poses += [(A @ wl.R[f], A @ (wl.t[f] - tk[k]) + te[k]) for f in g]
+    updates = {n: online.corrected(Rk[:n], tk[:n], drift[:n], 0.5 ** (n // EVERY))
+               for n in range(EVERY, len(groups) + 1, EVERY)}
+    idx = np.concatenate(groups)
+    _say(f"rendering {len(idx)} frames at 640x480")
+    z, rgb = synth.frames(wl, idx, device="cuda")
+    Z, C = torch.from_numpy(z).cuda(), torch.from_numpy(rgb).cuda()
+
+    def run(vol, radius):
+        sess = online.OnlineSession(vol, wl.intr, wl.kappa, M, stream_radius=radius)
+        orders, per_update = [], []
+        for f in range(len(idx)):
+            k = sess.add_frame(Z[f], C[f], *poses[f])
+            if k is not None and (k + 1) in updates:
+                before = vol.stream_stats() if radius else None
+                orders.append(sess.pose_update(*updates[k + 1]))
+                if radius:
+                    after = vol.stream_stats()
+                    per_update.append((after[4] - before[4], after[5] - before[5]))
+        orders.append(sess.final_pass())
+        vol.check_error()
+        return orders, per_update
+
+    _say("resident session")
+    res = scsurf.Volume(S, MU, 1 << 22, 1 << 21, max_batch_ops=512)
+    ref_orders, _ = run(res, None)
+    ref = res.export_sorted()
+    total = len(ref["blocks"])
+    res.close()
+    cap = total // 4
+    _say(f"{total} blocks; streamed session with a pool of {cap}")
+    vol = scsurf.Volume(S, MU, 1 << 22, cap, max_batch_ops=4)
+    orders, per_update = run(vol, 3.0)
+    st = vol.stream_stats()
+    _say(f"device {st[0]}, host {st[1]}; streamed out {st[4] / 1e9:.2f} GB, in {st[5] / 1e9:.2f} GB; "
+         f"per update (out, in) MB: {[(round(a / 1e6, 1), round(b / 1e6, 1)) for a, b in per_update]}")
+    assert orders == ref_orders
+    assert st[0] <= cap and st[0] + st[1] == total
+    _equal(vol.export_sorted(with_host=True), ref)
+    vol.close()
