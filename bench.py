@@ -187,6 +187,29 @@ def adjoint_stage(torch, scsurf, synth):
     return float(np.median(times[1:]) * 1e3)
 
 
+def backward_full_stage(torch, vol, kset, wl, A, reps=4):
+    """Backward of integration at the benchmark's size: all 200 keyframes at
+    640x480 as integrated at their first poses in the benchmark volume, with
+    a seeded upstream dL/dD, gradients for depth and the se(3) poses (RGBA8
+    colour carries none).  Median wall-clock of the call, synchronised."""
+    n_blocks, _ = vol.query()
+    H, Wd = wl.intr.height, wl.intr.width
+    g = torch.Generator(device="cuda").manual_seed(7)
+    grad_D = torch.randn((n_blocks, 512), device="cuda", generator=g)
+    grad_depth = torch.zeros((len(kset), H, Wd), device="cuda")
+    grad_xi = torch.zeros((len(kset), 6), device="cuda")
+    times = []
+    for _ in range(reps):
+        grad_depth.zero_()
+        grad_xi.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vol.integrate_backward(kset, wl.intr, A[0], A[1], grad_D, None, grad_depth, None, grad_xi)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times[1:]) * 1e3)
+
+
 def kernel_variant(sched):
     """Name of the voxel-pass kernel a schedule (vpl, waves_per_wg, wgs_per_cu,
     compact) launches."""
@@ -200,12 +223,14 @@ def kernel_variant(sched):
     return "batch_main_wave_kernel<RGBA8>" if vpl == 8 else f"batch_main_group_kernel<RGBA8,{vpl}>"
 
 
-def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20):
+def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20, stream_radius=None, pool_blocks=None):
     """The online loop on the corridor workload: frames fused into keyframes of
     five, each keyframe integrated at its drifting estimate, a pose-graph
     update every `every` keyframes re-integrating the Eq. 3 window of m,
     then the final pass.  Frames are rendered to the device first; the loop
-    is timed."""
+    is timed.  With a stream radius the volume streams (a pool of
+    `pool_blocks`, batches of 4 operations) and the bytes moved between the
+    GPU and the host are reported, in all and per pose-graph update."""
     from paper_1709_03763_amd import online
 
     wl = synth.workload(5)
@@ -228,23 +253,36 @@ def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20):
         poses += [(A @ wl.R[f], A @ (wl.t[f] - tk[k]) + te[k]) for f in g]
     updates = {n: online.corrected(Rk[:n], tk[:n], drift[:n], 0.5 ** (n // every))
                for n in range(every, len(groups) + 1, every)}
-    vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, 1 << 21, scsurf.COLOR_RGBA8,
-                        max_batch_ops=512)
-    sess = online.OnlineSession(vol, wl.intr, kappa, m)
+    streamed = stream_radius is not None
+    pool = pool_blocks if streamed else 1 << 21
+    vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, pool, scsurf.COLOR_RGBA8,
+                        max_batch_ops=4 if streamed else 512)
+    sess = online.OnlineSession(vol, wl.intr, wl.kappa, m, stream_radius=stream_radius)
+    per_update = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for f in range(len(idx)):
         k = sess.add_frame(Z[f], C[f], *poses[f])
         if k is not None and (k + 1) in updates:
+            before = vol.stream_stats() if streamed else None
             sess.pose_update(*updates[k + 1])
+            if streamed:
+                after = vol.stream_stats()
+                per_update.append(after[4] - before[4] + after[5] - before[5])
     final = sess.final_pass()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_blocks = vol.check_error()
+    out = {"frames": len(idx), "keyframes": len(groups), "updates": len(updates), "m": m,
+           "final_pass_keyframes": len(final), "reintegrated_keyframes": sess.reintegrated, "blocks": n_blocks,
+           "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1)}
+    if streamed:
+        st = vol.stream_stats()
+        out.update({"pool_blocks": pool, "stream_radius_m": stream_radius, "device_blocks": st[0],
+                    "host_blocks": st[1], "streamed_out_bytes": st[4], "streamed_in_bytes": st[5],
+                    "streamed_bytes_per_update_mean": int(np.mean(per_update)) if per_update else 0})
     vol.close()
-    return {"frames": len(idx), "keyframes": len(groups), "updates": len(updates), "m": m,
-            "final_pass_keyframes": len(final), "reintegrated_keyframes": sess.reintegrated, "blocks": n_blocks,
-            "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1)}
+    return out
 
 
 def mesh_stage(torch, scsurf, surface, synth, vol, wl):
@@ -583,7 +621,8 @@ def main():
         log(f"autotuned schedule {sched} ({tune_ms:.2f} ms)")
     if args.sweep:
         sweep = [(8, 4, 2, 0), (8, 4, 4, 0), (8, 4, 8, 0), (4, 2, 8, 0), (4, 2, 16, 0), (2, 4, 4, 0), (2, 4, 8, 0),
-                 (1, 8, 2, 0), (1, 8, 4, 0), (8, 4, 2, 1), (8, 4, 4, 1), (8, 2, 4, 1), (8, 2, 8, 1), (8, 1, 16, 1), (8, 4, 4, 2), (8, 2, 8, 2), (8, 1, 16, 2), (8, 4, 4, 3), (8, 2, 8, 3), (8, 1, 16, 3)]
+                 (1, 8, 2, 0), (1, 8, 4, 0), (8, 4, 2, 1), (8, 4, 4, 1), (8, 2, 4, 1), (8, 2, 8, 1), (8, 1, 16, 1), (8, 4, 4, 2), (8, 2, 8, 2), (8, 1, 16, 2), (8, 4, 4, 3), (8, 2, 8, 3), (8, 1, 16, 3),
+                 (8, 4, 4, 4), (8, 2, 8, 4), (8, 1, 16, 4)]
         keep = vol.get_schedule()
         for sc in sweep:
             vol.set_schedule(*sc)
@@ -665,13 +704,19 @@ def main():
         mesh_res = mesh_stage(torch, scsurf, surface, synth, vol, wl)
         log(f"mesh: {mesh_res}")
 
+    bwd_full_ms = None
+    if not args.no_adjoint:
+        bwd_full_ms = backward_full_stage(torch, vol, kset, wl, A)
+        log(f"backward of integrating the 200 keyframes (depth and pose gradients): {bwd_full_ms:.2f} ms")
+
     online_res = None
     if not args.no_online:
         online_res = online_stage(torch, scsurf, synth)
         log(f"online loop (corridor, {online_res['frames']} frames): {online_res['frames_per_s']} frames/s, "
             f"{online_res['reintegrated_keyframes']} keyframe re-integrations incl. a final pass of "
             f"{online_res['final_pass_keyframes']}")
-        online_res["streaming"] = online_stage(torch, scsurf, synth, stream_radius=3.0, pool_frac=0.25)
+        online_res["streaming"] = online_stage(torch, scsurf, synth, stream_radius=3.0,
+                                               pool_blocks=online_res["blocks"] // 4)
         log(f"online loop with streaming (pool of a quarter of the field, 3 m sphere): {online_res['streaming']}")
 
     adj_ms = None
@@ -762,7 +807,8 @@ def main():
                    "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)
                                                / integrate_s / 1e9 / HBM_PEAK_GBS, 5),
                    "keyframe_pack_ms_per_keyframe": None if pack_s is None else round(pack_s * 1e3 / n_kf, 4),
-                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms, "online_loop": online_res,
+                   "autotune_best_ms": tune_ms, "adjoint_fwd_bwd_ms": adj_ms,
+                   "backward_200_keyframes_ms": bwd_full_ms, "online_loop": online_res,
                    "mesh": mesh_res, "mesh_poses": "the keyframes integrated at their first poses"},
     }
     if surface_res is not None:

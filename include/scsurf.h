@@ -307,10 +307,15 @@ sc_status sc_get_schedule(sc_volume* vol, sc_schedule* sched);
 
 /* Autotuner: times every schedule on a private copy of the volume running the
  * given update (nothing in `vol` changes), stores the fastest in the volume,
- * and writes it to *best (host, may be NULL) with its time in *best_ms. */
+ * and writes it to *best (host, may be NULL) with its time in *best_ms.
+ * Results are cached for the process, keyed by the GPU architecture, the
+ * image size, the operations per chunk, whether the keyframes are packed
+ * and the volume parameters; a call whose key is cached sets the cached
+ * schedule without timing.  sc_autotune_clear empties the cache. */
 sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
                       const sc_pose* T_integrated, const sc_pose* T_new, int32_t m, int32_t mode,
                       sc_schedule* best, float* best_ms, void* stream);
+void sc_autotune_clear(void);
 
 /* Measurement of the batched voxel pass: HIP events are recorded on the
  * caller's stream immediately before and after the persistent voxel pass of
@@ -338,7 +343,9 @@ sc_status sc_volume_stats(sc_volume* vol, void* stream, int64_t* stats);
  * blocks the store holds (one synchronisation per operation or batch chunk),
  * so every operation sees every block it may touch and the field equals,
  * bit for bit, the one a resident volume would hold.  A stream-in that does
- * not fit the pool sets the sticky SC_EPOOLFULL.  Disabling fails
+ * not fit the pool sets the sticky SC_EPOOLFULL; any other failure of the
+ * streaming step (SC_ENOMEM, SC_EDEVICE) is made sticky too, since the
+ * operation is left undone.  Disabling fails
  * (SC_EINVAL) while the host store holds blocks.  hash_alloc,
  * sc_volume_import and tsdf_integrate_backward return SC_EINVAL while it
  * does; export, mesh and stats see the device blocks only.  The host store

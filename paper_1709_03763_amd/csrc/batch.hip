@@ -18,9 +18,14 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -1521,6 +1526,10 @@ extern "C" {
 
 // A schedule is usable on a volume if it is valid and its LDS fits in 64 KiB
 // per workgroup.
+// The autotuner's results of this process (see sc_autotune).
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<sc_schedule, float>> g_tune;
+
 static bool schedule_fits(const sc_volume* vol, const sc_schedule& s)
 {
     if (!schedule_ok(s)) return false;
@@ -1643,6 +1652,27 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     std::vector<int32_t> order(n_kf);
     const int32_t ns = sc_select(T_integrated, T_new, n_kf, m, mode, order.data(), nullptr);
     if (ns < 0) return ns;
+    // tuning cache: one entry per (architecture, image size, operations per
+    // chunk, keyframe form, volume parameters); a hit sets the schedule
+    // without timing anything
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, vol->device) != hipSuccess) return SC_EDEVICE;
+    bool packed = vol->p.color_mode == SC_COLOR_RGBA8;
+    for (int j = 0; j < ns && packed; ++j) packed = kfs[order[j]].packed != nullptr;
+    char key[256];
+    snprintf(key, sizeof(key), "%s|%dx%d|%d|%d|%g|%g|%d|%d|%lld", prop.gcnArchName, intr->width, intr->height,
+             std::min(2 * ns, vol->p.max_batch_ops), (int)packed, (double)vol->p.voxel_size, (double)vol->p.trunc,
+             vol->p.color_mode, vol->p.max_batch_ops, (long long)vol->p.n_buckets);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            vol->sched = it->second.first;
+            if (best) *best = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            return SC_OK;
+        }
+    }
     sc_volume* tmp = nullptr;
     sc_status st = sc_volume_create(&vol->p, &tmp);
     if (st != SC_OK) return st;
@@ -1693,7 +1723,17 @@ sc_status sc_autotune(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, cons
     vol->sched = bs;
     if (best) *best = bs;
     if (best_ms) *best_ms = bms;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = std::make_pair(bs, bms);
+    }
     return SC_OK;
+}
+
+void sc_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
 }
 
 }  // extern "C"

@@ -431,11 +431,32 @@ static sc_status prepare_work(sc_volume* vol, hipStream_t s, uint32_t ncand, boo
     return SC_OK;
 }
 
-// Batched path, after the candidate stage: room for every candidate block,
-// the host-held ones streamed in, and the candidates' pool slots refreshed.
+// A streaming step that failed after the candidates were generated leaves
+// the operation undone and its candidate entries in place: the failure is
+// made sticky, so the volume is reset before further use.
+static sc_status fail_sticky(sc_volume* vol, sc_status e, hipStream_t s)
+{
+    if (e != SC_OK && e != SC_EPOOLFULL) set_error_kernel<<<1, 1, 0, s>>>(vol->dev.err, e);
+    return e;
+}
+
+static sc_status stream_in_batch_impl(sc_volume* vol, hipStream_t s);
+static sc_status stream_in_plain_impl(sc_volume* vol, int parity, hipStream_t s);
+
 sc_status stream_in_batch(sc_volume* vol, hipStream_t s)
 {
-    if (!streaming(vol)) return SC_OK;
+    return streaming(vol) ? fail_sticky(vol, stream_in_batch_impl(vol, s), s) : SC_OK;
+}
+
+sc_status stream_in_plain(sc_volume* vol, int parity, hipStream_t s)
+{
+    return streaming(vol) ? fail_sticky(vol, stream_in_plain_impl(vol, parity, s), s) : SC_OK;
+}
+
+// Batched path, after the candidate stage: room for every candidate block,
+// the host-held ones streamed in, and the candidates' pool slots refreshed.
+static sc_status stream_in_batch_impl(sc_volume* vol, hipStream_t s)
+{
     StreamStore* st = vol->stream;
     if (!grow_keys(st, vol->cand_buckets)) return SC_ENOMEM;
     set_count_kernel<<<1, 1, 0, s>>>(st->d_req, 0u);
@@ -453,9 +474,8 @@ sc_status stream_in_batch(sc_volume* vol, hipStream_t s)
 
 // Plain path, after the candidate list of one operation is built (the
 // update kernel looks its blocks up itself).
-sc_status stream_in_plain(sc_volume* vol, int parity, hipStream_t s)
+static sc_status stream_in_plain_impl(sc_volume* vol, int parity, hipStream_t s)
 {
-    if (!streaming(vol)) return SC_OK;
     StreamStore* st = vol->stream;
     if (!grow_keys(st, vol->cand.cap)) return SC_ENOMEM;
     set_count_kernel<<<1, 1, 0, s>>>(st->d_req, 0u);

@@ -44,18 +44,18 @@ void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// hash_alloc: wavefront ballot deduplication, CAS insert, LDS-staged queue
-// of new blocks and one pool reservation per workgroup
+// hash_alloc: wavefront ballot deduplication (one round per distinct key),
+// CAS insert, LDS-staged queue of new blocks and one pool reservation per
+// workgroup
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void hash_alloc_kernel(VolDev v, const int32_t* xyz, int64_t n)
 {
-    __shared__ uint64_t s_key[256];
     __shared__ uint32_t q_bucket[256];
     __shared__ uint32_t q_n;
     __shared__ uint32_t q_base;
     const int tid = threadIdx.x;
-    const int wave0 = tid & ~63;
+    const int lane = tid & 63;
     if (tid == 0) q_n = 0;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
     const bool have = i < n;
@@ -67,11 +67,20 @@ __global__ __launch_bounds__(256) void hash_alloc_kernel(VolDev v, const int32_t
         bz = xyz[3 * i + 2];
         key = pack_key(bx, by, bz);
     }
-    s_key[tid] = key;
     __syncthreads();
-    // one leader per distinct key within each wavefront: the lowest lane holding it
-    bool leader = have;
-    for (int l = wave0; l < tid && leader; ++l) leader = s_key[l] != key;
+    // one leader per distinct key within each wavefront, by ballot: the
+    // lowest lane still undecided takes its key, every lane holding that key
+    // is decided; one round per distinct key of the wavefront
+    bool leader = false;
+    uint64_t todo = __ballot(have);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)key, l);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(key >> 32), l);
+        const uint64_t k = ((uint64_t)hi << 32) | lo;
+        leader = leader || lane == l;
+        todo &= ~__ballot(key == k);
+    }
     if (leader) {
         uint32_t h = hash_block(bx, by, bz) & v.bucket_mask;
         bool done = false;

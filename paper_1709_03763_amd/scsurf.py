@@ -67,7 +67,7 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "kf_fuse_noalloc", "hash_alloc", "tsdf_integrate",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "sc_relative_motion", "reintegrate_batch",
            "reintegrate_plain",
-           "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_batch_timing", "sc_batch_timing_read",
+           "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_autotune_clear", "sc_batch_timing", "sc_batch_timing_read",
            "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
            "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table",
            "sc_volume_import", "sc_stream_enable", "sc_stream_out", "sc_stream_in_all", "sc_stream_stats",
@@ -117,6 +117,8 @@ def lib():
     L.sc_autotune.argtypes = [P, ctypes.POINTER(sc_keyframe), i32, ctypes.POINTER(sc_intrinsics),
                               ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose), i32, i32, ctypes.POINTER(sc_schedule),
                               ctypes.POINTER(ctypes.c_float), P]
+    L.sc_autotune_clear.argtypes = []
+    L.sc_autotune_clear.restype = None
     L.sc_batch_timing.argtypes = [P, i32]
     L.sc_batch_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
     L.sc_volume_stats.argtypes = [P, P, P]
@@ -469,6 +471,11 @@ class Volume:
         check(lib().sc_autotune(self._h, kset.arr, len(kfs), ctypes.byref(intrinsics(intr)), Ti, Tn, m, mode,
                                 ctypes.byref(best), ctypes.byref(ms), stream_handle(stream)), "sc_autotune")
         return (best.vpl, best.waves_per_wg, best.wgs_per_cu, best.compact), float(ms.value)
+
+    @staticmethod
+    def autotune_clear():
+        """Empties the process's autotuning cache."""
+        lib().sc_autotune_clear()
 
     def batch_timing(self, capacity: int):
         """Record HIP events around the voxel pass of the next `capacity` batched launches."""

@@ -237,8 +237,13 @@ def test_autotune_leaves_volume_unchanged(scene):
     _say("autotune")
     vol, ref, dks, okf = _integrated(wl, kfs, R, t)
     before = vol.export_sorted()
+    scsurf.Volume.autotune_clear()
     best, ms = vol.autotune(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
     assert best[0] in (8, 4, 2, 1) and ms > 0
+    assert vol.get_schedule() == best
+    # the same configuration again: the cached result, set without timing
+    vol.set_schedule(8, 4, 4)
+    assert vol.autotune(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED) == (best, ms)
     assert vol.get_schedule() == best
     after = vol.export_sorted()
     for key in ("blocks", "D", "W", "C"):
