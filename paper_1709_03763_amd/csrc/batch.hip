@@ -912,30 +912,39 @@ __device__ inline T kf_load(const void* base, uint32_t i)
     return *(G*)((GlobalBytes*)base + i * (uint32_t)sizeof(T));
 }
 
+// The lane's voxels in z-slices kz0 .. kz0 + 3 of one (block, operation)
+// after their gathers: the camera z (NaN for a voxel outside the image, so
+// that its band test fails), the pixel, and the keyframe sample there (pixel
+// 0 for a voxel outside the image).
+template <int CM>
+struct RingFetch {
+    float pz[4], wr[4], z[4];
+    uint32_t pix[4];
+    uint32_t c[4];  // RGBA8 colour at the pixel (RGBA8 mode)
+};
+
 // Projections of the lane's voxels in z-slices kz0 .. kz0 + 3 and their
-// keyframe gathers (voxels outside the image read pixel 0): one record per
-// voxel from a packed keyframe, else depth, weight and (RGBA8) colour.
+// keyframe gathers: one record per voxel from a packed keyframe, else depth,
+// weight and (RGBA8) colour.  The z steps k a_z are the descriptor's
+// host-rounded products, equal to the FP32 products of the convention.
 template <int CM, bool kPacked>
-__device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, VoxFetch<CM, 4>& f)
+__device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, RingFetch<CM>& f)
 {
-    f.in = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float fz = (float)(kz0 + j);
-        const float px = g.base[0] + fz * o.a[2][0];
-        const float py = g.base[1] + fz * o.a[2][1];
-        const float pz = g.base[2] + fz * o.a[2][2];
-        int p = 0;
-        const bool in = nearest_pixel_fast(o, px, py, pz, p);
-        f.in |= in ? (1u << j) : 0u;
-        f.pix[j] = in ? p : 0;
-        f.pz[j] = pz;
+        const float* za = o.za[kz0 + j];
+        const float px = g.base[0] + za[0];
+        const float py = g.base[1] + za[1];
+        const float pz = g.base[2] + za[2];
+        bool in;
+        f.pix[j] = pixel_index_fast(o, px, py, pz, in);
+        f.pz[j] = in ? pz : __builtin_nanf("");
     }
     if (kPacked) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             // the record's first three words, adjacent: one 12-byte load
-            const uint32_t i = 4u * (uint32_t)f.pix[j];
+            const uint32_t i = 4u * f.pix[j];
             f.z[j] = __uint_as_float(kf_load<uint32_t, GlobalU32>(o.packed, i));
             f.wr[j] = __uint_as_float(kf_load<uint32_t, GlobalU32>(o.packed, i + 1u));
             f.c[j] = kf_load<uint32_t, GlobalU32>(o.packed, i + 2u);
@@ -943,9 +952,9 @@ __device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, V
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            f.wr[j] = kf_load<float, GlobalF32>(o.weight, (uint32_t)f.pix[j]);
-            f.z[j] = kf_load<float, GlobalF32>(o.depth, (uint32_t)f.pix[j]);
-            f.c[j] = (CM == SC_COLOR_RGBA8) ? kf_load<uint32_t, GlobalU32>(o.color, (uint32_t)f.pix[j]) : 0u;
+            f.wr[j] = kf_load<float, GlobalF32>(o.weight, f.pix[j]);
+            f.z[j] = kf_load<float, GlobalF32>(o.depth, f.pix[j]);
+            f.c[j] = (CM == SC_COLOR_RGBA8) ? kf_load<uint32_t, GlobalU32>(o.color, f.pix[j]) : 0u;
         }
     }
 }
@@ -953,16 +962,13 @@ __device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, V
 // Touched decisions of fetched voxels; with kPacked the weight is already
 // quantised and the depth of a pixel without weight is -inf.
 template <int CM, bool kPacked>
-__device__ inline uint32_t ring_decide(const VoxFetch<CM, 4>& f, float mu, float w[4])
+__device__ inline void ring_decide(const RingFetch<CM>& f, float mu, float w[4], bool t[4])
 {
-    uint32_t hit = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         w[j] = kPacked ? f.wr[j] : qweight(f.wr[j]);
-        const bool t = ((f.in >> j) & 1u) && (kPacked || w[j] > 0.0f) && fabsf(f.z[j] - f.pz[j]) <= mu;
-        hit |= t ? (1u << j) : 0u;
+        t[j] = (kPacked || w[j] > 0.0f) && fabsf(f.z[j] - f.pz[j]) <= mu;
     }
-    return hit;
 }
 
 // The operations of a block in bit order, its mask words held one per lane
@@ -1021,7 +1027,7 @@ __device__ inline void ring_flush(const OpDesc& op, double qz, Ring& ring, uint3
         float W = L.sW[x];
         if (CM == SC_COLOR_RGBA8) {
             uint32_t C = L.sC[x];
-            pb.e_w |= !update_rgba8(D, W, C, d, wq, L.qc[e], op.sign);
+            pb.e_w |= !update_rgba8_fast(D, W, C, d, wq, L.qc[e], op.sign);
             L.sC[x] = C;
         } else {
             GlobalF32* cp = (GlobalF32*)op.color + 3 * (size_t)L.qc[e];
@@ -1046,7 +1052,7 @@ __device__ inline void ring_flush(const OpDesc& op, double qz, Ring& ring, uint3
 // when the block has no further step.
 template <int CM, bool kPacked>
 __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v, LaneWalk& walk, PipeBlock& pb,
-                                 VoxFetch<CM, 4>& cur, VoxFetch<CM, 4>& nxt, RingGeom& gc, int& op_c, int& part_c,
+                                 RingFetch<CM>& cur, RingFetch<CM>& nxt, RingGeom& gc, int& op_c, int& part_c,
                                  int lane, const PipeLds& L, Ring& ring)
 {
     int op_n, part_n;
@@ -1065,27 +1071,31 @@ __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v
     const OpDesc& op = ops[op_c];
     pb.pairs += (part_c == 0) ? 1u : 0u;
     float w[4];
-    const uint32_t hit = ring_decide<CM, kPacked>(cur, v.mu, w);
-    const bool any = __ballot(hit != 0u) != 0ull;
+    bool t[4];
+    ring_decide<CM, kPacked>(cur, v.mu, w, t);
+    uint64_t bal[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bal[j] = __ballot(t[j]);
+    const bool any = ((bal[0] | bal[1]) | (bal[2] | bal[3])) != 0ull;
     pb.pair_any = (part_c == 0) ? any : (pb.pair_any || any);
     if (any && op.sign < 0 && pb.slot < 0) {
         pb.e_na = true;
     } else if (any) {
         if (op.sign > 0) pb.re_touch = true;
-        pb.touched |= hit << (part_c * 4);
-        pb.n_upd += __popc(hit);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const bool t = (hit >> j) & 1u;
-            const uint64_t bal = __ballot(t);
-            if (t) {
-                const uint32_t pos = (ring.tail + lanes_below(bal)) & 127u;
+            if (bal[j] == 0ull) continue;
+            const uint32_t nb = (uint32_t)__popcll(bal[j]);
+            pb.touched |= 1u << (part_c * 4 + j);
+            pb.n_upd += nb;
+            if (t[j]) {
+                const uint32_t pos = (ring.tail + lanes_below(bal[j])) & 127u;
                 L.qvox[pos] = (uint16_t)(lane + 64 * (part_c * 4 + j));
                 L.qw[pos] = w[j];
                 L.qz[pos] = cur.z[j];
-                L.qc[pos] = (CM == SC_COLOR_RGBA8) ? cur.c[j] : (uint32_t)cur.pix[j];
+                L.qc[pos] = (CM == SC_COLOR_RGBA8) ? cur.c[j] : cur.pix[j];
             }
-            ring.tail += (uint32_t)__popcll(bal);
+            ring.tail += nb;
             if (ring.tail - ring.head >= 64u) ring_flush<CM>(op, gc.qz, ring, 64u, pb, lane, L);
         }
     }
@@ -1109,7 +1119,9 @@ __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v
 }
 
 // Persistent voxel pass with the ring queue: one wavefront per block, block
-// state in LDS, the same LDS footprint as the pipelined pass.  kPacked: every
+// state in LDS, the same LDS footprint as the pipelined pass.  Its
+// PipeBlock counts (touched z-slices, updates) are uniform over the
+// wavefront.  kPacked: every
 // operation's keyframe carries its packed copy (RGBA8 volumes).
 template <int CM, bool kPacked>
 __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
@@ -1159,7 +1171,7 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
         lanewalk_init(walk, cd.mask + (size_t)h * cd.words, cd.words, lane);
         int op_c = lanewalk_next(walk);
         if (op_c >= 0) {
-            VoxFetch<CM, 4> f0, f1;
+            RingFetch<CM> f0, f1;
             RingGeom gc;
             Ring ring;
             ring.head = ring.tail = 0u;
@@ -1181,6 +1193,8 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
             float* blk = v.pool + (size_t)slot * v.stride;
 #pragma unroll 2
             for (int j = 0; j < 8; ++j) {
+                // every slice with a touched voxel is written whole (the
+                // voxels the operations left keep the values read above)
                 if (!((pb.touched >> j) & 1u)) continue;
                 const int x = lane + 64 * j;
                 reinterpret_cast<double*>(blk)[x] = L.sD[x];
@@ -1195,13 +1209,12 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
                 }
             }
         }
-        const bool wrote = __ballot(pb.touched != 0) != 0;
-        n_written += (slot >= 0 && wrote) ? 1u : 0u;
+        n_written += (slot >= 0 && pb.touched != 0u) ? 1u : 0u;
         retire_candidate(cd, v, h, all, lane);
         wave_lds_sync();
     }
     stat_add(cd, 1, worker, n_pairs, lane);
-    stat_add(cd, 2, worker, wave_sum(n_upd), lane);
+    stat_add(cd, 2, worker, n_upd, lane);
     stat_add(cd, 3, worker, n_written, lane);
 }
 

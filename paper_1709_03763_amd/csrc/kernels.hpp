@@ -183,6 +183,24 @@ __device__ inline bool nearest_pixel_fast(const OpDesc& op, float px, float py, 
     return true;
 }
 
+// nearest_pixel_fast without branches around it: the pixel index (0 when
+// `in` is false: behind the camera or outside the image).  A lane behind
+// the camera projects with z = 1 so that its coordinates stay finite.  The
+// index fv W + fu is an integer below 2^24, so one FP32 fma forms it
+// exactly.
+__device__ inline uint32_t pixel_index_fast(const OpDesc& op, float px, float py, float pz, bool& in)
+{
+    const bool front = pz > 0.0f;
+    const float zs = front ? pz : 1.0f;
+    const float r = __builtin_amdgcn_rcpf(zs);
+    const float fu = pixel_coord_fast(op.fx * px, zs, r, op.cx, op.wl);
+    const float fv = pixel_coord_fast(op.fy * py, zs, r, op.cy, op.hl);
+    // bitwise, not short-circuit: no branches
+    in = front & (fu >= 0.0f) & (fu <= op.wl) & (fv >= 0.0f) & (fv <= op.hl);
+    const uint32_t p = (uint32_t)fmaf(fv, op.wf, fu);
+    return in ? p : 0u;
+}
+
 // Nearest pixel of the FP32 camera point (px, py, pz); false if behind the
 // camera or outside the image.
 __device__ inline bool nearest_pixel(const OpDesc& op, float px, float py, float pz, int& pix)
@@ -343,6 +361,54 @@ __device__ inline bool update_rgba8(double& D, float& W, uint32_t& C, double d, 
     for (int k = 0; k < 3; ++k) {
         const double N = (double)((C >> (8 * k)) & 0xFFu) * Wq + (double)((c >> (8 * k)) & 0xFFu) * swq;
         C1 |= mix_channel(N, M, rM) << (8 * k);
+    }
+    D = bad ? D : (zero ? 0.0 : D1);
+    C = bad ? C : (zero ? 0u : C1);
+    W = bad ? W : (zero ? 0.0f : W1);
+    return !bad;
+}
+
+// update_rgba8 with each colour channel's quotient y = N / M first estimated
+// in FP32: y' = fl(fl(c swq + fl(C Wq)) fl32(1/M)).  Below the weight limit
+// Wq, swq and M are integers below 2^24, and
+// |y' - y| <= 2^-24 (C Wq / M + 3 |y|) (1 + 2^-20), which is below
+// E = 2^-22 (255 Wq / M + |y'| + 1).  When |y' - rint(y')| + E <= 1/2 the
+// exact quotient lies strictly inside the same rounding interval, so
+// rint(y') clamped to [0, 255] is the exact result; a lane with a channel
+// nearer a rounding boundary (exact ties among them) takes update_rgba8's
+// FP64 path.  The same results as update_rgba8, bit for bit.
+__device__ inline bool update_rgba8_fast(double& D, float& W, uint32_t& C, double d, float w, uint32_t c, int sign)
+{
+    const float sw = (sign > 0) ? w : -w;
+    const float W1 = W + sw;  // exact on the 2^-10 grid
+    const bool bad = !(W1 < kWeightLimit) || W1 < 0.0f;
+    const bool zero = W1 == 0.0f;
+    const double M = (double)W1 * (double)kWeightScale;
+    double rM = __builtin_amdgcn_rcp(M);
+    rM = fma(rM, fma(-M, rM, 1.0), rM);
+    rM = fma(rM, fma(-M, rM, 1.0), rM);
+    const double D1 = (D * (double)W + d * (double)sw) * (rM * (double)kWeightScale);
+    const float Wq = W * kWeightScale, swq = sw * kWeightScale;
+    const float rMf = (float)rM;
+    const float E0 = fmaf(Wq * rMf, 255.0f * 0x1p-22f, 0x1p-22f);
+    uint32_t C1 = 0u;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float Ck = (float)((C >> (8 * k)) & 0xFFu), ck = (float)((c >> (8 * k)) & 0xFFu);
+        const float y = fmaf(ck, swq, Ck * Wq) * rMf;
+        const float q = rintf(y);
+        ok = ok && (fabsf(y - q) + fmaf(fabsf(y), 0x1p-22f, E0) <= 0.5f);
+        C1 |= (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f) << (8 * k);
+    }
+    if (!(ok || bad || zero)) {
+        const double Wqd = (double)Wq, swqd = (double)swq;
+        C1 = 0u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double N = (double)((C >> (8 * k)) & 0xFFu) * Wqd + (double)((c >> (8 * k)) & 0xFFu) * swqd;
+            C1 |= mix_channel(N, M, rM) << (8 * k);
+        }
     }
     D = bad ? D : (zero ? 0.0 : D1);
     C = bad ? C : (zero ? 0u : C1);

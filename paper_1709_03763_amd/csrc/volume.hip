@@ -311,6 +311,11 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
         for (int r = 0; r < 3; ++r) op->a[c][r] = (float)(s * T->R[3 * c + r]);
         op->az[c] = s * T->R[3 * c + 2];
     }
+    for (int k = 0; k < 8; ++k)
+        for (int r = 0; r < 3; ++r) op->za[k][r] = (float)k * op->a[2][r];  // one FP32 rounding, as on the device
+    op->wl = (float)(in->width - 1);
+    op->hl = (float)(in->height - 1);
+    op->wf = (float)in->width;
     op->sign = sign;
     op->kf = kf_index;
 }
