@@ -64,6 +64,7 @@ struct OpDesc {
     double az[3];         // s * R[axis][2] in FP64: camera-z step per voxel for the continuous distance
     float za[8][3];       // za[k][row] = fl32(k * a[2][row]): camera step of k voxels along world z
     float wl, hl, wf;     // width - 1, height - 1 and width as FP32
+    float kin_u, kin_v;   // 1/2 - (2 + |c|) 2^-21 for cx and cy: bound of the pixel rounding test
     int32_t sign;         // +1 integrate, -1 de-integrate
     int32_t kf;           // keyframe index within the call (for gradients)
     // Touched-block record of this (keyframe, pose): an integration with

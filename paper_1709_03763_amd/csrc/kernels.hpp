@@ -183,8 +183,28 @@ __device__ inline bool nearest_pixel_fast(const OpDesc& op, float px, float py, 
     return true;
 }
 
-// nearest_pixel_fast without branches around it: the pixel index (0 when
-// `in` is false: behind the camera or outside the image).  A lane behind
+// The pixel coordinate of pixel_coord_fast with a cheaper test.  For
+// |yq| < 2^22 the convention's fl32(y + 1/2) is exact, so its floor is the
+// nearest integer to y = fl32(t + c) away from half-integers, and rint(yq)
+// stands in for floor(fl32(yq + 1/2)).  |y - yq| <= |tq| 2^-22 +
+// (|y| + |yq|) 2^-24, below (2 |tq| + |c|) 2^-21 + 2^-21 >= (|tq| + |yq|)
+// 2^-21 + 2^-21; so when yq lies inside (-1/2, 1/2) of rint(yq) by more
+// than that, y lies in the same interval and floor(y + 1/2) = rint(yq).
+// kin <= 1/2 - (1 + |c|) 2^-21 comes with the operation.  A coordinate with
+// |yq| >= 2^22 is far outside the image either way.  Other lanes take the
+// interval test of pixel_coord.
+__device__ inline float pixel_coord_rint(float a, float z, float r, float c, float kin, float limit)
+{
+    const float tq = a * r;
+    const float yq = tq + c;
+    const float fl = rintf(yq);
+    if (fabsf(yq - fl) < fmaf(fabsf(tq), -0x1p-20f, kin)) return fl;
+    return pixel_coord(a, z, r, c, limit);
+}
+
+// The nearest pixel without branches around it, with pixel_coord_rint: the
+// pixel index (0 when `in` is false: behind the camera or outside the
+// image).  A lane behind
 // the camera projects with z = 1 so that its coordinates stay finite.  The
 // index fv W + fu is an integer below 2^24, so one FP32 fma forms it
 // exactly.
@@ -193,8 +213,8 @@ __device__ inline uint32_t pixel_index_fast(const OpDesc& op, float px, float py
     const bool front = pz > 0.0f;
     const float zs = front ? pz : 1.0f;
     const float r = __builtin_amdgcn_rcpf(zs);
-    const float fu = pixel_coord_fast(op.fx * px, zs, r, op.cx, op.wl);
-    const float fv = pixel_coord_fast(op.fy * py, zs, r, op.cy, op.hl);
+    const float fu = pixel_coord_rint(op.fx * px, zs, r, op.cx, op.kin_u, op.wl);
+    const float fv = pixel_coord_rint(op.fy * py, zs, r, op.cy, op.kin_v, op.hl);
     // bitwise, not short-circuit: no branches
     in = front & (fu >= 0.0f) & (fu <= op.wl) & (fv >= 0.0f) & (fv <= op.hl);
     const uint32_t p = (uint32_t)fmaf(fv, op.wf, fu);

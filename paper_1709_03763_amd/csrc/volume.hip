@@ -316,6 +316,9 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     op->wl = (float)(in->width - 1);
     op->hl = (float)(in->height - 1);
     op->wf = (float)in->width;
+    // one extra 2^-21 covers the rounding of the bound itself to FP32
+    op->kin_u = (float)(0.5 - (2.0 + fabs((double)in->cx)) * 0x1p-21);
+    op->kin_v = (float)(0.5 - (2.0 + fabs((double)in->cy)) * 0x1p-21);
     op->sign = sign;
     op->kf = kf_index;
 }

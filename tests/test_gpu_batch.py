@@ -99,6 +99,40 @@ def test_every_schedule_gives_identical_bits(scene, sched):
     vol.close()
 
 
+@pytest.mark.parametrize("sched", [(8, 2, 8, 4), (8, 4, 4, 3)])
+def test_colour_ties_and_clamping(scene, sched):
+    """Keyframes of one geometry with equal weights and independent colours,
+    integrated at one pose: every voxel's colour after the second is the
+    mean of two bytes, an exact tie whenever their sum is odd (rounded half
+    to even), and de-integrating one of them extrapolates, often beyond
+    [0, 255] (clamped).  A third keyframe with 3/2 the weight gives thirds
+    and fifths.  The batched pass must equal the oracle bit for bit on these
+    rounding boundaries."""
+    wl, kfs, R, t = scene
+    rng = np.random.default_rng(42)
+    base = kfs[0]
+    valid = base["weight"] > 0
+    mk = []
+    for wv in (0.5, 0.5, 0.75):
+        col = rng.integers(0, 256, base["color"].shape, dtype=np.uint8)
+        mk.append({"depth": base["depth"], "weight": np.where(valid, np.float32(wv), np.float32(0)).astype(np.float32),
+                   "color": col})
+    Rk = np.repeat(R[:1], 3, 0)
+    tk = np.repeat(t[:1], 3, 0)
+    _say(f"colour ties, schedule {sched}")
+    vol, ref, dks, okf = _integrated(wl, mk, Rk, tk)
+    mid = ref.export()
+    two = (mid["W"] > 0)
+    assert two.any()
+    vol.set_schedule(*sched)
+    Rn, tn = synth.perturb_all(Rk, tk, 0.004, 0.2, 9)
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (Rk, tk), (Rn, tn), 3, scsurf.SEL_ALL_ORDERED)
+    _oracle_update(ref, okf, wl, Rk, tk, Rn, tn, order)
+    vol.check_error()
+    compare_fields(vol.export_sorted(), ref.export())
+    vol.close()
+
+
 @pytest.mark.parametrize("sched", [(8, 2, 4, 1), (8, 2, 4, 2), (8, 2, 4, 3), (8, 2, 4, 4), (8, 1, 7, 4), (4, 2, 8)])
 def test_fp32_colour_schedules(scene, sched):
     """FP32-colour volumes under the compacting and the multi-wavefront
