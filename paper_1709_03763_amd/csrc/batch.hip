@@ -930,14 +930,20 @@ struct RingFetch {
 template <int CM, bool kPacked>
 __device__ inline void ring_fetch(const OpDesc& o, const RingGeom& g, int kz0, RingFetch<CM>& f)
 {
+    // the operation's constants, read together at the top
+    const ProjConst k = proj_const(o);
+    float za[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) za[j][r] = o.za[kz0 + j][r];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float* za = o.za[kz0 + j];
-        const float px = g.base[0] + za[0];
-        const float py = g.base[1] + za[1];
-        const float pz = g.base[2] + za[2];
+        const float px = g.base[0] + za[j][0];
+        const float py = g.base[1] + za[j][1];
+        const float pz = g.base[2] + za[j][2];
         bool in;
-        f.pix[j] = pixel_index_fast(o, px, py, pz, in);
+        f.pix[j] = pixel_index_fast(k, px, py, pz, in);
         f.pz[j] = in ? pz : __builtin_nanf("");
     }
     if (kPacked) {

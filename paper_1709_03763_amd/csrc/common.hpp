@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "scsurf.h"
@@ -52,21 +53,24 @@ __host__ __device__ inline uint32_t hash_block(int x, int y, int z)
 // One keyframe operation (integrate or de-integrate a keyframe at a pose):
 // everything the voxel pass needs, precomputed on the host.
 struct OpDesc {
+    // The projection's constants first and contiguous (za at byte 64), so
+    // that a pass reads them with a few wide scalar loads.
+    const uint4* packed;  // optional interleaved {depth, weight, RGBA8, 0} per pixel (RGBA8 volumes)
+    float fx, fy, cx, cy;
+    float kin_u, kin_v;   // 1/2 - (2 + |c|) 2^-21 for cx and cy: bound of the pixel rounding test
+    float wl, hl, wf;     // width - 1, height - 1 and width as FP32
+    int32_t width, height;
+    int32_t sign;         // +1 integrate, -1 de-integrate
+    int32_t kf;           // keyframe index within the call (for gradients)
+    int32_t rec_mode;     // touched-block record, see below
+    float za[8][3];       // za[k][row] = fl32(k * a[2][row]): camera step of k voxels along world z
     const float* depth;   // Z*, H x W
     const float* weight;  // W*, H x W
     const void* color;    // RGBA8 (uint32 per pixel) or float x 3
-    const uint4* packed;  // optional interleaved {depth, weight, RGBA8, 0} per pixel (RGBA8 volumes)
-    int32_t width, height;
-    float fx, fy, cx, cy;
     double R[9];          // camera -> world rotation, row-major
     double t[3];          // camera -> world translation
     float a[3][3];        // a[axis][row] = fl32(s * R[axis][row]): camera step of one voxel along a world axis
     double az[3];         // s * R[axis][2] in FP64: camera-z step per voxel for the continuous distance
-    float za[8][3];       // za[k][row] = fl32(k * a[2][row]): camera step of k voxels along world z
-    float wl, hl, wf;     // width - 1, height - 1 and width as FP32
-    float kin_u, kin_v;   // 1/2 - (2 + |c|) 2^-21 for cx and cy: bound of the pixel rounding test
-    int32_t sign;         // +1 integrate, -1 de-integrate
-    int32_t kf;           // keyframe index within the call (for gradients)
     // Touched-block record of this (keyframe, pose): an integration with
     // rec_mode 1 appends every block it touches; a de-integration with
     // rec_mode 2 takes those blocks as its candidates (the same keyframe at
@@ -74,9 +78,9 @@ struct OpDesc {
     // overflow; rec_mode 0: no record.
     uint64_t* rec_keys;   // rec_cap keys
     uint32_t* rec_count;  // appended so far (may exceed rec_cap: overflowed)
-    int32_t rec_mode;
     int32_t rec_cap;
 };
+static_assert(offsetof(OpDesc, za) == 64, "projection constants of OpDesc: za at byte 64");
 
 // Device view of a volume.
 struct VolDev {

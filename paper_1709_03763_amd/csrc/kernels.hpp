@@ -202,22 +202,31 @@ __device__ inline float pixel_coord_rint(float a, float z, float r, float c, flo
     return pixel_coord(a, z, r, c, limit);
 }
 
+// The projection constants of one operation, read together.
+struct ProjConst {
+    float fx, fy, cx, cy, kin_u, kin_v, wl, hl, wf;
+};
+
+__device__ inline ProjConst proj_const(const OpDesc& op)
+{
+    return {op.fx, op.fy, op.cx, op.cy, op.kin_u, op.kin_v, op.wl, op.hl, op.wf};
+}
+
 // The nearest pixel without branches around it, with pixel_coord_rint: the
 // pixel index (0 when `in` is false: behind the camera or outside the
-// image).  A lane behind
-// the camera projects with z = 1 so that its coordinates stay finite.  The
-// index fv W + fu is an integer below 2^24, so one FP32 fma forms it
-// exactly.
-__device__ inline uint32_t pixel_index_fast(const OpDesc& op, float px, float py, float pz, bool& in)
+// image).  A lane behind the camera projects with z = 1 so that its
+// coordinates stay finite.  The index fv W + fu is an integer below 2^24, so
+// one FP32 fma forms it exactly.
+__device__ inline uint32_t pixel_index_fast(const ProjConst& k, float px, float py, float pz, bool& in)
 {
     const bool front = pz > 0.0f;
     const float zs = front ? pz : 1.0f;
     const float r = __builtin_amdgcn_rcpf(zs);
-    const float fu = pixel_coord_rint(op.fx * px, zs, r, op.cx, op.kin_u, op.wl);
-    const float fv = pixel_coord_rint(op.fy * py, zs, r, op.cy, op.kin_v, op.hl);
+    const float fu = pixel_coord_rint(k.fx * px, zs, r, k.cx, k.kin_u, k.wl);
+    const float fv = pixel_coord_rint(k.fy * py, zs, r, k.cy, k.kin_v, k.hl);
     // bitwise, not short-circuit: no branches
-    in = front & (fu >= 0.0f) & (fu <= op.wl) & (fv >= 0.0f) & (fv <= op.hl);
-    const uint32_t p = (uint32_t)fmaf(fv, op.wf, fu);
+    in = front & (fu >= 0.0f) & (fu <= k.wl) & (fv >= 0.0f) & (fv <= k.hl);
+    const uint32_t p = (uint32_t)fmaf(fv, k.wf, fu);
     return in ? p : 0u;
 }
 
