@@ -95,9 +95,14 @@ typedef struct {
  * {float depth', float q(weight), uint32 RGBA8 colour, uint32 0} with
  * q(w) = rint(w 2^10) / 2^10 and depth' = depth where q(weight) > 0, -inf
  * elsewhere (so the band test alone rejects a pixel without weight),
- * 16-byte aligned, as written by sc_keyframe_pack.  Volumes in RGBA8 mode
- * then read every keyframe sample from it (one gather per voxel instead of
- * three); FP32-colour volumes ignore it.  It must hold the packing of this
+ * followed by the depth range of every 4 x 4 pixel cell:
+ * ceil(H/4) x ceil(W/4) pairs {float zmin, float zmax} (row-major) over the
+ * cell's valid pixels (q(weight) > 0 and 0 < depth < 1e30), {+inf, -inf}
+ * for a cell without one.  16-byte aligned, sc_keyframe_pack_bytes(W, H)
+ * bytes, as written by sc_keyframe_pack.  Volumes in RGBA8 mode then read
+ * every keyframe sample from it (one gather per voxel instead of three) and
+ * the batched candidate stage reads the cell ranges instead of the pixels;
+ * FP32-colour volumes ignore it.  It must hold the packing of this
  * keyframe's depth, weight and colour, and is owned by the caller. */
 typedef struct {
     const float* depth;  /* device, H x W, metres */
@@ -115,12 +120,19 @@ typedef struct {
 
 typedef struct sc_volume sc_volume;
 
-/* Writes the interleaved copy of an RGBA8 keyframe used by the voxel passes:
+/* Bytes of the packed copy of a width x height keyframe (records and cell
+ * depth ranges, see sc_keyframe); 0 for a size outside 1 .. 16384. */
+int64_t sc_keyframe_pack_bytes(int32_t width, int32_t height);
+
+/* Writes the packed copy of an RGBA8 keyframe used by the batched passes:
  * packed[i] = {q(weight[i]) > 0 ? depth[i] : -inf, q(weight[i]), color[i], 0}
- * for the width * height pixels (q as in sc_keyframe).  `packed` is a caller-owned device buffer of width * height * 16
- * bytes, 16-byte aligned.  SC_EINVAL on a null pointer, a misaligned buffer
- * or a non-positive size; asynchronous on `stream`. */
-sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream);
+ * for the width * height pixels (q as in sc_keyframe), then the cell depth
+ * ranges.  `packed` is a caller-owned device buffer of `packed_bytes` >=
+ * sc_keyframe_pack_bytes(width, height) bytes, 16-byte aligned.  SC_EINVAL
+ * on a null pointer, a misaligned or short buffer or a size outside
+ * 1 .. 16384; asynchronous on `stream`. */
+sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, int64_t packed_bytes,
+                           void* stream);
 
 /* ---- volume lifecycle --------------------------------------------------- */
 

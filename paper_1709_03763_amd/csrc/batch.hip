@@ -37,6 +37,8 @@ namespace sc {
 __global__ void batch_init_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr, CandDev cd, int n_bins)
 {
     for (int i = threadIdx.x; i < 8; i += blockDim.x) cd.counters[4 + i] = 0u;
+    for (int i = threadIdx.x; i < kCursors; i += blockDim.x) cd.cursors[i * kCursorStride] = 0u;
+    if (threadIdx.x == 0) cd.cursors[kCursorDone] = 0u;
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) cd.bins[i] = 0u;
     // integrations that record their touched blocks start an empty record
     for (int o = threadIdx.x; o < hdr->n_ops; o += blockDim.x)
@@ -88,8 +90,18 @@ __global__ __launch_bounds__(256) void cand_record_kernel(const OpDesc* __restri
 }
 
 // Frustum-cell candidates of the operations without a record, one (operation,
-// 64 x 64 tile) item at a time.
+// 64 x 64 tile) item at a time.  Tiles differ widely in cost (grazing
+// surfaces give large cell boxes), so items are handed out dynamically: item
+// i belongs to range i mod kCursors, workgroup b takes item b first (no
+// atomic), then kCandPop items at a time from its range's cursor; a
+// workgroup that finds its range exhausted marks it in a shared bit mask and
+// moves on to a range not yet marked.  One cursor for all items would
+// serialise the pops (a device-wide atomic on one address is serviced one at
+// a time).
+// kFromCells: every operation's keyframe is packed (its cell depth ranges
+// stand in for the pixels).
 constexpr int kCandPop = 2;
+template <bool kFromCells>
 __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr,
                                                          VolDev v, CandDev cd)
 {
@@ -98,40 +110,59 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
     __shared__ int next;
     const int tiles = hdr->tiles_x * hdr->tiles_y;
     const int items = hdr->n_tile_ops * tiles;
-    // first item static, then kCandPop items per pop from the batch's tile
-    // cursor: tiles differ widely in cost (grazing surfaces give large cell
-    // boxes), so a static stride leaves a tail of workgroups with heavy
-    // tiles, while the cursor's atomics are serviced one at a time
-    int it = blockIdx.x, end = it + 1;
+    int r = (int)blockIdx.x % kCursors;
+    int k = (int)blockIdx.x / kCursors, end = k + 1;  // index within range r
     for (;;) {
-        if (it >= end) {
+        if (k >= end) {
             __syncthreads();
-            if (threadIdx.x == 0) next = (int)gridDim.x + kCandPop * (int)atomicAdd(cd.counters + 6, 1u);
+            if (threadIdx.x == 0) {
+                // range r's first indices went to the static first items
+                const int base = ((int)gridDim.x - r + kCursors - 1) / kCursors;
+                next = base + kCandPop * (int)atomicAdd(cd.cursors + r * kCursorStride, 1u);
+            }
             __syncthreads();
-            it = next;
-            end = it + kCandPop;
+            k = next;
+            end = k + kCandPop;
         }
-        if (it >= items) break;
-        const int k = it / tiles;
-        const int o = hdr->tile_ops[k];
-        const int tile = it - k * tiles;
+        const int it = r + kCursors * k;
+        if (it >= items) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t m = atomicOr(cd.cursors + kCursorDone, 1u << r) | (1u << r);
+                int nr = -1;
+                for (int j = 1; j < kCursors && nr < 0; ++j)
+                    if (!((m >> ((r + j) % kCursors)) & 1u)) nr = (r + j) % kCursors;
+                next = nr;
+            }
+            __syncthreads();
+            if (next < 0) break;
+            r = next;
+            end = k;  // pop from the new range
+            continue;
+        }
+        const int kk = it / tiles;
+        const int o = hdr->tile_ops[kk];
+        const int tile = it - kk * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
-        cand_tile<kTileBatch, kCellBatch>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
+        cand_tile<kTileBatch, kCellBatch, kFromCells>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
         __syncthreads();
-        ++it;
+        ++k;
     }
 }
 
 // Workgroups of cand_batch_kernel that fit on one CU at once (registers and
 // LDS); the kernel strides over its items statically, so a grid larger than
 // this runs its surplus as a second, mostly idle wave of workgroups.
-int cand_batch_resident_wgs()
+int cand_batch_resident_wgs(bool from_cells)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cand_batch_kernel, CandCfg<kTileBatch, kCellBatch>::threads,
-                                                     0) != hipSuccess)
-        n = 0;
+    const hipError_t e =
+        from_cells ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cand_batch_kernel<true>,
+                                                                  CandCfg<kTileBatch, kCellBatch>::threads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cand_batch_kernel<false>,
+                                                                  CandCfg<kTileBatch, kCellBatch>::threads, 0);
+    if (e != hipSuccess) n = 0;
     return std::max(1, std::min(n, 8));
 }
 
@@ -1313,12 +1344,17 @@ static bool schedule_ok(const sc_schedule& s)
 
 // Candidate stage: clears the per-batch counters, generates the candidate
 // blocks with their operation masks, and orders them by operation count.
-static void launch_candidates(sc_volume* vol, hipStream_t s)
+static void launch_candidates(sc_volume* vol, bool from_cells, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->d_ops, vol->d_hdr, vol->cand, n_bins);
-    cand_batch_kernel<<<vol->n_cu * vol->cand_wgs, CandCfg<kTileBatch, kCellBatch>::threads, 0, s>>>(
-        vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
+    const int threads = CandCfg<kTileBatch, kCellBatch>::threads;
+    if (from_cells)
+        cand_batch_kernel<true><<<vol->n_cu * vol->cand_wgs[1], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
+                                                                                 vol->cand);
+    else
+        cand_batch_kernel<false><<<vol->n_cu * vol->cand_wgs[0], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
+                                                                                  vol->cand);
     cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(vol->d_ops, vol->d_hdr,
                                                                                            vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
@@ -1430,11 +1466,10 @@ static hipGraphExec_t capture(sc_volume* vol, F&& launch)
     return ex;
 }
 
-// Returns the candidate-stage graph and the voxel-pass graph for the current
-// schedule and keyframe form, capturing each on first use.
-static bool graphs_for(sc_volume* vol, bool packed, hipGraphExec_t& pre, hipGraphExec_t& main)
+// Returns the voxel-pass graph for the current schedule and keyframe form,
+// capturing it on first use.
+static bool graphs_for(sc_volume* vol, bool packed, hipGraphExec_t& main)
 {
-    if (!vol->graph_pre) vol->graph_pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, cs); });
     const int vi = sched_index(vol->sched) + (packed ? 4 : 0);
     const int key = (vol->sched.compact * 8 + vol->sched.waves_per_wg) * 64 + vol->sched.wgs_per_cu;
     if (vol->graph_main[vi] && vol->graph_keys[vi] != key) {
@@ -1446,9 +1481,8 @@ static bool graphs_for(sc_volume* vol, bool packed, hipGraphExec_t& pre, hipGrap
         vol->graph_main[vi] = capture(vol, [&](hipStream_t cs) { launch_voxel_pass(vol, sch, packed, cs); });
         vol->graph_keys[vi] = key;
     }
-    pre = vol->graph_pre;
     main = vol->graph_main[vi];
-    return pre && main;
+    return main != nullptr;
 }
 
 // Copies one chunk of staged operations to the device and runs the captured
@@ -1462,8 +1496,14 @@ sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_
     hdr->tiles_x = (in->width + kTileBatch - 1) / kTileBatch;
     hdr->tiles_y = (in->height + kTileBatch - 1) / kTileBatch;
     hdr->n_tile_ops = 0;
+    // the frustum-cell operations read cell depth ranges when every one of
+    // them has a packed keyframe
+    bool from_cells = true;
     for (int o = 0; o < n_ops; ++o)
-        if (ops[o].rec_mode != 2) hdr->tile_ops[hdr->n_tile_ops++] = (int16_t)o;
+        if (ops[o].rec_mode != 2) {
+            hdr->tile_ops[hdr->n_tile_ops++] = (int16_t)o;
+            from_cells = from_cells && ops[o].cells != nullptr;
+        }
     const size_t hdr_bytes = offsetof(BatchHdr, tile_ops) + sizeof(int16_t) * (size_t)std::max(hdr->n_tile_ops, 1);
     if (hipMemcpyAsync(vol->d_ops, ops, sizeof(OpDesc) * n_ops, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(vol->d_hdr, hdr, hdr_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -1471,8 +1511,9 @@ sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_
     // the staging buffer may be refilled once these copies have run
     const sc_status st = stage_end(vol, s);
     if (st != SC_OK) return st;
-    if (!vol->graph_pre) vol->graph_pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, cs); });
-    if (!vol->graph_pre || hipGraphLaunch(vol->graph_pre, s) != hipSuccess) return SC_EDEVICE;
+    hipGraphExec_t& pre = vol->graph_pre[from_cells ? 1 : 0];
+    if (!pre) pre = capture(vol, [&](hipStream_t cs) { launch_candidates(vol, from_cells, cs); });
+    if (!pre || hipGraphLaunch(pre, s) != hipSuccess) return SC_EDEVICE;
     return SC_OK;
 }
 
@@ -1487,8 +1528,8 @@ static sc_status run_chunk(sc_volume* vol, const OpDesc* ops, int n_ops, const s
     if (st != SC_OK) return st;
     bool packed = vol->p.color_mode == SC_COLOR_RGBA8;
     for (int i = 0; i < n_ops && packed; ++i) packed = ops[i].packed != nullptr;
-    hipGraphExec_t pre = nullptr, main = nullptr;
-    if (!graphs_for(vol, packed, pre, main)) return SC_EDEVICE;
+    hipGraphExec_t main = nullptr;
+    if (!graphs_for(vol, packed, main)) return SC_EDEVICE;
     const bool timed = vol->timing_n < vol->timing_cap;
     if (timed && hipEventRecord(vol->timing_ev[2 * vol->timing_n], s) != hipSuccess) return SC_EDEVICE;
     if (hipGraphLaunch(main, s) != hipSuccess) return SC_EDEVICE;

@@ -67,6 +67,7 @@ struct OpDesc {
     const float* depth;   // Z*, H x W
     const float* weight;  // W*, H x W
     const void* color;    // RGBA8 (uint32 per pixel) or float x 3
+    const float2* cells;  // with packed: {zmin, zmax} of the valid pixels of each 4 x 4 cell
     double R[9];          // camera -> world rotation, row-major
     double t[3];          // camera -> world translation
     float a[3][3];        // a[axis][row] = fl32(s * R[axis][row]): camera step of one voxel along a world axis
@@ -110,11 +111,19 @@ struct CandDev {
     uint32_t* counters;   // [0..1] list length (parity), [2..3] work cursor (parity),
                           // [4] batch candidates, [5] batch work cursor, [6] batch tile cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
+    uint32_t* cursors;    // kCursors work cursors of the batched passes, kCursorStride words apart
     unsigned long long* stats;  // cumulative: candidate blocks, (block, op) pairs, voxel updates, blocks written
     uint32_t mask_bits;   // cand buckets - 1
     uint32_t cap;         // list capacity (plain path)
     int32_t words;        // 64-bit mask words per bucket
 };
+
+// Work cursors of the batched passes: a device-wide atomic on one address is
+// serviced one at a time, so the items of a pass are split over kCursors
+// interleaved ranges, each with its own counter in its own 4 KB page.
+constexpr int kCursors = 32;
+constexpr int kCursorStride = 1024;  // 32-bit words
+constexpr int kCursorDone = 512;     // word of the bit mask of exhausted ranges (its own cache line)
 
 // Batched-update header in device memory, so a captured graph can be
 // replayed with a different number of operations.
@@ -144,14 +153,14 @@ struct sc_volume {
     hipStream_t cap_stream;  // private stream used for graph capture
     hipEvent_t staged[2];    // recorded after each staging buffer's descriptors were copied to the device
     int stage;               // staging buffer the next chunk fills
-    hipGraphExec_t graph_pre;   // captured candidate stage (init, candidates, histogram, scan, scatter)
+    hipGraphExec_t graph_pre[2];  // captured candidate stage (init, candidates, histogram, scan, scatter): pixels, cell ranges
     hipGraphExec_t graph_main[8]; // captured voxel pass per voxels-per-lane choice, unpacked / packed keyframes
     int graph_keys[8];       // schedule the voxel-pass graph of each slot was captured with
     hipEvent_t* timing_ev;   // optional per-launch event pairs (2 * timing_cap)
     int timing_cap, timing_n;
     sc_schedule sched;
     int n_cu;
-    int cand_wgs;            // resident workgroups per CU of the batched candidate kernel
+    int cand_wgs[2];         // resident workgroups per CU of the batched candidate kernel: pixels, cell ranges
     int plain_wgs;           // resident workgroups per CU of the plain update kernel
     double* adj_acc;         // device, 3 x kAdjChunk: pose terms of one backward chunk (zero between calls)
     struct RecordRegistry* rec;  // touched-block records of integrations (host index, device lists)

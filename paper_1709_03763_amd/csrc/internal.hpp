@@ -13,7 +13,7 @@ bool keyframe_ok(const sc_keyframe* kf);
 OpDesc* stage_begin(sc_volume* vol);
 BatchHdr* stage_hdr(sc_volume* vol);
 sc_status stage_end(sc_volume* vol, hipStream_t s);
-int cand_batch_resident_wgs();
+int cand_batch_resident_wgs(bool from_cells);
 sc_status run_candidates(sc_volume* vol, const OpDesc* ops, int n_ops, const sc_intrinsics* in, hipStream_t s);
 void rec_clear(sc_volume* vol);
 void rec_destroy(sc_volume* vol);

@@ -763,6 +763,55 @@ __device__ inline void insert_pixels(uint64_t* lds, const CandDev& cd, const Vol
         set_error(v.err, SC_ERANGE);
 }
 
+// The per-thread part of cand_tile (4 x 4 cells) for a packed keyframe: the
+// cell's depth range comes from the packed cell ranges, and a cell that is
+// not one frustum cell reads its 2 x 2 quads' depths from the packed records
+// (depth' is -inf where the quantised weight is zero, so 0 < depth' < 1e30
+// is the validity test of the pixel path).  The same decisions and inserts
+// as the pixel path, without the cell's 16 depths in registers.
+template <int SET>
+__device__ inline void cell_inserts_packed(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count,
+                                           int op_bit, uint64_t* lds, float ifx, float ify, float is, int u0, int v0)
+{
+    const int cw = (op.width + 3) >> 2, ch = (op.height + 3) >> 2;
+    const int cx = u0 >> 2, cy = v0 >> 2;
+    if (cx >= cw || cy >= ch) return;
+    const float2 r = op.cells[cy * cw + cx];
+    if (!(r.x <= r.y)) return;  // no valid pixel
+    if (r.y - r.x <= kCellSpread * v.mu &&
+        insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0, u0 + 3, v0, v0 + 3, r.x, r.y))
+        return;
+    const uint32_t* rec = reinterpret_cast<const uint32_t*>(op.packed);
+    for (int qd = 0; qd < 4; ++qd) {
+        const int qu = u0 + 2 * (qd & 1), qv = v0 + 2 * (qd >> 1);
+        float z[4];
+        uint32_t qvalid = 0u;
+        float qmin = 3.0e38f, qmax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = qu + (k & 1), vv = qv + (k >> 1);
+            z[k] = 0.0f;
+            if (u < op.width && vv < op.height) {
+                const float zz = __uint_as_float(rec[4 * ((size_t)vv * op.width + u)]);
+                if (zz > 0.0f && zz < 1.0e30f) {
+                    qvalid |= 1u << k;
+                    z[k] = zz;
+                    qmin = fminf(qmin, zz);
+                    qmax = fmaxf(qmax, zz);
+                }
+            }
+        }
+        if (!qvalid) continue;
+        if (qmax - qmin <= kQuadSpread * v.mu &&
+            insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu, qu + 1, qv, qv + 1, qmin, qmax))
+            continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((qvalid >> k) & 1u)
+                insert_pixels<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu + (k & 1), qv + (k >> 1), z[k]);
+    }
+}
+
 // Candidate generation for one TILE x TILE tile of one keyframe operation,
 // one CELL x CELL pixel cell per thread (CELL 2 or 4).  A cell whose valid
 // depths lie within kCellSpread mu of each other is treated as one frustum
@@ -774,7 +823,7 @@ __device__ inline void insert_pixels(uint64_t* lds, const CandDev& cd, const Vol
 // is set in the block's mask.  With count non-null, new candidates are also
 // appended to the candidate list (the plain path); the batched path finds
 // them by scanning the table instead.
-template <int TILE, int CELL>
+template <int TILE, int CELL, bool kFromCells = false>
 __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count, int tx,
                                  int ty, int op_bit, uint64_t* lds, uint16_t* idx)
 {
@@ -788,6 +837,9 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
     const int u0 = tx * TILE + CELL * (tid % kCells);
     const int v0 = ty * TILE + CELL * (tid / kCells);
     const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
+    if (kFromCells) {
+        cell_inserts_packed<kSet>(op, v, cd, count, op_bit, lds, ifx, ify, is, u0, v0);
+    } else {
     float zc[kPix];
     uint32_t valid = 0u;
     float zmin = 3.0e38f, zmax = 0.0f;
@@ -841,6 +893,7 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
                     insert_pixels<kSet>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0 + (q % CELL),
                                         v0 + (q / CELL), zc[q]);
         }
+    }
     }
     __syncthreads();
     // insert the tile's blocks: each wavefront first compacts the occupied

@@ -286,6 +286,30 @@ __global__ void pack_kernel(const float* depth, const float* weight, const uint3
     }
 }
 
+// Depth range {zmin, zmax} of the valid pixels (positive quantised weight,
+// 0 < depth < 1e30) of each 4 x 4 cell, {+inf, -inf} without one: the
+// candidate stage's per-cell test without reading the pixels.
+__global__ void pack_cells_kernel(const float* depth, const float* weight, float2* cells, int width, int height,
+                                  int cells_w, int64_t n_cells)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_cells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int cy = (int)(c / cells_w), cx = (int)(c - (int64_t)cy * cells_w);
+        float zmin = __builtin_inff(), zmax = -__builtin_inff();
+        for (int q = 0; q < 16; ++q) {
+            const int u = 4 * cx + (q & 3), v = 4 * cy + (q >> 2);
+            if (u >= width || v >= height) continue;
+            const int64_t pix = (int64_t)v * width + u;
+            const float z = depth[pix];
+            if (qweight(weight[pix]) > 0.0f && z > 0.0f && z < 1.0e30f) {
+                zmin = fminf(zmin, z);
+                zmax = fmaxf(zmax, z);
+            }
+        }
+        cells[c] = make_float2(zmin, zmax);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
@@ -298,6 +322,8 @@ void make_op(const sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* i
     op->weight = kf->weight;
     op->color = kf->color;
     op->packed = (vol->p.color_mode == SC_COLOR_RGBA8) ? reinterpret_cast<const uint4*>(kf->packed) : nullptr;
+    // the cell depth ranges follow the width x height records
+    op->cells = op->packed ? reinterpret_cast<const float2*>(op->packed + (size_t)in->width * in->height) : nullptr;
     op->width = in->width;
     op->height = in->height;
     op->fx = in->fx;
@@ -571,7 +597,8 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     vol->p = *p;
     vol->device = dev;
     vol->n_cu = prop.multiProcessorCount;
-    vol->cand_wgs = cand_batch_resident_wgs();
+    vol->cand_wgs[0] = cand_batch_resident_wgs(false);
+    vol->cand_wgs[1] = cand_batch_resident_wgs(true);
     {
         int n = 0;
         const hipError_t e = (p->color_mode == SC_COLOR_RGBA8)
@@ -613,6 +640,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.sslot, sizeof(int32_t) * cb) == hipSuccess;
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
+    ok &= hipMalloc(&c.cursors, sizeof(uint32_t) * kCursors * kCursorStride) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
     ok &= hipMalloc(&vol->adj_acc, sizeof(double) * 3 * kAdjChunk) == hipSuccess;
@@ -643,7 +671,8 @@ void sc_volume_destroy(sc_volume* vol)
 {
     if (!vol) return;
     hipDeviceSynchronize();
-    if (vol->graph_pre) hipGraphExecDestroy(vol->graph_pre);
+    for (hipGraphExec_t g : vol->graph_pre)
+        if (g) hipGraphExecDestroy(g);
     for (auto& g : vol->graph_main)
         if (g) hipGraphExecDestroy(g);
     for (int i = 0; i < 2 * vol->timing_cap; ++i) hipEventDestroy(vol->timing_ev[i]);
@@ -663,6 +692,7 @@ void sc_volume_destroy(sc_volume* vol)
     hipFree(vol->cand.sorted);
     hipFree(vol->cand.counters);
     hipFree(vol->cand.bins);
+    hipFree(vol->cand.cursors);
     hipFree(vol->d_ops);
     hipFree(vol->adj_acc);
     hipFree(vol->d_hdr);
@@ -690,6 +720,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u64(c.mask, 0ull, (size_t)vol->cand_buckets * c.words, s);
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
+    fill_u32(c.cursors, 0u, (size_t)kCursors * kCursorStride, s);
     fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
     fill_u64(reinterpret_cast<uint64_t*>(vol->adj_acc), 0ull, 3 * kAdjChunk, s);
     vol->parity = 0;
@@ -750,16 +781,30 @@ sc_status sc_volume_import(sc_volume* vol, void* stream, const int32_t* block_xy
     return sticky;
 }
 
-sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, void* stream)
+int64_t sc_keyframe_pack_bytes(int32_t width, int32_t height)
 {
-    if (!kf || !kf->depth || !kf->weight || !kf->color || !packed || ((uintptr_t)packed & 15u) || width <= 0 ||
-        height <= 0 || width > 16384 || height > 16384)
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384) return 0;
+    const int64_t cells = (int64_t)((width + 3) / 4) * ((height + 3) / 4);
+    return (int64_t)width * height * 16 + cells * 8;
+}
+
+sc_status sc_keyframe_pack(const sc_keyframe* kf, int32_t width, int32_t height, void* packed, int64_t packed_bytes,
+                           void* stream)
+{
+    const int64_t need = sc_keyframe_pack_bytes(width, height);
+    if (!kf || !kf->depth || !kf->weight || !kf->color || !packed || ((uintptr_t)packed & 15u) || need == 0 ||
+        packed_bytes < need)
         return SC_EINVAL;
     const int64_t n = (int64_t)width * height;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
     pack_kernel<<<grid, 256, 0, (hipStream_t)stream>>>(kf->depth, kf->weight,
                                                         reinterpret_cast<const uint32_t*>(kf->color),
                                                         reinterpret_cast<uint4*>(packed), n);
+    const int cells_w = (width + 3) / 4;
+    const int64_t n_cells = (int64_t)cells_w * ((height + 3) / 4);
+    pack_cells_kernel<<<(int)std::min<int64_t>((n_cells + 255) / 256, 65536), 256, 0, (hipStream_t)stream>>>(
+        kf->depth, kf->weight, reinterpret_cast<float2*>(reinterpret_cast<uint4*>(packed) + n), width, height, cells_w,
+        n_cells);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 

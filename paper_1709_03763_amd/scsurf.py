@@ -68,7 +68,7 @@ EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_res
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "sc_relative_motion", "reintegrate_batch",
            "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_autotune_clear", "sc_batch_timing", "sc_batch_timing_read",
-           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_overlap",
+           "sc_volume_stats", "tsdf_integrate_backward", "sc_keyframe_pack", "sc_keyframe_pack_bytes", "sc_overlap",
            "sc_volume_mesh", "sc_mesh_vertices", "sc_nn_distance", "sc_mesh_table",
            "sc_volume_import", "sc_stream_enable", "sc_stream_out", "sc_stream_in_all", "sc_stream_stats",
            "sc_stream_export"]
@@ -122,7 +122,9 @@ def lib():
     L.sc_batch_timing.argtypes = [P, i32]
     L.sc_batch_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
     L.sc_volume_stats.argtypes = [P, P, P]
-    L.sc_keyframe_pack.argtypes = [ctypes.POINTER(sc_keyframe), i32, i32, P, P]
+    L.sc_keyframe_pack.argtypes = [ctypes.POINTER(sc_keyframe), i32, i32, P, i64, P]
+    L.sc_keyframe_pack_bytes.argtypes = [i32, i32]
+    L.sc_keyframe_pack_bytes.restype = i64
     L.sc_overlap.argtypes = [P, ctypes.POINTER(sc_intrinsics), ctypes.POINTER(sc_pose), ctypes.POINTER(sc_pose),
                              ctypes.c_float, ctypes.c_float, P, P]
     L.sc_volume_mesh.argtypes = [P, P, P, P, i64, ctypes.POINTER(i64)]
@@ -225,6 +227,10 @@ class Keyframe:
             raise ValueError("keyframe colour must be uint8 (H, W, 4) or float32 (H, W, 3)")
         if self.packed is not None:
             _check_shape(self.packed, (H, W, 4), "packed keyframe")
+            # the cell depth ranges must follow the records in the same storage
+            have = self.packed.untyped_storage().nbytes() - 4 * self.packed.storage_offset()
+            if not self.packed.is_contiguous() or have < int(lib().sc_keyframe_pack_bytes(W, H)):
+                raise ValueError("packed keyframe: not a buffer written by keyframe_pack (cell ranges missing)")
         return H, W
 
     def c(self) -> sc_keyframe:
@@ -588,10 +594,14 @@ def keyframe_pack(kf: Keyframe, stream=None) -> Keyframe:
     H, W = kf.depth.shape
     if kf.color.dtype != torch.uint8 or tuple(kf.color.shape) != (H, W, 4):
         raise ValueError("keyframe_pack needs an RGBA8 keyframe")
-    packed = torch.empty((H, W, 4), dtype=torch.int32, device=kf.depth.device)
-    check(lib().sc_keyframe_pack(ctypes.byref(kf.c()), W, H, packed.data_ptr(), stream_handle(stream)),
+    nbytes = int(lib().sc_keyframe_pack_bytes(W, H))
+    if nbytes <= 0:
+        raise ValueError(f"keyframe size {W} x {H} outside 1 .. 16384")
+    buf = torch.empty(nbytes // 4, dtype=torch.int32, device=kf.depth.device)
+    check(lib().sc_keyframe_pack(ctypes.byref(kf.c()), W, H, buf.data_ptr(), nbytes, stream_handle(stream)),
           "sc_keyframe_pack")
-    return Keyframe(kf.depth, kf.weight, kf.color, packed)
+    # the records as an (H, W, 4) view; the cell ranges follow them in `buf`
+    return Keyframe(kf.depth, kf.weight, kf.color, buf[:H * W * 4].view(H, W, 4))
 
 
 def overlap(depth: torch.Tensor, intr, R, t, R_ref, t_ref, z_min=0.3, z_max=4.0, stream=None):

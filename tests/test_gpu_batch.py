@@ -158,8 +158,59 @@ def test_keyframe_pack_layout(scene):
     np.testing.assert_array_equal(rec[..., 0].view(np.float32), np.where(q > 0, kfs[0]["depth"], -np.inf))
     np.testing.assert_array_equal(rec[..., 2].view(np.uint32), kfs[0]["color"].view(np.uint32)[..., 0])
     assert not rec[..., 3].any()
+    _check_cells(kf, kfs[0])
     with pytest.raises(ValueError):
         scsurf.keyframe_pack(_dev_kf(as_f32_color(kfs[0]), f32=True))
+    # records without the cell ranges behind them are refused
+    short = scsurf.Keyframe(kf.depth, kf.weight, kf.color, kf.packed.clone())
+    with pytest.raises(ValueError):
+        short.image_size()
+
+
+def _check_cells(kf, ref):
+    """The cell depth ranges behind the packed records: min and max over the
+    valid pixels of each 4 x 4 cell (ragged border cells included)."""
+    H, W = ref["depth"].shape
+    n = scsurf.lib().sc_keyframe_pack_bytes(W, H) // 4
+    flat = kf.packed.as_strided((n,), (1,)).cpu().numpy()
+    ch, cw = (H + 3) // 4, (W + 3) // 4
+    cells = flat[H * W * 4:].view(np.float32).reshape(ch, cw, 2)
+    q = np.rint(ref["weight"] * np.float32(1024)) / np.float32(1024)
+    z = ref["depth"]
+    with np.errstate(invalid="ignore"):
+        ok = (q > 0) & (z > 0) & (z < np.float32(1e30))
+    zp = np.full((4 * ch, 4 * cw), np.nan, np.float32)
+    zp[:H, :W] = np.where(ok, z, np.nan)
+    blk = zp.reshape(ch, 4, cw, 4).transpose(0, 2, 1, 3).reshape(ch, cw, 16)
+    has = np.isfinite(blk).any(-1)
+    with np.errstate(all="ignore"):
+        lo = np.where(has, np.nanmin(np.where(has[..., None], blk, 0), -1), np.inf)
+        hi = np.where(has, np.nanmax(np.where(has[..., None], blk, 0), -1), -np.inf)
+    np.testing.assert_array_equal(cells[..., 0], lo.astype(np.float32))
+    np.testing.assert_array_equal(cells[..., 1], hi.astype(np.float32))
+
+
+def test_keyframe_pack_cells_ragged():
+    """Cell ranges of a ragged 83 x 641 keyframe holding zero, negative,
+    NaN, infinite and out-of-range depths and zero, tiny and NaN weights."""
+    rng = np.random.default_rng(3)
+    H, W = 83, 641
+    z = rng.uniform(0.3, 6.0, (H, W)).astype(np.float32)
+    w = rng.uniform(0.0, 2.0, (H, W)).astype(np.float32)
+    m = rng.random((H, W))
+    z[m < 0.05] = 0.0
+    z[(m >= 0.05) & (m < 0.08)] = -1.0
+    z[(m >= 0.08) & (m < 0.10)] = np.nan
+    z[(m >= 0.10) & (m < 0.12)] = np.inf
+    z[(m >= 0.12) & (m < 0.13)] = 2e30
+    w[(m >= 0.13) & (m < 0.20)] = 0.0
+    w[(m >= 0.20) & (m < 0.23)] = 1e-4  # quantises to zero
+    w[(m >= 0.23) & (m < 0.25)] = np.nan
+    z[:8, :8] = 0.0  # whole cells without a valid pixel
+    col = rng.integers(0, 256, (H, W, 4), dtype=np.uint8)
+    ref = {"depth": z, "weight": w, "color": col}
+    kf = scsurf.keyframe_pack(_dev_kf(ref))
+    _check_cells(kf, ref)
 
 
 @pytest.mark.parametrize("sched", [(8, 4, 4), (8, 2, 8, 1), (8, 2, 8, 3), (8, 2, 8, 4), (8, 4, 4, 4), (4, 2, 8)])
@@ -173,6 +224,7 @@ def test_packed_keyframes_give_identical_bits(scene, sched):
     vol.set_schedule(*sched)
     vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
     plain = vol.export_sorted()
+    counts = vol.stats()
     vol.close()
     pks = [scsurf.keyframe_pack(k) for k in dks]
     for fn in ("reintegrate_batch", "reintegrate_plain"):
@@ -185,6 +237,9 @@ def test_packed_keyframes_give_identical_bits(scene, sched):
         got = volp.export_sorted()
         for key in ("blocks", "D", "W", "C"):
             np.testing.assert_array_equal(got[key], plain[key])
+        if fn == "reintegrate_batch":
+            # the candidate stage reads the cell ranges: the same candidates
+            assert volp.stats() == counts
         volp.close()
 
 

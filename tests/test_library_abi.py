@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "scsurf.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:sc_status|int32_t|void|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:sc_status|int32_t|int64_t|void|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_library_loads_and_exports_every_declared_symbol():
@@ -92,3 +92,14 @@ def test_library_relative_motion():
         a = scsurf.relative_motion(wl.R[f], wl.t[f], wl.R[f + 9], wl.t[f + 9])
         b = strategies.relative_motion(wl.R[f], wl.t[f], wl.R[f + 9], wl.t[f + 9])
         np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+def test_keyframe_pack_bytes():
+    """Records (16 bytes a pixel) followed by one {zmin, zmax} pair per 4 x 4
+    cell; 0 outside 1 .. 16384."""
+    L = scsurf.lib()
+    assert L.sc_keyframe_pack_bytes(640, 480) == 640 * 480 * 16 + 160 * 120 * 8
+    assert L.sc_keyframe_pack_bytes(641, 83) == 641 * 83 * 16 + 161 * 21 * 8
+    assert L.sc_keyframe_pack_bytes(1, 1) == 16 + 8
+    for w, h in [(0, 10), (10, 0), (-1, 5), (16385, 2), (2, 16385)]:
+        assert L.sc_keyframe_pack_bytes(w, h) == 0
