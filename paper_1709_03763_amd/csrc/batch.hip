@@ -1161,7 +1161,7 @@ __device__ inline bool ring_step(const OpDesc* __restrict__ ops, const VolDev& v
 // wavefront.  kPacked: every
 // operation's keyframe carries its packed copy (RGBA8 volumes).
 template <int CM, bool kPacked>
-__global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_ring_kernel(const OpDesc* __restrict__ ops, VolDev v, CandDev cd)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -1185,36 +1185,58 @@ __global__ __launch_bounds__(256) void batch_ring_kernel(const OpDesc* __restric
         pb.re_touch = pb.e_na = pb.e_w = false;
         pb.n_rec = 0u;
         pb.rec_op = 0;
-        {
-            const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
-            const bool have = pb.slot >= 0;
+        // the operation mask first, then the block state into registers;
+        // the first operation's gathers are issued before the state goes to
+        // LDS, so the two round trips overlap
+        LaneWalk walk;
+        lanewalk_init(walk, cd.mask + (size_t)h * cd.words, cd.words, lane);
+        const float* blk = v.pool + (size_t)max(pb.slot, 0) * v.stride;
+        const bool have = pb.slot >= 0;
+        double rD[8];
+        float rW[8];
+        uint32_t rC[8];
+        if (CM == SC_COLOR_RGBA8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                rD[j] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
+                rW[j] = have ? blk[kPoolW + x] : 0.0f;
+                rC[j] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
+            }
+        } else {
+            // FP32 colour: 24 bytes of colour per voxel, written to LDS as read
 #pragma unroll 4
             for (int j = 0; j < 8; ++j) {
                 const int x = lane + 64 * j;
                 L.sD[x] = have ? reinterpret_cast<const double*>(blk)[x] : 0.0;
                 L.sW[x] = have ? blk[kPoolW + x] : 0.0f;
-                if (CM == SC_COLOR_RGBA8) {
-                    L.sC[x] = have ? reinterpret_cast<const uint32_t*>(blk + kPoolC)[x] : 0u;
-                } else {
-                    const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
-                    L.sCf[x] = have ? Cd[x] : 0.0;
-                    L.sCf[512 + x] = have ? Cd[512 + x] : 0.0;
-                    L.sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
-                }
+                const double* Cd = reinterpret_cast<const double*>(blk + kPoolC);
+                L.sCf[x] = have ? Cd[x] : 0.0;
+                L.sCf[512 + x] = have ? Cd[512 + x] : 0.0;
+                L.sCf[1024 + x] = have ? Cd[1024 + x] : 0.0;
+            }
+        }
+        int op_c = lanewalk_next(walk);
+        RingFetch<CM> f0, f1;
+        RingGeom gc;
+        if (op_c >= 0) {
+            ring_geom(ops[op_c], v, pb, lane, gc);
+            ring_fetch<CM, kPacked>(ops[op_c], gc, 0, f0);
+        }
+        if (CM == SC_COLOR_RGBA8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x = lane + 64 * j;
+                L.sD[x] = rD[j];
+                L.sW[x] = rW[j];
+                L.sC[x] = rC[j];
             }
         }
         wave_lds_sync();
-        LaneWalk walk;
-        lanewalk_init(walk, cd.mask + (size_t)h * cd.words, cd.words, lane);
-        int op_c = lanewalk_next(walk);
         if (op_c >= 0) {
-            RingFetch<CM> f0, f1;
-            RingGeom gc;
             Ring ring;
             ring.head = ring.tail = 0u;
             int part_c = 0;
-            ring_geom(ops[op_c], v, pb, lane, gc);
-            ring_fetch<CM, kPacked>(ops[op_c], gc, 0, f0);
             for (;;) {
                 if (!ring_step<CM, kPacked>(ops, v, walk, pb, f0, f1, gc, op_c, part_c, lane, L, ring)) break;
                 if (!ring_step<CM, kPacked>(ops, v, walk, pb, f1, f0, gc, op_c, part_c, lane, L, ring)) break;
