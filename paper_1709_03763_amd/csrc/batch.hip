@@ -37,8 +37,8 @@ namespace sc {
 __global__ void batch_init_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr, CandDev cd, int n_bins)
 {
     for (int i = threadIdx.x; i < 8; i += blockDim.x) cd.counters[4 + i] = 0u;
-    for (int i = threadIdx.x; i < kCursors; i += blockDim.x) cd.cursors[i * kCursorStride] = 0u;
-    if (threadIdx.x == 0) cd.cursors[kCursorDone] = 0u;
+    for (int i = threadIdx.x; i < 2 * kCursors; i += blockDim.x) cd.cursors[i * kCursorStride] = 0u;
+    if (threadIdx.x < 2) cd.cursors[threadIdx.x * kCursorSet + kCursorDone] = 0u;
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) cd.bins[i] = 0u;
     // integrations that record their touched blocks start an empty record
     for (int o = threadIdx.x; o < hdr->n_ops; o += blockDim.x)
@@ -1170,11 +1170,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const uint32_t n = cd.counters[4];
     const uint32_t worker = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave;
     const uint32_t n_workers = gridDim.x * (blockDim.x >> 6);
-    WorkCursor cur;
-    cursor_init(cur, worker);
+    RangeCursor cur;
+    range_init(cur, worker);
+    uint32_t* const cursors = cd.cursors + kCursorSet;  // the voxel pass's set
     uint32_t n_upd = 0, n_pairs = 0, n_written = 0;
     for (;;) {
-        const uint32_t i = cursor_pop(cur, cd.counters + 5, n_workers, lane);
+        const uint32_t i = range_pop(cur, cursors, n, n_workers, lane);
         if (i >= n) break;
         const uint32_t h = bcast(cd.sorted[i]);
         const uint64_t key = bcast64(cd.skey[i]);

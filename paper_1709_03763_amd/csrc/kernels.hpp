@@ -99,6 +99,59 @@ __device__ inline uint32_t cursor_pop(WorkCursor& c, uint32_t* ctr, uint32_t n_w
     return c.next++;
 }
 
+// The same distribution over kCursors interleaved ranges (item i in range
+// i mod kCursors, each range with its own counter in its own page), so that
+// the claims of many wavefronts do not queue on one address: worker w takes
+// item w first, then claims from its range (single items through the heavy
+// front, kRangePop after it); a worker that finds its range exhausted marks
+// it in a shared bit mask and moves on to a range not yet marked.  Returns
+// n when every range is exhausted.  Used in uniform control flow only.
+static_assert(kCursors == 32, "the exhausted-range mask is one 32-bit word");
+constexpr uint32_t kRangePop = 8;  // items per claim past the heavy front
+
+struct RangeCursor {
+    uint32_t next, end;  // indices [next, end) within range r held
+    int r;
+};
+
+__device__ inline void range_init(RangeCursor& c, uint32_t worker)
+{
+    c.r = (int)(worker % kCursors);
+    c.next = worker / kCursors;
+    c.end = c.next + 1u;
+}
+
+__device__ inline uint32_t range_pop(RangeCursor& c, uint32_t* cursors, uint32_t n, uint32_t n_workers, int lane)
+{
+    for (;;) {
+        // indices below `base` of range r are the workers' static first items
+        const uint32_t base = (n_workers + kCursors - 1u - (uint32_t)c.r) / kCursors;
+        if (c.next >= c.end) {
+            const uint32_t k = (c.end < 2u * base) ? 1u : kRangePop;
+            c.next = base + bcast(atomicAdd(cursors + c.r * kCursorStride, lane == 0 ? k : 0u));
+            c.end = c.next + k;
+        }
+        const uint32_t item = (uint32_t)c.r + kCursors * c.next;
+        if (item < n) {
+            c.next++;
+            return item;
+        }
+        const uint32_t m =
+            bcast(atomicOr(cursors + kCursorDone, lane == 0 ? (1u << c.r) : 0u)) | (1u << c.r);
+        if (m == ~0u) return n;
+        int nr = c.r;
+        for (int j = 1; j < kCursors; ++j) {
+            const int q = (c.r + j) % kCursors;
+            if (!((m >> q) & 1u)) {
+                nr = q;
+                break;
+            }
+        }
+        c.r = nr;
+        c.next = c.end = 0u;
+    }
+}
+
 // Per-pass statistics are added into kStatSlots slots per counter so that the
 // workers' final atomics do not all meet on one address.
 constexpr int kStatSlots = 64;

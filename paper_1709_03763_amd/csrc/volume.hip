@@ -640,7 +640,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.sslot, sizeof(int32_t) * cb) == hipSuccess;
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
-    ok &= hipMalloc(&c.cursors, sizeof(uint32_t) * kCursors * kCursorStride) == hipSuccess;
+    ok &= hipMalloc(&c.cursors, sizeof(uint32_t) * 2 * kCursorSet) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
     ok &= hipMalloc(&vol->adj_acc, sizeof(double) * 3 * kAdjChunk) == hipSuccess;
@@ -720,7 +720,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u64(c.mask, 0ull, (size_t)vol->cand_buckets * c.words, s);
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
-    fill_u32(c.cursors, 0u, (size_t)kCursors * kCursorStride, s);
+    fill_u32(c.cursors, 0u, (size_t)2 * kCursorSet, s);
     fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
     fill_u64(reinterpret_cast<uint64_t*>(vol->adj_acc), 0ull, 3 * kAdjChunk, s);
     vol->parity = 0;
