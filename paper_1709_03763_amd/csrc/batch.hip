@@ -39,6 +39,7 @@ __global__ void batch_init_kernel(const OpDesc* __restrict__ ops, const BatchHdr
     for (int i = threadIdx.x; i < 8; i += blockDim.x) cd.counters[4 + i] = 0u;
     for (int i = threadIdx.x; i < 2 * kCursors; i += blockDim.x) cd.cursors[i * kCursorStride] = 0u;
     if (threadIdx.x < 2) cd.cursors[threadIdx.x * kCursorSet + kCursorDone] = 0u;
+    if (threadIdx.x == 0) cd.big[0] = 0u;
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) cd.bins[i] = 0u;
     // integrations that record their touched blocks start an empty record
     for (int o = threadIdx.x; o < hdr->n_ops; o += blockDim.x)
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
 {
     __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
     __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    __shared__ float red[8];
     __shared__ int next;
     const int tiles = hdr->tiles_x * hdr->tiles_y;
     const int items = hdr->n_tile_ops * tiles;
@@ -145,9 +147,44 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
         const int tile = it - kk * tiles;
         const int ty = tile / hdr->tiles_x;
         const int tx = tile - ty * hdr->tiles_x;
-        cand_tile<kTileBatch, kCellBatch, kFromCells>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
+        if (kFromCells) {
+            // packed keyframes: the tile's bit map; a tile whose box is too
+            // large is listed for cand_big_kernel (the hash set)
+            if (!cand_tile_bits<kTileBatch>(ops[o], v, cd, tx, ty, o, reinterpret_cast<uint32_t*>(lds), idx, red) &&
+                threadIdx.x == 0) {
+                const uint32_t pos = atomicAdd(cd.big, 1u);
+                if (pos < (uint32_t)kBigCap) cd.big[1 + pos] = (uint32_t)it;
+            }
+        } else {
+            cand_tile<kTileBatch, kCellBatch, false>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
+        }
         __syncthreads();
         ++k;
+    }
+}
+
+// The tiles of packed keyframes whose block box exceeds the bit map, on the
+// LDS hash set: the listed items, or every item when the list overflowed
+// (inserting a tile's candidates twice changes nothing).
+__global__ __launch_bounds__(256) void cand_big_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr, VolDev v,
+                                                       CandDev cd)
+{
+    __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
+    const int tiles = hdr->tiles_x * hdr->tiles_y;
+    const int items = hdr->n_tile_ops * tiles;
+    const uint32_t nb = cd.big[0];
+    const bool all = nb > (uint32_t)kBigCap;
+    const int count = all ? items : (int)nb;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const int it = all ? k : (int)cd.big[1 + k];
+        const int kk = it / tiles;
+        const int o = hdr->tile_ops[kk];
+        const int tile = it - kk * tiles;
+        const int ty = tile / hdr->tiles_x;
+        const int tx = tile - ty * hdr->tiles_x;
+        cand_tile<kTileBatch, kCellBatch, true>(ops[o], v, cd, nullptr, tx, ty, o, lds, idx);
+        __syncthreads();
     }
 }
 
@@ -1372,10 +1409,11 @@ static void launch_candidates(sc_volume* vol, bool from_cells, hipStream_t s)
     const int n_bins = vol->p.max_batch_ops + 1;
     batch_init_kernel<<<1, 1024, 0, s>>>(vol->d_ops, vol->d_hdr, vol->cand, n_bins);
     const int threads = CandCfg<kTileBatch, kCellBatch>::threads;
-    if (from_cells)
+    if (from_cells) {
         cand_batch_kernel<true><<<vol->n_cu * vol->cand_wgs[1], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
                                                                                  vol->cand);
-    else
+        cand_big_kernel<<<vol->n_cu, threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev, vol->cand);
+    } else
         cand_batch_kernel<false><<<vol->n_cu * vol->cand_wgs[0], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
                                                                                   vol->cand);
     cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(vol->d_ops, vol->d_hdr,

@@ -112,6 +112,7 @@ struct CandDev {
                           // [4] batch candidates, [5] batch work cursor, [6] batch tile cursor
     uint32_t* bins;       // per-operation-count histogram / offsets (batched path)
     uint32_t* cursors;    // two sets (candidate stage, voxel pass) of kCursors work cursors, kCursorStride words apart
+    uint32_t* big;        // [0] tiles whose block box exceeds the bit map, then up to kBigCap of their items
     unsigned long long* stats;  // cumulative: candidate blocks, (block, op) pairs, voxel updates, blocks written
     uint32_t mask_bits;   // cand buckets - 1
     uint32_t cap;         // list capacity (plain path)
@@ -125,6 +126,7 @@ constexpr int kCursors = 32;
 constexpr int kCursorStride = 1024;  // 32-bit words
 constexpr int kCursorDone = 512;     // word of the bit mask of exhausted ranges (its own cache line)
 constexpr int kCursorSet = kCursors * kCursorStride;  // words per set
+constexpr int kBigCap = 16384;  // listed tiles with an oversized block box (beyond: every tile is redone)
 
 // Batched-update header in device memory, so a captured graph can be
 // replayed with a different number of operations.

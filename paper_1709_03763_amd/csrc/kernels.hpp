@@ -820,20 +820,19 @@ __device__ inline void insert_pixels(uint64_t* lds, const CandDev& cd, const Vol
 // cell's depth range comes from the packed cell ranges, and a cell that is
 // not one frustum cell reads its 2 x 2 quads' depths from the packed records
 // (depth' is -inf where the quantised weight is zero, so 0 < depth' < 1e30
-// is the validity test of the pixel path).  The same decisions and inserts
-// as the pixel path, without the cell's 16 depths in registers.
-template <int SET>
-__device__ inline void cell_inserts_packed(const OpDesc& op, const VolDev& v, const CandDev& cd, uint32_t* count,
-                                           int op_bit, uint64_t* lds, float ifx, float ify, float is, int u0, int v0)
+// is the validity test of the pixel path).  The same decisions and boxes as
+// the pixel path, without the cell's 16 depths in registers.  `ins.cell`
+// inserts the blocks of one frustum cell's box (false: the box is out of
+// range, nothing inserted).
+template <class Ins>
+__device__ inline void cell_inserts_packed(const OpDesc& op, const VolDev& v, Ins& ins, int u0, int v0)
 {
     const int cw = (op.width + 3) >> 2, ch = (op.height + 3) >> 2;
     const int cx = u0 >> 2, cy = v0 >> 2;
     if (cx >= cw || cy >= ch) return;
     const float2 r = op.cells[cy * cw + cx];
     if (!(r.x <= r.y)) return;  // no valid pixel
-    if (r.y - r.x <= kCellSpread * v.mu &&
-        insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0, u0 + 3, v0, v0 + 3, r.x, r.y))
-        return;
+    if (r.y - r.x <= kCellSpread * v.mu && ins.cell(u0, u0 + 3, v0, v0 + 3, r.x, r.y)) return;
     const uint32_t* rec = reinterpret_cast<const uint32_t*>(op.packed);
     for (int qd = 0; qd < 4; ++qd) {
         const int qu = u0 + 2 * (qd & 1), qv = v0 + 2 * (qd >> 1);
@@ -855,14 +854,216 @@ __device__ inline void cell_inserts_packed(const OpDesc& op, const VolDev& v, co
             }
         }
         if (!qvalid) continue;
-        if (qmax - qmin <= kQuadSpread * v.mu &&
-            insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu, qu + 1, qv, qv + 1, qmin, qmax))
-            continue;
+        if (qmax - qmin <= kQuadSpread * v.mu && ins.cell(qu, qu + 1, qv, qv + 1, qmin, qmax)) continue;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if ((qvalid >> k) & 1u)
-                insert_pixels<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, qu + (k & 1), qv + (k >> 1), z[k]);
+            if ((qvalid >> k) & 1u) {
+                const int u = qu + (k & 1), vv = qv + (k >> 1);
+                if (!ins.cell(u, u, vv, vv, z[k], z[k])) set_error(v.err, SC_ERANGE);
+            }
     }
+}
+
+// Box inserter of the LDS hash set (insert_cell).
+template <int SET>
+struct HashIns {
+    uint64_t* lds;
+    const CandDev& cd;
+    const VolDev& v;
+    uint32_t* count;
+    int op_bit;
+    const OpDesc& op;
+    float ifx, ify, is;
+    __device__ bool cell(int u0, int u1, int v0, int v1, float zlo, float zhi)
+    {
+        return insert_cell<SET>(lds, cd, v, count, op_bit, op, ifx, ify, is, u0, u1, v0, v1, zlo, zhi);
+    }
+};
+
+// Candidate tiles of packed keyframes on an LDS bit map over the tile's block
+// box: the box of the whole tile's frustum (its pixels between the smallest
+// depth less mu and the largest plus mu) contains every frustum cell's box,
+// so a cell's blocks are bits of a bit map over it, set a z-run at a time
+// (one or two LDS ORs instead of one probed insert per block); the set bits
+// are then claimed in the global candidate table.  A tile whose box exceeds
+// kTileBits blocks takes the LDS hash set.
+constexpr int kTileBits = 65536;  // 8 KB
+
+// The tile's block box: as cell_block_range without its size limit, widened
+// by one block on every side (so that the cells' own FP32 boxes, padded the
+// same way, lie inside it); false if it leaves the key range or exceeds
+// kTileBits blocks.
+__device__ inline bool tile_block_box(const OpDesc& op, float is, const CellGeom& c, int lo[3], int n[3])
+{
+    float mn[3], mx[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        mn[r] = 3.0e38f;
+        mx[r] = -3.0e38f;
+    }
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz) {
+        const float zz = iz ? c.zh : c.zl;
+        const float cxm = c.xm * zz, hx = c.hx * zz;
+        const float cym = c.ym * zz, hy = c.hy * zz;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float r0 = (float)op.R[3 * r + 0], r1 = (float)op.R[3 * r + 1], r2 = (float)op.R[3 * r + 2];
+            const float cc = r0 * cxm + r1 * cym + r2 * zz + (float)op.t[r];
+            const float e = fabsf(r0) * hx + fabsf(r1) * hy;
+            mn[r] = fminf(mn[r], cc - e);
+            mx[r] = fmaxf(mx[r], cc + e);
+        }
+    }
+    bool ok = true;
+    int vol = 1;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float pad = 2e-3f + 2e-5f * fmaxf(fabsf(mn[r]), fabsf(mx[r]));
+        const float flo = ceilf((mn[r] - pad) * is);
+        const float fhi = floorf((mx[r] + pad) * is);
+        ok = ok && (flo > -8.0e6f) && (fhi < 8.0e6f) && (fhi - flo < 8.0f * 1024.0f);
+        lo[r] = ok ? ((int)flo >> 3) - 1 : 0;
+        n[r] = ok ? ((int)fhi >> 3) + 1 - lo[r] + 1 : 1;
+        vol *= n[r];
+    }
+    return ok && vol <= kTileBits;
+}
+
+// Box inserter of the bit map: a cell box inside the tile box sets its
+// z-runs; one outside it (not expected: the tile box is a block wider) goes
+// block by block to the global table.
+struct BitIns {
+    uint32_t* bits;
+    const CandDev& cd;
+    const VolDev& v;
+    int op_bit;
+    const OpDesc& op;
+    float ifx, ify, is;
+    int tlo[3], tn[3];
+    __device__ bool cell(int u0, int u1, int v0, int v1, float zlo, float zhi)
+    {
+        const CellGeom c = cell_geom(op, ifx, ify, v.mu, u0, u1, v0, v1, zlo, zhi);
+        int lo[3], hi[3];
+        if (!cell_block_range(op, is, c, lo, hi)) return false;
+        bool inside = true;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) inside = inside && lo[r] >= tlo[r] && hi[r] < tlo[r] + tn[r];
+        if (!inside) {
+            for (int bx = lo[0]; bx <= hi[0]; ++bx)
+                for (int by = lo[1]; by <= hi[1]; ++by)
+                    for (int bz = lo[2]; bz <= hi[2]; ++bz) {
+                        const int gb = cand_insert(cd, v, pack_key(bx, by, bz), bx, by, bz, nullptr);
+                        if (gb >= 0) cand_mark(cd, gb, op_bit);
+                    }
+            return true;
+        }
+        const int run = hi[2] - lo[2] + 1;  // at most 16 blocks
+        const uint32_t m = (run >= 32) ? ~0u : ((1u << run) - 1u);
+        for (int bx = lo[0]; bx <= hi[0]; ++bx)
+            for (int by = lo[1]; by <= hi[1]; ++by) {
+                const int first = ((bx - tlo[0]) * tn[1] + (by - tlo[1])) * tn[2] + (lo[2] - tlo[2]);
+                const int w = first >> 5, b = first & 31;
+                atomicOr(bits + w, m << b);
+                if (b + run > 32) atomicOr(bits + w + 1, m >> (32 - b));
+            }
+        return true;
+    }
+};
+
+// Bit-map candidate generation for one TILE x TILE tile of a packed keyframe
+// (4 x 4 cells); returns false when the tile's box is too large (nothing
+// done: the caller takes the hash set).  `red` holds 8 floats of LDS.
+template <int TILE>
+__device__ inline bool cand_tile_bits(const OpDesc& op, const VolDev& v, const CandDev& cd, int tx, int ty, int op_bit,
+                                      uint32_t* bits, uint16_t* idx, float* red)
+{
+    constexpr int kCells = TILE / 4;
+    constexpr int kThreads = kCells * kCells;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int u0 = tx * TILE + 4 * (tid % kCells);
+    const int v0 = ty * TILE + 4 * (tid / kCells);
+    const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
+    // the tile's depth range from its cells' ranges
+    const int cw = (op.width + 3) >> 2, ch = (op.height + 3) >> 2;
+    const int cx = u0 >> 2, cy = v0 >> 2;
+    const float2 r = (cx < cw && cy < ch) ? op.cells[cy * cw + cx] : make_float2(1.0f, 0.0f);
+    const bool any = r.x <= r.y;
+    float zlo = any ? r.x : 3.0e38f, zhi = any ? r.y : 0.0f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        zlo = fminf(zlo, __shfl_xor(zlo, o));
+        zhi = fmaxf(zhi, __shfl_xor(zhi, o));
+    }
+    if (lane == 0) {
+        red[2 * wave] = zlo;
+        red[2 * wave + 1] = zhi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        zlo = fminf(zlo, red[2 * w]);
+        zhi = fmaxf(zhi, red[2 * w + 1]);
+    }
+    if (!(zlo <= zhi)) return true;  // no valid pixel in the tile
+    // the whole tile's pixel rectangle (cells at a ragged border reach past
+    // the image just as far)
+    const CellGeom tg =
+        cell_geom(op, ifx, ify, v.mu, tx * TILE, tx * TILE + TILE - 1, ty * TILE, ty * TILE + TILE - 1, zlo, zhi);
+    BitIns ins{bits, cd, v, op_bit, op, ifx, ify, is, {0, 0, 0}, {1, 1, 1}};
+    if (!tile_block_box(op, is, tg, ins.tlo, ins.tn)) return false;
+    const int nw = (ins.tn[0] * ins.tn[1] * ins.tn[2] + 31) >> 5;
+    for (int w = tid; w < nw; w += kThreads) bits[w] = 0u;
+    __syncthreads();
+    cell_inserts_packed(op, v, ins, u0, v0);
+    __syncthreads();
+    // claims: each wavefront compacts the set bits of 16 words at a time into
+    // its index list (at most 512 entries) and claims the list 64 at a time
+    uint16_t* wl = idx + wave * 512;
+    const int nyz = ins.tn[1] * ins.tn[2];
+    int n = 0;
+    auto claim = [&](int cnt) {
+        for (int r0 = 0; r0 < cnt; r0 += 64) {
+            const int q = r0 + lane;
+            if (q < cnt) {
+                const int e = wl[q];
+                const int bx = ins.tlo[0] + e / nyz;
+                const int rem = e - (e / nyz) * nyz;
+                const int by = ins.tlo[1] + rem / ins.tn[2];
+                const int bz = ins.tlo[2] + rem - (rem / ins.tn[2]) * ins.tn[2];
+                bool fresh;
+                const int gb = cand_claim(cd, v, pack_key(bx, by, bz), bx, by, bz, fresh);
+                if (gb >= 0) cand_mark(cd, gb, op_bit);
+            }
+        }
+        wave_lds_sync();
+    };
+    for (int base = wave * 16; base < nw; base += 16 * (kThreads / 64)) {
+        const int w = base + lane;
+        uint32_t m = (lane < 16 && w < nw) ? bits[w] : 0u;
+        const uint32_t c = (uint32_t)__popc(m);
+        uint32_t pre = c;  // inclusive prefix over the lanes
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(pre, o);
+            pre += (lane >= o) ? y : 0u;
+        }
+        const int total = (int)__shfl(pre, 63);
+        if (n + total > 512) {
+            claim(n);
+            n = 0;
+        }
+        int pos = n + (int)(pre - c);
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            wl[pos++] = (uint16_t)(w * 32 + b);
+        }
+        n += total;
+        wave_lds_sync();
+    }
+    claim(n);
+    return true;
 }
 
 // Candidate generation for one TILE x TILE tile of one keyframe operation,
@@ -891,7 +1092,8 @@ __device__ inline void cand_tile(const OpDesc& op, const VolDev& v, const CandDe
     const int v0 = ty * TILE + CELL * (tid / kCells);
     const float ifx = 1.0f / op.fx, ify = 1.0f / op.fy, is = 1.0f / v.s;
     if (kFromCells) {
-        cell_inserts_packed<kSet>(op, v, cd, count, op_bit, lds, ifx, ify, is, u0, v0);
+        HashIns<kSet> ins{lds, cd, v, count, op_bit, op, ifx, ify, is};
+        cell_inserts_packed(op, v, ins, u0, v0);
     } else {
     float zc[kPix];
     uint32_t valid = 0u;

@@ -641,6 +641,7 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
     ok &= hipMalloc(&c.counters, 64 * sizeof(uint32_t)) == hipSuccess;
     ok &= hipMalloc(&c.bins, sizeof(uint32_t) * (kMaxBatchOps + 2)) == hipSuccess;
     ok &= hipMalloc(&c.cursors, sizeof(uint32_t) * 2 * kCursorSet) == hipSuccess;
+    ok &= hipMalloc(&c.big, sizeof(uint32_t) * (kBigCap + 1)) == hipSuccess;
     ok &= hipMalloc(&c.stats, sizeof(unsigned long long) * 4 * kStatSlots) == hipSuccess;
     ok &= hipMalloc(&vol->d_ops, sizeof(OpDesc) * p->max_batch_ops) == hipSuccess;
     ok &= hipMalloc(&vol->adj_acc, sizeof(double) * 3 * kAdjChunk) == hipSuccess;
@@ -693,6 +694,7 @@ void sc_volume_destroy(sc_volume* vol)
     hipFree(vol->cand.counters);
     hipFree(vol->cand.bins);
     hipFree(vol->cand.cursors);
+    hipFree(vol->cand.big);
     hipFree(vol->d_ops);
     hipFree(vol->adj_acc);
     hipFree(vol->d_hdr);
@@ -721,6 +723,7 @@ sc_status sc_volume_reset(sc_volume* vol, void* stream)
     fill_u32(c.counters, 0u, 64, s);
     fill_u32(c.bins, 0u, kMaxBatchOps + 2, s);
     fill_u32(c.cursors, 0u, (size_t)2 * kCursorSet, s);
+    fill_u32(c.big, 0u, 1, s);
     fill_u64(reinterpret_cast<uint64_t*>(c.stats), 0ull, 4 * kStatSlots, s);
     fill_u64(reinterpret_cast<uint64_t*>(vol->adj_acc), 0ull, 3 * kAdjChunk, s);
     vol->parity = 0;

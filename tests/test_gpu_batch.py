@@ -243,6 +243,42 @@ def test_packed_keyframes_give_identical_bits(scene, sched):
         volp.close()
 
 
+def test_oversized_tile_boxes_take_the_hash_set(scene):
+    """Keyframes whose 64 x 64 tiles mix near and far depths (one 4-pixel
+    column group in four pushed to 10 m): their tiles' block boxes exceed the
+    bit map, so the candidate stage lists them for the hash-set kernel.  The
+    packed path must give the unpacked path's candidates and field bit for
+    bit, and the oracle's field."""
+    wl, kfs, R, t = scene
+    odd = []
+    for k in range(2):
+        kf = dict(kfs[k])
+        z = kf["depth"].copy()
+        cols = (np.arange(z.shape[1]) // 4) % 4 == 1
+        z[:, cols] = np.where(kf["weight"][:, cols] > 0, np.float32(10.0), z[:, cols])
+        kf["depth"] = z
+        odd.append(kf)
+    Rk, tk = R[:2], t[:2]
+    Rn, tn = synth.perturb_all(Rk, tk, 0.02, 0.3, 12)
+    _say("oversized tile boxes")
+    results = []
+    for packed in (False, True):
+        vol, ref, dks, okf = _integrated(wl, odd, Rk, tk)
+        if packed:
+            dks = [scsurf.keyframe_pack(k) for k in dks]
+        vol.set_schedule(8, 2, 8, 4)
+        order, _ = vol.reintegrate_batch(dks, wl.intr, (Rk, tk), (Rn, tn), 2, scsurf.SEL_ALL_ORDERED)
+        vol.check_error()
+        results.append((vol.export_sorted(), vol.stats()))
+        if packed:
+            _oracle_update(ref, okf, wl, Rk, tk, Rn, tn, order)
+            compare_fields(results[-1][0], ref.export())
+        vol.close()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(results[0][0][key], results[1][0][key])
+    assert results[0][1] == results[1][1]
+
+
 def test_schedule_validation(scene):
     vol = scsurf.Volume(S, MU, 1 << 10, 1 << 8, color_mode=scsurf.COLOR_F32)
     for bad in [(3, 4, 4), (8, 4, 0), (8, 4, 33), (4, 2, 8, 1), (8, 3, 4, 1), (8, 4, 4, 1), (8, 4, 4, 4), (8, 2, 4, 5),
