@@ -115,6 +115,8 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
     int r = (int)blockIdx.x % kCursors;
     int k = (int)blockIdx.x / kCursors, end = k + 1;  // index within range r
     for (;;) {
+        // with no more items than workgroups every item is a static one
+        if (k >= end && items <= (int)gridDim.x) break;
         if (k >= end) {
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(256) void cand_batch_kernel(const OpDesc* __restric
             end = k + kCandPop;
         }
         const int it = r + kCursors * k;
+        if (it >= items && items <= (int)gridDim.x) break;
         if (it >= items) {
             __syncthreads();
             if (threadIdx.x == 0) {

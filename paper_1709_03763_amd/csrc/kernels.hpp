@@ -126,6 +126,8 @@ __device__ inline uint32_t range_pop(RangeCursor& c, uint32_t* cursors, uint32_t
     for (;;) {
         // indices below `base` of range r are the workers' static first items
         const uint32_t base = (n_workers + kCursors - 1u - (uint32_t)c.r) / kCursors;
+        // a pass with no more items than workers has only static items
+        if (c.next >= c.end && n <= n_workers) return n;
         if (c.next >= c.end) {
             const uint32_t k = (c.end < 2u * base) ? 1u : kRangePop;
             c.next = base + bcast(atomicAdd(cursors + c.r * kCursorStride, lane == 0 ? k : 0u));
@@ -136,6 +138,7 @@ __device__ inline uint32_t range_pop(RangeCursor& c, uint32_t* cursors, uint32_t
             c.next++;
             return item;
         }
+        if (n <= n_workers) return n;
         const uint32_t m =
             bcast(atomicOr(cursors + kCursorDone, lane == 0 ? (1u << c.r) : 0u)) | (1u << c.r);
         if (m == ~0u) return n;
