@@ -34,14 +34,17 @@
 
 namespace sc {
 
-__global__ void batch_init_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr, CandDev cd, int n_bins)
+// Clears the batch's counters, cursors and histogram, and starts an empty
+// record for every integration that records its touched blocks; run by one
+// workgroup of the first candidate kernel (nothing else that kernel does
+// reads them).
+__device__ inline void batch_init(const OpDesc* __restrict__ ops, const BatchHdr* hdr, const CandDev& cd, int n_bins)
 {
     for (int i = threadIdx.x; i < 8; i += blockDim.x) cd.counters[4 + i] = 0u;
     for (int i = threadIdx.x; i < 2 * kCursors; i += blockDim.x) cd.cursors[i * kCursorStride] = 0u;
     if (threadIdx.x < 2) cd.cursors[threadIdx.x * kCursorSet + kCursorDone] = 0u;
     if (threadIdx.x == 0) cd.big[0] = 0u;
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) cd.bins[i] = 0u;
-    // integrations that record their touched blocks start an empty record
     for (int o = threadIdx.x; o < hdr->n_ops; o += blockDim.x)
         if (ops[o].rec_mode == 1) *ops[o].rec_count = 0u;
 }
@@ -60,8 +63,9 @@ __device__ inline bool uses_record(const OpDesc& op)
 // overflowed its capacity is not used: the operation's frustum-cell tiles
 // are generated here instead, tile x, x + gridDim.x, ...
 __global__ __launch_bounds__(256) void cand_record_kernel(const OpDesc* __restrict__ ops, const BatchHdr* hdr,
-                                                          VolDev v, CandDev cd)
+                                                          VolDev v, CandDev cd, int n_bins)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0) batch_init(ops, hdr, cd, n_bins);
     __shared__ uint64_t lds[CandCfg<kTileBatch, kCellBatch>::lds_set];
     __shared__ uint16_t idx[CandCfg<kTileBatch, kCellBatch>::lds_set];
     const int n_ops = hdr->n_ops;
@@ -1410,7 +1414,10 @@ static bool schedule_ok(const sc_schedule& s)
 static void launch_candidates(sc_volume* vol, bool from_cells, hipStream_t s)
 {
     const int n_bins = vol->p.max_batch_ops + 1;
-    batch_init_kernel<<<1, 1024, 0, s>>>(vol->d_ops, vol->d_hdr, vol->cand, n_bins);
+    // first the recorded candidates (their kernel also clears the batch's
+    // counters), then the frustum tiles
+    cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(
+        vol->d_ops, vol->d_hdr, vol->dev, vol->cand, n_bins);
     const int threads = CandCfg<kTileBatch, kCellBatch>::threads;
     if (from_cells) {
         cand_batch_kernel<true><<<vol->n_cu * vol->cand_wgs[1], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
@@ -1419,8 +1426,6 @@ static void launch_candidates(sc_volume* vol, bool from_cells, hipStream_t s)
     } else
         cand_batch_kernel<false><<<vol->n_cu * vol->cand_wgs[0], threads, 0, s>>>(vol->d_ops, vol->d_hdr, vol->dev,
                                                                                   vol->cand);
-    cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(vol->d_ops, vol->d_hdr,
-                                                                                           vol->dev, vol->cand);
     hist_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, n_bins);
     scan_kernel<<<1, 1024, 0, s>>>(vol->cand, n_bins);
     scatter_kernel<<<vol->n_cu * 4, 256, 0, s>>>(vol->cand, vol->dev, n_bins);

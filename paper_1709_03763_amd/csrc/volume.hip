@@ -468,11 +468,11 @@ void rec_destroy(sc_volume* vol)
     vol->rec = nullptr;
 }
 
-// An integration of kf at T: with `records` (the kernel that will run
-// appends the touched blocks) the op appends to the key's record (rec_mode
-// 1; its count is cleared on the device before the pass).  Without, an
-// existing record of the key only gains a reference: the same keyframe at
-// the same pose touches the same blocks, so the record still holds them.
+// An integration of kf at T: an existing record of the key only gains a
+// reference (the same keyframe at the same pose touches the same blocks, so
+// the record still holds them); otherwise, with `records` (the kernel that
+// will run appends the touched blocks), the op fills a fresh record (rec_mode
+// 1; its count is cleared on the device before the pass).
 void rec_for_integration(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* in, const sc_pose* T,
                          bool records, OpDesc* op)
 {
@@ -484,16 +484,17 @@ void rec_for_integration(sc_volume* vol, const sc_keyframe* kf, const sc_intrins
         if (it != r->map.end()) it->second.refs += 1;
         return;
     }
-    int slot;
     if (it != r->map.end()) {
-        slot = it->second.slot;
+        // the same keyframe at the same pose touches the same blocks: the
+        // record stands as it is (so a slot being recorded is always a fresh
+        // one, never one a de-integration of the same batch reads)
         it->second.refs += 1;
-    } else {
-        if (r->free_slots.empty()) return;
-        slot = r->free_slots.back();
-        r->free_slots.pop_back();
-        r->map.emplace(f, RecordRegistry::Entry{slot, 1});
+        return;
     }
+    if (r->free_slots.empty()) return;
+    const int slot = r->free_slots.back();
+    r->free_slots.pop_back();
+    r->map.emplace(f, RecordRegistry::Entry{slot, 1});
     op->rec_keys = r->d_keys + (size_t)slot * r->cap;
     op->rec_count = r->d_count + (size_t)kRecCountStride * slot;
     op->rec_cap = r->cap;
