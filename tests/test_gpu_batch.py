@@ -279,6 +279,35 @@ def test_oversized_tile_boxes_take_the_hash_set(scene):
     assert results[0][1] == results[1][1]
 
 
+def test_duplicate_keyframe_shares_its_record(scene):
+    """The same keyframe integrated twice at one pose holds one touched-block
+    record with two references (the second integration keeps it): a batched
+    update that de-integrates both copies takes its candidates from it twice
+    and must equal the oracle's sequential updates."""
+    wl, kfs, R, t = scene
+    dup = [kfs[0], kfs[0], kfs[1]]
+    Rk = np.stack([R[0], R[0], R[1]])
+    tk = np.stack([t[0], t[0], t[1]])
+    Rn, tn = synth.perturb_all(Rk, tk, 0.02, 1.0, 21)
+    _say("duplicate keyframe")
+    vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+    ref = oracle.Volume(S, MU)
+    d0 = _dev_kf(kfs[0])
+    dks = [d0, d0, _dev_kf(kfs[1])]  # the same device buffers twice: one record key
+    okf = dup
+    vol.set_schedule(8, 2, 8, 4)
+    for k in range(3):
+        vol.integrate(dks[k], wl.intr, Rk[k], tk[k])
+        assert ref.integrate(okf[k], wl.intr, Rk[k], tk[k]) == oracle.OK
+    for _ in range(2):
+        order, (Rk2, tk2) = vol.reintegrate_batch(dks, wl.intr, (Rk, tk), (Rn, tn), 3, scsurf.SEL_ALL_ORDERED)
+        _oracle_update(ref, okf, wl, Rk, tk, Rn, tn, order)
+        vol.check_error()
+        compare_fields(vol.export_sorted(), ref.export())
+        (Rk, tk), (Rn, tn) = (Rn, tn), (Rk, tk)
+    vol.close()
+
+
 def test_schedule_validation(scene):
     vol = scsurf.Volume(S, MU, 1 << 10, 1 << 8, color_mode=scsurf.COLOR_F32)
     for bad in [(3, 4, 4), (8, 4, 0), (8, 4, 33), (4, 2, 8, 1), (8, 3, 4, 1), (8, 4, 4, 1), (8, 4, 4, 4), (8, 2, 4, 5),
