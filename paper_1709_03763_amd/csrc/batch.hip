@@ -1416,7 +1416,8 @@ static void launch_candidates(sc_volume* vol, bool from_cells, hipStream_t s)
     const int n_bins = vol->p.max_batch_ops + 1;
     // first the recorded candidates (their kernel also clears the batch's
     // counters), then the frustum tiles
-    cand_record_kernel<<<dim3(8, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(
+    // 16 workgroups per operation: about one recorded key per thread
+    cand_record_kernel<<<dim3(16, (unsigned)std::min(vol->p.max_batch_ops, 256)), 256, 0, s>>>(
         vol->d_ops, vol->d_hdr, vol->dev, vol->cand, n_bins);
     const int threads = CandCfg<kTileBatch, kCellBatch>::threads;
     if (from_cells) {
