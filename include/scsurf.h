@@ -209,7 +209,10 @@ sc_status sc_color_prep(const uint8_t* rgb, int32_t n_frames, int32_t width, int
  * device n x H x W float; rgb: device n x H x W x 3 uint8; poses: host n.
  * Outputs (device, H x W): kf_depth, kf_weight (on the 2^-10 grid), kf_rgba
  * (uint8 x 4, alpha 255 on valid pixels).  n_frames <= 64.  Scratch is held
- * by the library between calls and reused. */
+ * by the library between calls and reused (one set per device), so calls
+ * that overlap on one device (two streams) race and must be ordered by the
+ * caller.  Relative poses travel as kernel arguments: the host does not wait
+ * for the device. */
 sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, int32_t n_frames, int32_t ref,
                   const sc_intrinsics* intr, const sc_fuse_params* params, float* kf_depth, float* kf_weight,
                   uint8_t* kf_rgba, void* stream);

@@ -11,10 +11,16 @@
 //   color_prep     unsharp mask C + (C - G * C), G the binomial [1 4 6 4 1]/16
 //                  kernel, exact in units of 1/256, and the re-blur measure's
 //                  integer luminance sums (exact int64 per-tile partials)
-//   blur_final     per-frame sums of the partials and w_b
-//   color_kernel   back-warp of each keyframe pixel into every frame,
+//   blur_final     per-frame sums of the partials and w_b (inside the
+//                  depth-weight launch when fusing)
+//   color_kernel   the keyframe depth and weight from the accumulators, then
+//                  the back-warp of each keyframe pixel into every frame,
 //                  bilinear sample of the sharpened colour, weight w_b * w_z,
 //                  per-channel lower weighted median
+//
+// A fusion is four launches: colour prep, depth weight (which also forms
+// w_b from the colour-prep partials, clears the accumulators and stores the
+// relative poses, passed to it as arguments), warp and colour.
 //
 // Decisions are FP32 with the written operation order (-ffp-contract=off).
 #include <string.h>
@@ -33,6 +39,30 @@ constexpr int kMaxFrames = 64;
 struct FuseFrames {
     float Rf[kMaxFrames][12];  // forward: T*^-1 T_i, rows of R then t
     float Rb[kMaxFrames][12];  // backward: T_i^-1 T*
+};
+
+// Relative poses passed by value, kStageFrames frames per launch, so that no
+// host staging buffer or copy is needed.
+constexpr int kStageFrames = 32;
+struct PoseChunk {
+    float Rf[kStageFrames][12];
+    float Rb[kStageFrames][12];
+};
+
+// Work of one fusion done by the depth-weight launch, which follows the
+// colour prep and precedes the warp and colour kernels on its stream: frame
+// 0's workgroups clear the fixed-point accumulators of their tile's pixels,
+// workgroup (0, 0) stores the first `count` relative poses, and the first
+// workgroup of each frame adds up that frame's colour-prep partials into w_b.
+// Null pointers and count 0 skip it (the standalone depth weight).
+struct FuseInit {
+    unsigned long long* acc;  // KW then KZ, 2 x H W
+    const long long* parts;   // colour-prep partials, 4 per tile and frame
+    double* wb;               // w_b per frame
+    int32_t prep_tiles;       // colour-prep tiles per frame
+    FuseFrames* fr;
+    int32_t count;
+    PoseChunk poses;
 };
 
 __device__ inline bool zvalid(float z, float zmin, float zmax) { return z >= zmin && z <= zmax; }
@@ -62,6 +92,34 @@ __device__ inline bool project(const sc_intrinsics& in, const float q[3], float&
     return true;
 }
 
+// One frame's tile partials (4 exact int64 sums per tile) added up by a
+// 256-thread workgroup, then w_b = 1 - max(blur_h, blur_v) in FP64 (the
+// integer sums are exact, so the order of the additions does not matter).
+__device__ inline void blur_reduce(const long long* p, int tiles, long long (*red)[4], double* wb)
+{
+    long long acc[4] = {0, 0, 0, 0};
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += p[(size_t)t * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();  // `red` may still be read from the caller's own reduction
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long s[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        const double bh = s[0] > 0 ? (double)(s[0] - s[1]) / (double)s[0] : 0.0;
+        const double bv = s[2] > 0 ? (double)(s[2] - s[3]) / (double)s[2] : 0.0;
+        *wb = 1.0 - (bh > bv ? bh : bv);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // depth weight
 // ---------------------------------------------------------------------------
@@ -77,7 +135,7 @@ constexpr int kDwStage = (kDwLW * kDwLH + 255) / 256;  // staged pixels per thre
 
 __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restrict__ Z, int n, sc_intrinsics in,
                                                            sc_fuse_params p, int tiles_x, int tiles,
-                                                           float* __restrict__ wz)
+                                                           float* __restrict__ wz, const FuseInit init)
 {
     __shared__ float sx[kDwLH][kDwLW], sy[kDwLH][kDwLW], sz[kDwLH][kDwLW];
     const int W = in.width, H = in.height;
@@ -85,6 +143,12 @@ __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restri
     const int f = blockIdx.y, tile = blockIdx.x;
     if (f >= n || tile >= tiles) return;
     const int u0 = (tile % tiles_x) * kDwTW, v0 = (tile / tiles_x) * kDwTH;
+    if (f == 0 && tile == 0) {
+        for (int i = threadIdx.x; i < init.count * 12; i += blockDim.x) {
+            init.fr->Rf[i / 12][i % 12] = init.poses.Rf[i / 12][i % 12];
+            init.fr->Rb[i / 12][i % 12] = init.poses.Rb[i / 12][i % 12];
+        }
+    }
     const float* Zf = Z + (size_t)f * np;
     // staging: every depth load of a thread issues before the divisions
     float zs[kDwStage];
@@ -138,6 +202,14 @@ __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restri
             }
         }
         wz[(size_t)f * np + (size_t)v * W + u] = out;
+        if (init.acc && f == 0) {
+            init.acc[(size_t)v * W + u] = 0ull;
+            init.acc[np + (size_t)v * W + u] = 0ull;
+        }
+    }
+    if (init.parts && tile == 0) {
+        __shared__ long long red[4][4];
+        blur_reduce(init.parts + (size_t)f * init.prep_tiles * 4, init.prep_tiles, red, init.wb + f);
     }
 }
 
@@ -167,22 +239,6 @@ __global__ void warp_kernel(const float* __restrict__ Z, const float* __restrict
     const int64_t t = (int64_t)iv * W + iu;
     atomicAdd(KW + t, (unsigned long long)wk);
     atomicAdd(KZ + t, (unsigned long long)(wk * zk));
-}
-
-__global__ void depth_final_kernel(const unsigned long long* KW, const unsigned long long* KZ, int64_t np, float* Zs,
-                                   float* Ws)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const long long kw = (long long)KW[i];
-    if (kw > 0) {
-        const long long kz = (long long)KZ[i];
-        Ws[i] = (float)((double)kw / 1024.0);
-        Zs[i] = (float)(((double)kz / (double)kw) * 0x1p-20);
-    } else {
-        Ws[i] = 0.0f;
-        Zs[i] = 0.0f;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -299,34 +355,14 @@ __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restri
     }
 }
 
-// One workgroup per frame: the tiles' partial sums in a fixed order, then
-// w_b = 1 - max(blur_h, blur_v) in FP64.
+// One workgroup per frame (standalone colour pre-processing).
 __global__ __launch_bounds__(256) void blur_final_kernel(const long long* __restrict__ parts, int n, int tiles,
                                                          double* wb)
 {
     __shared__ long long red[4][4];
     const int f = blockIdx.x;
     if (f >= n) return;
-    long long acc[4] = {0, 0, 0, 0};
-    for (int t = threadIdx.x; t < tiles; t += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] += parts[((size_t)f * tiles + t) * 4 + k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long s[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-        const double bh = s[0] > 0 ? (double)(s[0] - s[1]) / (double)s[0] : 0.0;
-        const double bv = s[2] > 0 ? (double)(s[2] - s[3]) / (double)s[2] : 0.0;
-        wb[f] = 1.0 - (bh > bv ? bh : bv);
-    }
+    blur_reduce(parts + (size_t)f * tiles * 4, tiles, red, wb + f);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,11 +375,14 @@ struct Obs {
 };
 
 // One thread per keyframe pixel; observations staged in LDS (dynamic,
-// n frames per thread).
+// n frames per thread).  The pixel's depth and weight come first from the
+// fixed-point accumulators: W* = sum(w) and Z* = sum(w z) / sum(w), rounded
+// once to FP32.
 __global__ void color_kernel(const float* __restrict__ Z, const float* __restrict__ wz,
                              const uint16_t* __restrict__ cs, const double* __restrict__ wb, int n,
-                             sc_intrinsics in, float occ_rel, const FuseFrames* __restrict__ fr, float* Zs, float* Ws,
-                             uint8_t* rgba)
+                             sc_intrinsics in, float occ_rel, const FuseFrames* __restrict__ fr,
+                             const unsigned long long* __restrict__ KW, const unsigned long long* __restrict__ KZ,
+                             float* Zs, float* Ws, uint8_t* rgba)
 {
     extern __shared__ Obs obs_lds[];
     const int W = in.width, H = in.height;
@@ -352,13 +391,17 @@ __global__ void color_kernel(const float* __restrict__ Z, const float* __restric
     if (idx >= np) return;
     Obs* obs = obs_lds + (size_t)threadIdx.x * n;
     uint8_t* out = rgba + 4 * idx;
-    if (!(Ws[idx] > 0.0f)) {
+    const long long kw = (long long)KW[idx];
+    if (!(kw > 0)) {
+        Ws[idx] = 0.0f;
+        Zs[idx] = 0.0f;
         out[0] = out[1] = out[2] = out[3] = 0;
         return;
     }
+    const float zk = (float)(((double)(long long)KZ[idx] / (double)kw) * 0x1p-20);
     const int u = (int)(idx % W), v = (int)(idx / W);
     float P[3];
-    backproject((float)u, (float)v, Zs[idx], in, P);
+    backproject((float)u, (float)v, zk, in, P);
     int m = 0;
     for (int i = 0; i < n; ++i) {
         float q[3], uf, vf;
@@ -396,6 +439,8 @@ __global__ void color_kernel(const float* __restrict__ Z, const float* __restric
         out[0] = out[1] = out[2] = out[3] = 0;
         return;
     }
+    Ws[idx] = (float)((double)kw / 1024.0);
+    Zs[idx] = zk;
     uint64_t total = 0;
     for (int j = 0; j < m; ++j) total += obs[j].w;
 #pragma unroll
@@ -440,8 +485,6 @@ struct FuseWs {
     size_t cap_parts = 0;
     double* wb = nullptr;
     FuseFrames* d_fr = nullptr;
-    FuseFrames* h_fr = nullptr;
-    hipEvent_t staged = nullptr;
 };
 
 static FuseWs g_ws;
@@ -465,15 +508,10 @@ static sc_status ws_reserve(size_t np, size_t frames, size_t parts)
         g_ws.cap_parts = 0;
         g_ws.wb = nullptr;
         g_ws.d_fr = nullptr;
-        g_ws.h_fr = nullptr;
-        g_ws.staged = nullptr;
         g_ws.device = dev;
     }
     if (!g_ws.d_fr) {
         if (hipMalloc(&g_ws.d_fr, sizeof(FuseFrames)) != hipSuccess) return SC_ENOMEM;
-        if (hipHostMalloc((void**)&g_ws.h_fr, sizeof(FuseFrames), hipHostMallocDefault) != hipSuccess) return SC_ENOMEM;
-        if (hipEventCreateWithFlags(&g_ws.staged, hipEventDisableTiming) != hipSuccess) return SC_EDEVICE;
-        if (hipEventRecord(g_ws.staged, 0) != hipSuccess) return SC_EDEVICE;
         if (hipMalloc(&g_ws.wb, sizeof(double) * kMaxFrames) != hipSuccess) return SC_ENOMEM;
     }
     if (np * frames > g_ws.cap_px * g_ws.cap_frames || np > g_ws.cap_px) {
@@ -586,20 +624,30 @@ static void rel_pose(const sc_pose& A, const sc_pose& B, float out[12])
 }
 
 static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& in, const sc_fuse_params& p, float* out,
-                                hipStream_t s)
+                                const FuseInit& init, hipStream_t s)
 {
     const int tiles_x = (in.width + kDwTW - 1) / kDwTW;
     const int tiles = tiles_x * ((in.height + kDwTH - 1) / kDwTH);
-    depth_weight_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(depth, n, in, p, tiles_x, tiles, out);
+    depth_weight_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(depth, n, in, p, tiles_x, tiles, out, init);
 }
 
+// wb null: the partials only (a fusion forms w_b in its depth-weight launch).
 static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, long long* parts, double* wb,
                               hipStream_t s)
 {
     const int tiles = prep_tiles(W, H);
     color_prep_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp,
                                                                         parts);
-    blur_final_kernel<<<n, 256, 0, s>>>(parts, n, tiles, wb);
+    if (wb) blur_final_kernel<<<n, 256, 0, s>>>(parts, n, tiles, wb);
+}
+
+// Relative poses of frames first .. first + count - 1 into the device table.
+__global__ void stage_poses_kernel(PoseChunk c, int first, int count, FuseFrames* fr)
+{
+    for (int i = threadIdx.x; i < count * 12; i += blockDim.x) {
+        fr->Rf[first + i / 12][i % 12] = c.Rf[i / 12][i % 12];
+        fr->Rb[first + i / 12][i % 12] = c.Rb[i / 12][i % 12];
+    }
 }
 
 // Device buffers of one fusion: per-frame weights, sharpened colour, the
@@ -613,26 +661,42 @@ struct FuseBufs {
     FuseFrames* fr;
 };
 
-// The fusion kernels of one keyframe, on buffers whose relative poses are
-// already in place (or enqueued before on the same stream).
-static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rgb, int n_frames,
-                        const sc_intrinsics& in, const sc_fuse_params& params, float* kf_depth, float* kf_weight,
-                        uint8_t* kf_rgba, hipStream_t s)
+// The fusion kernels of one keyframe.  The relative poses of the first
+// kStageFrames frames travel in the depth-weight launch; those of later
+// frames are stored by stage_poses_kernel launches enqueued first.
+static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rgb, const sc_pose* poses, int n_frames,
+                        int ref, const sc_intrinsics& in, const sc_fuse_params& params, float* kf_depth,
+                        float* kf_weight, uint8_t* kf_rgba, hipStream_t s)
 {
     const int64_t np = (int64_t)in.width * in.height;
-    // depth
-    launch_depth_weight(depth, n_frames, in, params, b.wz, s);
-    fill_u64(reinterpret_cast<uint64_t*>(b.acc), 0ull, 2 * (size_t)np, s);
+    FuseInit init;
+    init.acc = b.acc;
+    init.parts = b.parts;
+    init.wb = b.wb;
+    init.prep_tiles = prep_tiles(in.width, in.height);
+    init.fr = b.fr;
+    for (int i0 = kStageFrames; i0 < n_frames; i0 += kStageFrames) {
+        const int cnt = std::min(kStageFrames, n_frames - i0);
+        for (int j = 0; j < cnt; ++j) {
+            rel_pose(poses[ref], poses[i0 + j], init.poses.Rf[j]);
+            rel_pose(poses[i0 + j], poses[ref], init.poses.Rb[j]);
+        }
+        stage_poses_kernel<<<1, 256, 0, s>>>(init.poses, i0, cnt, b.fr);
+    }
+    init.count = std::min(kStageFrames, n_frames);
+    for (int j = 0; j < init.count; ++j) {
+        rel_pose(poses[ref], poses[j], init.poses.Rf[j]);
+        rel_pose(poses[j], poses[ref], init.poses.Rb[j]);
+    }
+    launch_color_prep(rgb, n_frames, in.width, in.height, b.cs, b.parts, nullptr, s);
+    launch_depth_weight(depth, n_frames, in, params, b.wz, init, s);
     dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
     warp_kernel<<<grid, 256, 0, s>>>(depth, b.wz, n_frames, in, b.fr, b.acc, b.acc + np);
-    depth_final_kernel<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(b.acc, b.acc + np, np, kf_depth, kf_weight);
-    // colour
-    launch_color_prep(rgb, n_frames, in.width, in.height, b.cs, b.parts, b.wb, s);
     int threads = 256;
     while (threads > 64 && (size_t)threads * n_frames * sizeof(Obs) > 48 * 1024) threads >>= 1;
     const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
     color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
-        depth, b.wz, b.cs, b.wb, n_frames, in, params.occ_rel, b.fr, kf_depth, kf_weight, kf_rgba);
+        depth, b.wz, b.cs, b.wb, n_frames, in, params.occ_rel, b.fr, b.acc, b.acc + np, kf_depth, kf_weight, kf_rgba);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,22 +752,6 @@ static size_t fuse_layout(unsigned char* base, size_t np, size_t frames, size_t 
     return off;
 }
 
-// Relative poses passed by value, kStageFrames frames per launch, so that no
-// host staging buffer is needed.
-constexpr int kStageFrames = 32;
-struct PoseChunk {
-    float Rf[kStageFrames][12];
-    float Rb[kStageFrames][12];
-};
-
-__global__ void stage_poses_kernel(PoseChunk c, int first, int count, FuseFrames* fr)
-{
-    for (int i = threadIdx.x; i < count * 12; i += blockDim.x) {
-        fr->Rf[first + i / 12][i % 12] = c.Rf[i / 12][i % 12];
-        fr->Rb[first + i / 12][i % 12] = c.Rb[i / 12][i % 12];
-    }
-}
-
 }  // namespace sc
 
 using namespace sc;
@@ -714,7 +762,7 @@ sc_status sc_depth_weight(const float* depth, int32_t n_frames, const sc_intrins
                           float* wz_out, void* stream)
 {
     if (!depth || !wz_out || n_frames <= 0 || n_frames > 65535 || !intr_valid(intr) || !params) return SC_EINVAL;
-    launch_depth_weight(depth, n_frames, *intr, *params, wz_out, (hipStream_t)stream);
+    launch_depth_weight(depth, n_frames, *intr, *params, wz_out, FuseInit{}, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
@@ -745,16 +793,8 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
     std::lock_guard<std::mutex> lk(g_ws.mu);
     sc_status st = ws_reserve((size_t)np, (size_t)n_frames, 4 * (size_t)prep_tiles(in.width, in.height) * n_frames);
     if (st != SC_OK) return st;
-    if (hipEventSynchronize(g_ws.staged) != hipSuccess) return SC_EDEVICE;
-    for (int i = 0; i < n_frames; ++i) {
-        rel_pose(poses[ref], poses[i], g_ws.h_fr->Rf[i]);
-        rel_pose(poses[i], poses[ref], g_ws.h_fr->Rb[i]);
-    }
-    if (hipMemcpyAsync(g_ws.d_fr, g_ws.h_fr, sizeof(FuseFrames), hipMemcpyHostToDevice, s) != hipSuccess)
-        return SC_EDEVICE;
-    if (hipEventRecord(g_ws.staged, s) != hipSuccess) return SC_EDEVICE;
     const FuseBufs b{g_ws.wz, g_ws.cs, g_ws.acc, g_ws.parts, g_ws.wb, g_ws.d_fr};
-    launch_fuse(b, depth, rgb, n_frames, in, *params, kf_depth, kf_weight, kf_rgba, s);
+    launch_fuse(b, depth, rgb, poses, n_frames, ref, in, *params, kf_depth, kf_weight, kf_rgba, s);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
@@ -775,16 +815,7 @@ sc_status kf_fuse_noalloc(const float* depth, const uint8_t* rgb, const sc_pose*
     const sc_status st = scratch_address(&base);
     if (st != SC_OK) return st;
     fuse_layout(base, np, (size_t)n_frames, parts, b);
-    for (int i0 = 0; i0 < n_frames; i0 += kStageFrames) {
-        const int cnt = std::min(kStageFrames, n_frames - i0);
-        PoseChunk c;
-        for (int j = 0; j < cnt; ++j) {
-            rel_pose(poses[ref], poses[i0 + j], c.Rf[j]);
-            rel_pose(poses[i0 + j], poses[ref], c.Rb[j]);
-        }
-        stage_poses_kernel<<<1, 256, 0, s>>>(c, i0, cnt, b.fr);
-    }
-    launch_fuse(b, depth, rgb, n_frames, in, *params, kf_depth, kf_weight, kf_rgba, s);
+    launch_fuse(b, depth, rgb, poses, n_frames, ref, in, *params, kf_depth, kf_weight, kf_rgba, s);
     return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
 }
 
