@@ -221,10 +221,10 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
  * serving loops, harnesses that forbid hipMalloc): the same arguments,
  * kernels and results, with every intermediate buffer (per-frame weights,
  * sharpened colour, fixed-point accumulators, colour-prep partials, relative
- * poses) in one fixed 64 MiB device array per device, held until the process
+ * poses) in one fixed 76 MiB device array per device, held until the process
  * ends.  Relative poses travel as kernel arguments, so no host staging or
  * copy is enqueued either.  The array needs about
- * 16 H W + 10 H W n_frames bytes (640 x 480 fits up to 20 frames); a larger
+ * 16 H W + 12 H W n_frames bytes (640 x 480 fits up to 20 frames); a larger
  * input returns SC_ESCRATCH with nothing enqueued.  Every call on a device
  * shares that device's array, so calls that overlap on one device (two
  * streams, or two host threads) race and must be ordered by the caller.

@@ -267,6 +267,9 @@ constexpr int kPrepLW = kPrepTW + 9, kPrepLH = kPrepTH + 9;
 constexpr int kPrepHalo = 5;
 constexpr int kPrepStage = (kPrepLW * kPrepLH + 255) / 256;  // staged pixels per thread (256 threads)
 
+// kOutCh: 3 (packed RGB, the standalone output) or 4 (RGB and a zero, one
+// 8-byte store per pixel; the layout the colour kernel gathers from).
+template <int kOutCh>
 __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restrict__ rgb, int n, int W, int H,
                                                          int tiles_x, int tiles, uint16_t* __restrict__ out,
                                                          long long* __restrict__ parts)
@@ -321,11 +324,20 @@ __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restri
         const uint64_t S = (hsum[y][tx] + 4 * hsum[y + 1][tx]) +
                            ((6 * hsum[y + 2][tx] + 4 * hsum[y + 3][tx]) + hsum[y + 4][tx]);
         const uint64_t c0 = pix[j][i];
-        uint16_t* o = out + (size_t)f * np * 3 + 3 * ((size_t)v * W + u);
+        uint32_t sh[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int val = 512 * (int)((c0 >> (16 * k)) & 0xFFFFu) - (int)((S >> (16 * k)) & 0xFFFFu);
-            o[k] = (uint16_t)clampi(val, 0, 65280);
+            sh[k] = (uint32_t)clampi(val, 0, 65280);
+        }
+        const size_t px = (size_t)f * np + (size_t)v * W + u;
+        if (kOutCh == 4) {
+            *reinterpret_cast<uint2*>(out + 4 * px) = make_uint2(sh[0] | (sh[1] << 16), sh[2]);
+        } else {
+            uint16_t* o = out + 3 * px;
+            o[0] = (uint16_t)sh[0];
+            o[1] = (uint16_t)sh[1];
+            o[2] = (uint16_t)sh[2];
         }
         const int y0 = lum[j][i];
         if (u >= 1) {
@@ -371,103 +383,116 @@ __global__ __launch_bounds__(256) void blur_final_kernel(const long long* __rest
 
 struct Obs {
     float c[3];
-    uint32_t w;  // weight on the 2^-20 grid
+    uint32_t w;  // weight on the 2^-20 grid; 0: no observation from this frame
 };
 
-// One thread per keyframe pixel; observations staged in LDS (dynamic,
-// n frames per thread).  The pixel's depth and weight come first from the
-// fixed-point accumulators: W* = sum(w) and Z* = sum(w z) / sum(w), rounded
-// once to FP32.
-__global__ void color_kernel(const float* __restrict__ Z, const float* __restrict__ wz,
-                             const uint16_t* __restrict__ cs, const double* __restrict__ wb, int n,
-                             sc_intrinsics in, float occ_rel, const FuseFrames* __restrict__ fr,
-                             const unsigned long long* __restrict__ KW, const unsigned long long* __restrict__ KZ,
-                             float* Zs, float* Ws, uint8_t* rgba)
+// One thread per (keyframe pixel, frame): a workgroup of 256 threads takes
+// ppw = 256 / n pixels, thread t the pixel t / n and the frame t % n.  Every
+// thread of a pixel forms the pixel's depth from the fixed-point
+// accumulators (W* = sum(w), Z* = sum(w z) / sum(w), rounded once to FP32),
+// back-warps it into its frame and stores its observation (or none) in LDS.
+// Then each thread decides for its own observation j and each channel
+// whether it is the lower weighted median: with the observations ordered by
+// (value, frame), j is the first whose cumulative weight reaches half the
+// total exactly when the weight ordered strictly before it is below half
+// and that weight plus its own reaches half; one observation per channel
+// passes, and it writes the channel.
+__global__ __launch_bounds__(256) void color_kernel(const float* __restrict__ Z, const float* __restrict__ wz,
+                                                    const uint16_t* __restrict__ cs, const double* __restrict__ wb,
+                                                    int n, int ppw, sc_intrinsics in, float occ_rel,
+                                                    const FuseFrames* __restrict__ fr,
+                                                    const unsigned long long* __restrict__ KW,
+                                                    const unsigned long long* __restrict__ KZ, float* Zs, float* Ws,
+                                                    uint8_t* rgba)
 {
-    extern __shared__ Obs obs_lds[];
+    __shared__ Obs obs[256];
     const int W = in.width, H = in.height;
     const int64_t np = (int64_t)W * H;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= np) return;
-    Obs* obs = obs_lds + (size_t)threadIdx.x * n;
-    uint8_t* out = rgba + 4 * idx;
-    const long long kw = (long long)KW[idx];
-    if (!(kw > 0)) {
-        Ws[idx] = 0.0f;
-        Zs[idx] = 0.0f;
-        out[0] = out[1] = out[2] = out[3] = 0;
-        return;
-    }
-    const float zk = (float)(((double)(long long)KZ[idx] / (double)kw) * 0x1p-20);
-    const int u = (int)(idx % W), v = (int)(idx / W);
-    float P[3];
-    backproject((float)u, (float)v, zk, in, P);
-    int m = 0;
-    for (int i = 0; i < n; ++i) {
-        float q[3], uf, vf;
-        int iu, iv;
-        xform(fr->Rb[i], P, q);
-        if (!project(in, q, uf, vf, iu, iv)) continue;
-        const size_t base = (size_t)i * np;
-        const float wzi = wz[base + (size_t)iv * W + iu];
-        if (!(wzi > 0.0f)) continue;
-        if (!(fabsf(Z[base + (size_t)iv * W + iu] - q[2]) <= occ_rel * q[2])) continue;
-        const float x0 = floorf(uf), y0 = floorf(vf);
-        if (!(x0 >= 0.0f && x0 + 1.0f <= (float)(W - 1) && y0 >= 0.0f && y0 + 1.0f <= (float)(H - 1))) continue;
-        const float ax = uf - x0, ay = vf - y0;
-        const int ix = (int)x0, iy = (int)y0;
-        const float wc = (float)wb[i] * wzi;
-        const float wcs = rintf(wc * 1048576.0f);
-        if (!(wcs > 0.0f)) continue;
-        const uint16_t* C = cs + base * 3;
-        Obs o;
+    const int lp = (int)threadIdx.x / n, i = (int)threadIdx.x - lp * n;
+    const int64_t idx = (int64_t)blockIdx.x * ppw + lp;
+    const bool mine = lp < ppw && idx < np;
+    Obs o;
+    o.c[0] = o.c[1] = o.c[2] = 0.0f;
+    o.w = 0u;
+    long long kw = 0;
+    float zk = 0.0f;
+    if (mine) {
+        kw = (long long)KW[idx];
+        if (kw > 0) {
+            zk = (float)(((double)(long long)KZ[idx] / (double)kw) * 0x1p-20);
+            const int u = (int)(idx % W), v = (int)(idx / W);
+            float P[3], q[3], uf, vf;
+            int iu, iv;
+            backproject((float)u, (float)v, zk, in, P);
+            xform(fr->Rb[i], P, q);
+            if (project(in, q, uf, vf, iu, iv)) {
+                const size_t base = (size_t)i * np;
+                const float wzi = wz[base + (size_t)iv * W + iu];
+                const float zi = Z[base + (size_t)iv * W + iu];
+                const float x0 = floorf(uf), y0 = floorf(vf);
+                if (wzi > 0.0f && fabsf(zi - q[2]) <= occ_rel * q[2] && x0 >= 0.0f &&
+                    x0 + 1.0f <= (float)(W - 1) && y0 >= 0.0f && y0 + 1.0f <= (float)(H - 1)) {
+                    const float ax = uf - x0, ay = vf - y0;
+                    const int ix = (int)x0, iy = (int)y0;
+                    const float wcs = rintf(((float)wb[i] * wzi) * 1048576.0f);
+                    if (wcs > 0.0f) {
+                        // four channels of 16 bits per pixel, 8-byte aligned
+                        const uint2* C0 = reinterpret_cast<const uint2*>(cs) + base + (size_t)iy * W + ix;
+                        const uint2* C1 = C0 + W;
+                        const uint2 p00 = C0[0], p10 = C0[1], p01 = C1[0], p11 = C1[1];
+                        auto ch = [](uint2 p, int k) {
+                            return (float)(k == 0 ? (p.x & 0xFFFFu) : k == 1 ? (p.x >> 16) : (p.y & 0xFFFFu));
+                        };
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float c00 = (float)C[3 * ((size_t)iy * W + ix) + k], c10 = (float)C[3 * ((size_t)iy * W + ix + 1) + k];
-            const float c01 = (float)C[3 * ((size_t)(iy + 1) * W + ix) + k];
-            const float c11 = (float)C[3 * ((size_t)(iy + 1) * W + ix + 1) + k];
-            const float top = c00 + ax * (c10 - c00);
-            const float bot = c01 + ax * (c11 - c01);
-            o.c[k] = top + ay * (bot - top);
-        }
-        o.w = (uint32_t)wcs;
-        obs[m++] = o;
-    }
-    if (m == 0) {
-        Zs[idx] = 0.0f;
-        Ws[idx] = 0.0f;
-        out[0] = out[1] = out[2] = out[3] = 0;
-        return;
-    }
-    Ws[idx] = (float)((double)kw / 1024.0);
-    Zs[idx] = zk;
-    uint64_t total = 0;
-    for (int j = 0; j < m; ++j) total += obs[j].w;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        // lower weighted median: the smallest (value, frame) whose cumulative
-        // weight in (value, frame) order reaches half the total
-        int best = -1;
-        float bc = 0.0f;
-        for (int j = 0; j < m; ++j) {
-            const float cj = obs[j].c[k];
-            uint64_t below = 0;
-            for (int l = 0; l < m; ++l) {
-                const float cl = obs[l].c[k];
-                if (cl < cj || (cl == cj && l < j)) below += obs[l].w;
-            }
-            if (2 * (below + obs[j].w) >= total) {
-                if (best < 0 || cj < bc) {
-                    best = j;
-                    bc = cj;
+                        for (int k = 0; k < 3; ++k) {
+                            const float c00 = ch(p00, k), c10 = ch(p10, k);
+                            const float c01 = ch(p01, k), c11 = ch(p11, k);
+                            const float top = c00 + ax * (c10 - c00);
+                            const float bot = c01 + ax * (c11 - c01);
+                            o.c[k] = top + ay * (bot - top);
+                        }
+                        o.w = (uint32_t)wcs;
+                    }
                 }
             }
         }
-        float val = rintf(bc / 256.0f);
-        val = fminf(fmaxf(val, 0.0f), 255.0f);
-        out[k] = (uint8_t)val;
     }
-    out[3] = 255;
+    if (lp < ppw) obs[threadIdx.x] = o;
+    __syncthreads();
+    if (!mine) return;
+    const Obs* po = obs + lp * n;
+    uint64_t total = 0, below[3] = {0, 0, 0};
+    for (int l = 0; l < n; ++l) {
+        const Obs ol = po[l];
+        total += ol.w;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (ol.c[k] < o.c[k] || (ol.c[k] == o.c[k] && l < i)) below[k] += ol.w;
+    }
+    uint8_t* out = rgba + 4 * idx;
+    if (total == 0) {
+        // no frame observed the pixel (or it has no depth)
+        if (i == 0) {
+            Ws[idx] = 0.0f;
+            Zs[idx] = 0.0f;
+            out[0] = out[1] = out[2] = out[3] = 0;
+        }
+        return;
+    }
+    if (i == 0) {
+        Ws[idx] = (float)((double)kw / 1024.0);
+        Zs[idx] = zk;
+        out[3] = 255;
+    }
+    if (o.w == 0u) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (2 * below[k] < total && 2 * (below[k] + o.w) >= total) {
+            float val = rintf(o.c[k] / 256.0f);
+            val = fminf(fmaxf(val, 0.0f), 255.0f);
+            out[k] = (uint8_t)val;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -526,7 +551,7 @@ static sc_status ws_reserve(size_t np, size_t frames, size_t parts)
         g_ws.acc = nullptr;
         g_ws.cap_px = g_ws.cap_frames = 0;
         if (hipMalloc(&g_ws.wz, sizeof(float) * px * fr) != hipSuccess) return SC_ENOMEM;
-        if (hipMalloc(&g_ws.cs, sizeof(uint16_t) * 3 * px * fr) != hipSuccess) return SC_ENOMEM;
+        if (hipMalloc(&g_ws.cs, sizeof(uint16_t) * 4 * px * fr) != hipSuccess) return SC_ENOMEM;
         if (hipMalloc(&g_ws.acc, sizeof(unsigned long long) * 2 * px) != hipSuccess) return SC_ENOMEM;
         g_ws.cap_px = px;
         g_ws.cap_frames = fr;
@@ -631,14 +656,20 @@ static void launch_depth_weight(const float* depth, int n, const sc_intrinsics& 
     depth_weight_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(depth, n, in, p, tiles_x, tiles, out, init);
 }
 
-// wb null: the partials only (a fusion forms w_b in its depth-weight launch).
+// wb null: the partials only, sharpened colour with four channels per pixel
+// (a fusion forms w_b in its depth-weight launch); else three channels and
+// w_b.
 static void launch_color_prep(const uint8_t* rgb, int n, int W, int H, uint16_t* sharp, long long* parts, double* wb,
                               hipStream_t s)
 {
     const int tiles = prep_tiles(W, H);
-    color_prep_kernel<<<dim3((unsigned)tiles, (unsigned)n), 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp,
-                                                                        parts);
-    if (wb) blur_final_kernel<<<n, 256, 0, s>>>(parts, n, tiles, wb);
+    const dim3 grid((unsigned)tiles, (unsigned)n);
+    if (wb) {
+        color_prep_kernel<3><<<grid, 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp, parts);
+        blur_final_kernel<<<n, 256, 0, s>>>(parts, n, tiles, wb);
+    } else {
+        color_prep_kernel<4><<<grid, 256, 0, s>>>(rgb, n, W, H, prep_tiles_x(W), tiles, sharp, parts);
+    }
 }
 
 // Relative poses of frames first .. first + count - 1 into the device table.
@@ -692,11 +723,10 @@ static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rg
     launch_depth_weight(depth, n_frames, in, params, b.wz, init, s);
     dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
     warp_kernel<<<grid, 256, 0, s>>>(depth, b.wz, n_frames, in, b.fr, b.acc, b.acc + np);
-    int threads = 256;
-    while (threads > 64 && (size_t)threads * n_frames * sizeof(Obs) > 48 * 1024) threads >>= 1;
-    const size_t lds = (size_t)threads * n_frames * sizeof(Obs);
-    color_kernel<<<(unsigned)((np + threads - 1) / threads), threads, lds, s>>>(
-        depth, b.wz, b.cs, b.wb, n_frames, in, params.occ_rel, b.fr, b.acc, b.acc + np, kf_depth, kf_weight, kf_rgba);
+    const int ppw = 256 / n_frames;  // pixels per colour workgroup (n_frames <= kMaxFrames = 64)
+    color_kernel<<<(unsigned)((np + ppw - 1) / ppw), 256, 0, s>>>(depth, b.wz, b.cs, b.wb, n_frames, ppw, in,
+                                                                  params.occ_rel, b.fr, b.acc, b.acc + np, kf_depth,
+                                                                  kf_weight, kf_rgba);
 }
 
 // ---------------------------------------------------------------------------
@@ -708,7 +738,7 @@ static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rg
 // device with hipGetSymbolAddress and only that address is passed on.  Every
 // call on a device shares that device's copy, so calls that overlap on one
 // device race.
-constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchBytes = size_t(76) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -748,7 +778,7 @@ static size_t fuse_layout(unsigned char* base, size_t np, size_t frames, size_t 
     b.acc = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2 * np));
     b.parts = reinterpret_cast<long long*>(take(sizeof(long long) * parts));
     b.wz = reinterpret_cast<float*>(take(sizeof(float) * np * frames));
-    b.cs = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * 3 * np * frames));
+    b.cs = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * 4 * np * frames));
     return off;
 }
 

@@ -65,7 +65,7 @@ def test_noalloc_equals_kf_fuse_on_two_calls():
 def test_noalloc_rejects_input_beyond_scratch():
     assert torch.cuda.is_available(), "GPU tests need a device"
     wl = synth.workload(2)
-    n = 21  # 640x480: 16 HW + 10 HW n bytes exceed 64 MiB from 21 frames on
+    n = 21  # 640x480: 16 HW + 12 HW n bytes exceed 76 MiB from 21 frames on
     z = torch.zeros((n, 480, 640), device="cuda")
     c = torch.zeros((n, 480, 640, 3), dtype=torch.uint8, device="cuda")
     with pytest.raises(scsurf.ScError) as e:
