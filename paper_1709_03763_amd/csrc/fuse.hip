@@ -217,28 +217,113 @@ __global__ __launch_bounds__(256) void depth_weight_kernel(const float* __restri
 // depth fusion
 // ---------------------------------------------------------------------------
 
-__global__ void warp_kernel(const float* __restrict__ Z, const float* __restrict__ wz, int n, sc_intrinsics in,
-                            const FuseFrames* __restrict__ fr, unsigned long long* KW, unsigned long long* KZ)
+// The warp by target tiles.  Workgroup k owns the 16 x 16 tile k of
+// keyframe pixels (on a grid extended by kWpE tiles on each side) and, for
+// each frame f, the source tile k shifted back by that frame's displacement
+// d_f: the image centre back-projected at depth z_nom, moved into the
+// keyframe and projected, rounded to whole pixels and clamped to +-kWpD.
+// Every workgroup computes the same d_f, and a whole-pixel shift of the tile
+// grid still covers each frame's pixels exactly once, so every sample is
+// warped once whatever d_f is; d_f only decides how many land near the
+// tile.  The samples are first added into an LDS window of keyframe pixels
+// (the tile and kWpM pixels on each side); each window pixel that received
+// any then goes to the device-wide accumulators with one pair of atomics,
+// and samples that land outside the window go there directly.  The sums are
+// exact integers, so the grouping does not change them.
+constexpr int kWpT = 16, kWpM = 8, kWpL = kWpT + 2 * kWpM;
+constexpr int kWpE = 4, kWpD = kWpE * kWpT;
+
+__global__ __launch_bounds__(256) void warp_kernel(const float* __restrict__ Z, const float* __restrict__ wz, int n,
+                                                   sc_intrinsics in, float z_nom, int tiles_x,
+                                                   const FuseFrames* __restrict__ fr, unsigned long long* KW,
+                                                   unsigned long long* KZ)
 {
+    __shared__ unsigned long long lw[kWpL * kWpL], lz[kWpL * kWpL];
+    __shared__ int2 shift[kMaxFrames];
     const int W = in.width, H = in.height;
     const int64_t np = (int64_t)W * H;
-    const int f = blockIdx.y;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n || idx >= np) return;
-    const float w = wz[(size_t)f * np + idx];
-    if (!(w > 0.0f)) return;
-    const int u = (int)(idx % W), v = (int)(idx / W);
-    float P[3], q[3];
-    backproject((float)u, (float)v, Z[(size_t)f * np + idx], in, P);
-    xform(fr->Rf[f], P, q);
-    float uf, vf;
-    int iu, iv;
-    if (!project(in, q, uf, vf, iu, iv)) return;
-    const long long wk = (long long)rintf(w * kWeightScale);
-    const long long zk = (long long)rintf(q[2] * 1048576.0f);
-    const int64_t t = (int64_t)iv * W + iu;
-    atomicAdd(KW + t, (unsigned long long)wk);
-    atomicAdd(KZ + t, (unsigned long long)(wk * zk));
+    for (int e = threadIdx.x; e < kWpL * kWpL; e += blockDim.x) {
+        lw[e] = 0ull;
+        lz[e] = 0ull;
+    }
+    if ((int)threadIdx.x < n) {
+        const float cu = (float)(W / 2), cv = (float)(H / 2);
+        float P[3], q[3];
+        backproject(cu, cv, z_nom, in, P);
+        xform(fr->Rf[threadIdx.x], P, q);
+        int2 d = make_int2(0, 0);
+        if (q[2] > 0.0f) {
+            const float du = rintf((in.fx * q[0]) / q[2] + in.cx - cu);
+            const float dv = rintf((in.fy * q[1]) / q[2] + in.cy - cv);
+            // (a NaN compares false and leaves 0)
+            if (fabsf(du) <= (float)kWpD) d.x = (int)du;
+            else if (du > 0.0f) d.x = kWpD;
+            else if (du < 0.0f) d.x = -kWpD;
+            if (fabsf(dv) <= (float)kWpD) d.y = (int)dv;
+            else if (dv > 0.0f) d.y = kWpD;
+            else if (dv < 0.0f) d.y = -kWpD;
+        }
+        shift[threadIdx.x] = d;
+    }
+    __syncthreads();
+    const int ku = ((int)blockIdx.x % tiles_x - kWpE) * kWpT, kv = ((int)blockIdx.x / tiles_x - kWpE) * kWpT;
+    const int wx0 = ku - kWpM, wy0 = kv - kWpM;
+    const int tx = (int)threadIdx.x & (kWpT - 1), ty = (int)threadIdx.x / kWpT;
+    // frames in groups of kWpF: every load of a group issues before its samples are warped
+    constexpr int kWpF = 4;
+    for (int f0 = 0; f0 < n; f0 += kWpF) {
+        float wg[kWpF], zg[kWpF];
+#pragma unroll
+        for (int j = 0; j < kWpF; ++j) {
+            wg[j] = 0.0f;
+            zg[j] = 0.0f;
+            const int f = f0 + j;
+            if (f < n) {
+                const int2 d = shift[f];
+                const int u = ku + tx - d.x, v = kv + ty - d.y;
+                if (u >= 0 && u < W && v >= 0 && v < H) {
+                    const size_t pix = (size_t)f * np + (size_t)v * W + u;
+                    wg[j] = wz[pix];
+                    zg[j] = Z[pix];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kWpF; ++j) {
+            const int f = f0 + j;
+            const float w = wg[j];
+            if (!(w > 0.0f)) continue;  // also frames past n and pixels outside the image
+            const int2 d = shift[f];
+            const int u = ku + tx - d.x, v = kv + ty - d.y;
+            float P[3], q[3];
+            backproject((float)u, (float)v, zg[j], in, P);
+            xform(fr->Rf[f], P, q);
+            float uf, vf;
+            int iu, iv;
+            if (!project(in, q, uf, vf, iu, iv)) continue;
+            const long long wk = (long long)rintf(w * kWeightScale);
+            const long long zk = (long long)rintf(q[2] * 1048576.0f);
+            const int lx = iu - wx0, ly = iv - wy0;
+            if ((unsigned)lx < (unsigned)kWpL && (unsigned)ly < (unsigned)kWpL) {
+                atomicAdd(&lw[ly * kWpL + lx], (unsigned long long)wk);
+                atomicAdd(&lz[ly * kWpL + lx], (unsigned long long)(wk * zk));
+            } else {
+                const int64_t t = (int64_t)iv * W + iu;
+                atomicAdd(KW + t, (unsigned long long)wk);
+                atomicAdd(KZ + t, (unsigned long long)(wk * zk));
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kWpL * kWpL; e += blockDim.x) {
+        const unsigned long long a = lw[e];
+        if (a != 0ull) {
+            // only samples inside the image were added, so the pixel is too
+            const int64_t t = (int64_t)(wy0 + e / kWpL) * W + (wx0 + e % kWpL);
+            atomicAdd(KW + t, a);
+            atomicAdd(KZ + t, lz[e]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -721,8 +806,11 @@ static void launch_fuse(const FuseBufs& b, const float* depth, const uint8_t* rg
     }
     launch_color_prep(rgb, n_frames, in.width, in.height, b.cs, b.parts, nullptr, s);
     launch_depth_weight(depth, n_frames, in, params, b.wz, init, s);
-    dim3 grid((unsigned)((np + 255) / 256), (unsigned)n_frames);
-    warp_kernel<<<grid, 256, 0, s>>>(depth, b.wz, n_frames, in, b.fr, b.acc, b.acc + np);
+    // target tiles over the image and kWpE more on each side
+    const int wtx = (in.width + kWpT - 1) / kWpT + 2 * kWpE, wty = (in.height + kWpT - 1) / kWpT + 2 * kWpE;
+    const float z_nom = 0.5f * (params.z_min + params.z_max);
+    warp_kernel<<<(unsigned)(wtx * wty), 256, 0, s>>>(depth, b.wz, n_frames, in, z_nom, wtx, b.fr, b.acc,
+                                                       b.acc + np);
     const int ppw = 256 / n_frames;  // pixels per colour workgroup (n_frames <= kMaxFrames = 64)
     color_kernel<<<(unsigned)((np + ppw - 1) / ppw), 256, 0, s>>>(depth, b.wz, b.cs, b.wb, n_frames, ppw, in,
                                                                   params.occ_rel, b.fr, b.acc, b.acc + np, kf_depth,
