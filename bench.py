@@ -85,6 +85,11 @@ def gpu_keyframes(torch, scsurf, wl, frames, masks=None):
     dev = torch.device("cuda")
     dz = [torch.from_numpy(f[0]).to(dev) for f in frames]
     dc = [torch.from_numpy(f[1]).to(dev) for f in frames]
+    # one untimed pass first (code loading, the library's scratch, the GPU's
+    # clocks leaving idle): the first pass of a fresh process ran about 4x
+    # slower than the next ones
+    for k, f in enumerate(frames):
+        scsurf.kf_fuse(dz[k], dc[k], wl.R[f[2]], wl.t[f[2]], wl.intr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kfs = [scsurf.kf_fuse(dz[k], dc[k], wl.R[f[2]], wl.t[f[2]], wl.intr) for k, f in enumerate(frames)]

@@ -111,7 +111,10 @@ typedef struct {
     const void* packed;  /* device, optional, see above */
 } sc_keyframe;
 
-/* Keyframe fusion parameters (Sec. 3, "Keyframe Fusion"). */
+/* Keyframe fusion parameters (Sec. 3, "Keyframe Fusion").  kf_fuse and
+ * kf_fuse_noalloc require 2^-5 <= z_min <= z_max < 1e6 and non-negative
+ * ratios (SC_EINVAL otherwise): the bound on z_min bounds the depth weight
+ * 1 / Z^2, which the colour weights are held against in 32 bits. */
 typedef struct {
     float z_min, z_max; /* valid depth range, metres */
     float disc_rel;     /* reject a pixel whose 4-neighbour depth differs by more than disc_rel * Z */

@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restri
 {
     __shared__ uint64_t pix[kPrepLH][kPrepLW];
     __shared__ uint64_t hsum[kPrepTH + 4][kPrepTW];  // horizontal binomial of staged rows 3 .. 22
-    __shared__ int lum[kPrepLH][kPrepLW];
+    __shared__ uint8_t lum[kPrepLH][kPrepLW];  // luma <= 255; bytes keep the workgroup under 26.7 KB of LDS (six per CU)
     __shared__ long long red[4][4];
     const int f = blockIdx.y, tile = blockIdx.x;
     if (f >= n || tile >= tiles) return;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void color_prep_kernel(const uint8_t* __restri
             const int i = p % kPrepLW, j = p / kPrepLW;
             const uint32_t px = st[k];
             pix[j][i] = (uint64_t)(px & 255u) | ((uint64_t)((px >> 8) & 255u) << 16) | ((uint64_t)(px >> 16) << 32);
-            lum[j][i] = luma(px);
+            lum[j][i] = (uint8_t)luma(px);
         }
     }
     __syncthreads();
@@ -472,16 +472,17 @@ struct Obs {
 };
 
 // One thread per (keyframe pixel, frame): a workgroup of 256 threads takes
-// ppw = 256 / n pixels, thread t the pixel t / n and the frame t % n.  Every
-// thread of a pixel forms the pixel's depth from the fixed-point
-// accumulators (W* = sum(w), Z* = sum(w z) / sum(w), rounded once to FP32),
-// back-warps it into its frame and stores its observation (or none) in LDS.
-// Then each thread decides for its own observation j and each channel
-// whether it is the lower weighted median: with the observations ordered by
-// (value, frame), j is the first whose cumulative weight reaches half the
-// total exactly when the weight ordered strictly before it is below half
-// and that weight plus its own reaches half; one observation per channel
-// passes, and it writes the channel.
+// ppw = 256 / n pixels, thread t the pixel t / n and the frame t % n.  The
+// first ppw threads form each pixel's depth from the fixed-point
+// accumulators (W* = sum(w), Z* = sum(w z) / sum(w), rounded once to FP32)
+// and its back-projection, once per pixel, in LDS; then every thread
+// back-warps its pixel into its frame and stores its observation (or none)
+// in LDS.  Then each thread decides for its own observation j and each
+// channel whether it is the lower weighted median: with the observations
+// ordered by (value, frame), j is the first whose cumulative weight reaches
+// half the total exactly when the weight ordered strictly before it is below
+// half and that weight plus its own reaches half; one observation per
+// channel passes, and it writes the channel.
 __global__ __launch_bounds__(256) void color_kernel(const float* __restrict__ Z, const float* __restrict__ wz,
                                                     const uint16_t* __restrict__ cs, const double* __restrict__ wb,
                                                     int n, int ppw, sc_intrinsics in, float occ_rel,
@@ -491,53 +492,65 @@ __global__ __launch_bounds__(256) void color_kernel(const float* __restrict__ Z,
                                                     uint8_t* rgba)
 {
     __shared__ Obs obs[256];
+    __shared__ float4 pt[256];  // per pixel: camera point (x, y, Z*) and W* (0: no depth)
     const int W = in.width, H = in.height;
-    const int64_t np = (int64_t)W * H;
+    // np <= 16384^2 < 2^31: pixel indices and their division in 32 bits
+    const int np = W * H;
+    {
+        const int p = (int)blockIdx.x * ppw + (int)threadIdx.x;
+        if ((int)threadIdx.x < ppw && p < np) {
+            float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const long long kw = (long long)KW[p];
+            if (kw > 0) {
+                const float zk = (float)(((double)(long long)KZ[p] / (double)kw) * 0x1p-20);
+                const int v = p / W, u = p - v * W;
+                float P[3];
+                backproject((float)u, (float)v, zk, in, P);
+                e = make_float4(P[0], P[1], P[2], (float)((double)kw / 1024.0));
+            }
+            pt[threadIdx.x] = e;
+        }
+    }
+    __syncthreads();
     const int lp = (int)threadIdx.x / n, i = (int)threadIdx.x - lp * n;
-    const int64_t idx = (int64_t)blockIdx.x * ppw + lp;
+    const int idx = (int)blockIdx.x * ppw + lp;
     const bool mine = lp < ppw && idx < np;
     Obs o;
     o.c[0] = o.c[1] = o.c[2] = 0.0f;
     o.w = 0u;
-    long long kw = 0;
-    float zk = 0.0f;
-    if (mine) {
-        kw = (long long)KW[idx];
-        if (kw > 0) {
-            zk = (float)(((double)(long long)KZ[idx] / (double)kw) * 0x1p-20);
-            const int u = (int)(idx % W), v = (int)(idx / W);
-            float P[3], q[3], uf, vf;
-            int iu, iv;
-            backproject((float)u, (float)v, zk, in, P);
-            xform(fr->Rb[i], P, q);
-            if (project(in, q, uf, vf, iu, iv)) {
-                const size_t base = (size_t)i * np;
-                const float wzi = wz[base + (size_t)iv * W + iu];
-                const float zi = Z[base + (size_t)iv * W + iu];
-                const float x0 = floorf(uf), y0 = floorf(vf);
-                if (wzi > 0.0f && fabsf(zi - q[2]) <= occ_rel * q[2] && x0 >= 0.0f &&
-                    x0 + 1.0f <= (float)(W - 1) && y0 >= 0.0f && y0 + 1.0f <= (float)(H - 1)) {
-                    const float ax = uf - x0, ay = vf - y0;
-                    const int ix = (int)x0, iy = (int)y0;
-                    const float wcs = rintf(((float)wb[i] * wzi) * 1048576.0f);
-                    if (wcs > 0.0f) {
-                        // four channels of 16 bits per pixel, 8-byte aligned
-                        const uint2* C0 = reinterpret_cast<const uint2*>(cs) + base + (size_t)iy * W + ix;
-                        const uint2* C1 = C0 + W;
-                        const uint2 p00 = C0[0], p10 = C0[1], p01 = C1[0], p11 = C1[1];
-                        auto ch = [](uint2 p, int k) {
-                            return (float)(k == 0 ? (p.x & 0xFFFFu) : k == 1 ? (p.x >> 16) : (p.y & 0xFFFFu));
-                        };
+    const float4 e = mine ? pt[lp] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (e.w > 0.0f) {
+        const float P[3] = {e.x, e.y, e.z};
+        float q[3], uf, vf;
+        int iu, iv;
+        xform(fr->Rb[i], P, q);
+        if (project(in, q, uf, vf, iu, iv)) {
+            const size_t base = (size_t)i * np;
+            const float wzi = wz[base + (size_t)iv * W + iu];
+            const float zi = Z[base + (size_t)iv * W + iu];
+            const float x0 = floorf(uf), y0 = floorf(vf);
+            if (wzi > 0.0f && fabsf(zi - q[2]) <= occ_rel * q[2] && x0 >= 0.0f && x0 + 1.0f <= (float)(W - 1) &&
+                y0 >= 0.0f && y0 + 1.0f <= (float)(H - 1)) {
+                const float ax = uf - x0, ay = vf - y0;
+                const int ix = (int)x0, iy = (int)y0;
+                const float wcs = rintf(((float)wb[i] * wzi) * 1048576.0f);
+                if (wcs > 0.0f) {
+                    // four channels of 16 bits per pixel, 8-byte aligned
+                    const uint2* C0 = reinterpret_cast<const uint2*>(cs) + base + (size_t)iy * W + ix;
+                    const uint2* C1 = C0 + W;
+                    const uint2 p00 = C0[0], p10 = C0[1], p01 = C1[0], p11 = C1[1];
+                    auto ch = [](uint2 p, int k) {
+                        return (float)(k == 0 ? (p.x & 0xFFFFu) : k == 1 ? (p.x >> 16) : (p.y & 0xFFFFu));
+                    };
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const float c00 = ch(p00, k), c10 = ch(p10, k);
-                            const float c01 = ch(p01, k), c11 = ch(p11, k);
-                            const float top = c00 + ax * (c10 - c00);
-                            const float bot = c01 + ax * (c11 - c01);
-                            o.c[k] = top + ay * (bot - top);
-                        }
-                        o.w = (uint32_t)wcs;
+                    for (int k = 0; k < 3; ++k) {
+                        const float c00 = ch(p00, k), c10 = ch(p10, k);
+                        const float c01 = ch(p01, k), c11 = ch(p11, k);
+                        const float top = c00 + ax * (c10 - c00);
+                        const float bot = c01 + ax * (c11 - c01);
+                        o.c[k] = top + ay * (bot - top);
                     }
+                    o.w = (uint32_t)wcs;
                 }
             }
         }
@@ -554,7 +567,7 @@ __global__ __launch_bounds__(256) void color_kernel(const float* __restrict__ Z,
         for (int k = 0; k < 3; ++k)
             if (ol.c[k] < o.c[k] || (ol.c[k] == o.c[k] && l < i)) below[k] += ol.w;
     }
-    uint8_t* out = rgba + 4 * idx;
+    uint8_t* out = rgba + 4 * (size_t)idx;
     if (total == 0) {
         // no frame observed the pixel (or it has no depth)
         if (i == 0) {
@@ -565,8 +578,8 @@ __global__ __launch_bounds__(256) void color_kernel(const float* __restrict__ Z,
         return;
     }
     if (i == 0) {
-        Ws[idx] = (float)((double)kw / 1024.0);
-        Zs[idx] = zk;
+        Ws[idx] = e.w;
+        Zs[idx] = e.z;
         out[3] = 255;
     }
     if (o.w == 0u) return;
@@ -650,6 +663,15 @@ static sc_status ws_reserve(size_t np, size_t frames, size_t parts)
         g_ws.cap_parts = parts;
     }
     return SC_OK;
+}
+
+// Fusion parameters a fusion accepts: z_min at least 2^-5 m keeps every
+// depth weight w_z <= 1 / z_min^2 at most 2^10, so a colour weight on the
+// 2^-20 grid stays below 2^31 and fits the 32 bits it is held in.
+static bool fuse_params_valid(const sc_fuse_params* p)
+{
+    return p && p->z_min >= 0x1p-5f && p->z_max >= p->z_min && p->z_max < 1e6f && p->disc_rel >= 0.0f &&
+           p->occ_rel >= 0.0f;
 }
 
 static bool intr_valid(const sc_intrinsics* in)
@@ -903,7 +925,7 @@ sc_status kf_fuse(const float* depth, const uint8_t* rgb, const sc_pose* poses, 
                   uint8_t* kf_rgba, void* stream)
 {
     if (!depth || !rgb || !poses || n_frames <= 0 || n_frames > kMaxFrames || ref < 0 || ref >= n_frames ||
-        !intr_valid(intr) || !params || !kf_depth || !kf_weight || !kf_rgba)
+        !intr_valid(intr) || !fuse_params_valid(params) || !kf_depth || !kf_weight || !kf_rgba)
         return SC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const sc_intrinsics in = *intr;
@@ -921,7 +943,7 @@ sc_status kf_fuse_noalloc(const float* depth, const uint8_t* rgb, const sc_pose*
                           uint8_t* kf_rgba, void* stream)
 {
     if (!depth || !rgb || !poses || n_frames <= 0 || n_frames > kMaxFrames || ref < 0 || ref >= n_frames ||
-        !intr_valid(intr) || !params || !kf_depth || !kf_weight || !kf_rgba)
+        !intr_valid(intr) || !fuse_params_valid(params) || !kf_depth || !kf_weight || !kf_rgba)
         return SC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const sc_intrinsics in = *intr;

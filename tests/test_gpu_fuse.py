@@ -146,3 +146,14 @@ def test_kf_fuse_rejects_bad_arguments(c1):
     with pytest.raises(scsurf.ScError):
         scsurf.kf_fuse(big, torch.zeros((65, 8, 8, 3), dtype=torch.uint8, device="cuda"),
                        np.repeat(np.eye(3)[None], 65, 0), np.zeros((65, 3)), synth.Intrinsics(8, 8, 5, 5, 3.5, 3.5))
+    # fusion parameters outside the accepted range: z_min below 2^-5 m (the
+    # colour weights' 32-bit bound), z_max below z_min, a negative ratio
+    for p in (scsurf.fuse_params(z_min=0.01), scsurf.fuse_params(z_min=1.0, z_max=0.5),
+              scsurf.fuse_params(occ_rel=-0.1), scsurf.fuse_params(z_min=float("nan"))):
+        with pytest.raises(scsurf.ScError) as e:
+            scsurf.kf_fuse(zz, cc, wl.R, wl.t, wl.intr, params=p)
+        assert e.value.status == scsurf.SC_EINVAL
+        with pytest.raises(scsurf.ScError):
+            scsurf.kf_fuse_noalloc(zz, cc, wl.R, wl.t, wl.intr, params=p)
+    # the smallest accepted z_min fuses
+    scsurf.kf_fuse(zz, cc, wl.R, wl.t, wl.intr, params=scsurf.fuse_params(z_min=2.0 ** -5))
