@@ -228,14 +228,17 @@ def kernel_variant(sched):
     return "batch_main_wave_kernel<RGBA8>" if vpl == 8 else f"batch_main_group_kernel<RGBA8,{vpl}>"
 
 
-def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20, stream_radius=None, pool_blocks=None):
+def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20, stream_radius=None, pool_blocks=None,
+                 integrate_every=1):
     """The online loop on the corridor workload: frames fused into keyframes of
     five, each keyframe integrated at its drifting estimate, a pose-graph
     update every `every` keyframes re-integrating the Eq. 3 window of m,
     then the final pass.  Frames are rendered to the device first; the loop
     is timed.  With a stream radius the volume streams (a pool of
     `pool_blocks`, batches of 4 operations) and the bytes moved between the
-    GPU and the host are reported, in all and per pose-graph update."""
+    GPU and the host are reported, in all and per pose-graph update.  With
+    integrate_every > 1 finished keyframes are integrated that many at a
+    time by the batched integration (and before each update)."""
     from paper_1709_03763_amd import online
 
     wl = synth.workload(5)
@@ -262,7 +265,8 @@ def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20, stream_rad
     pool = pool_blocks if streamed else 1 << 21
     vol = scsurf.Volume(wl.volume.voxel_size, wl.volume.trunc, 1 << 22, pool, scsurf.COLOR_RGBA8,
                         max_batch_ops=4 if streamed else 512)
-    sess = online.OnlineSession(vol, wl.intr, wl.kappa, m, stream_radius=stream_radius)
+    sess = online.OnlineSession(vol, wl.intr, wl.kappa, m, stream_radius=stream_radius,
+                                integrate_every=integrate_every)
     per_update = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -280,7 +284,7 @@ def online_stage(torch, scsurf, synth, n_frames=1000, every=20, m=20, stream_rad
     n_blocks = vol.check_error()
     out = {"frames": len(idx), "keyframes": len(groups), "updates": len(updates), "m": m,
            "final_pass_keyframes": len(final), "reintegrated_keyframes": sess.reintegrated, "blocks": n_blocks,
-           "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1)}
+           "seconds": round(dt, 4), "frames_per_s": round(len(idx) / dt, 1), "integrate_every": integrate_every}
     if streamed:
         st = vol.stream_stats()
         out.update({"pool_blocks": pool, "stream_radius_m": stream_radius, "device_blocks": st[0],
@@ -608,6 +612,20 @@ def main():
     integrate_s = time.perf_counter() - t0
     n_blocks = vol.check_error()
     log(f"integrated {n_kf} keyframes in {integrate_s * 1e3:.1f} ms; {n_blocks} blocks")
+    # the same 200 integrations in one batched call, into a fresh volume (a
+    # first call untimed), checked equal to the sequential volume's blocks
+    vb = scsurf.Volume(0.01, 0.04, 1 << 21, 1 << 21, scsurf.COLOR_RGBA8, max_batch_ops=512)
+    vb.integrate_batch(kfs, wl.intr, R, t)
+    vb.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vb.integrate_batch(kfs, wl.intr, R, t)
+    torch.cuda.synchronize()
+    integrate_batch_s = time.perf_counter() - t0
+    if vb.check_error() != n_blocks:
+        raise RuntimeError("batched integration allocated a different block count")
+    vb.close()
+    log(f"integrated {n_kf} keyframes in one batched call in {integrate_batch_s * 1e3:.2f} ms")
     mode = scsurf.SEL_ALL_ORDERED
     kset = scsurf.KeyframeSet(kfs)  # marshalled once, reused by every update
     state = [A, B]  # state[0] = current integration poses, state[1] = the other set
@@ -720,6 +738,9 @@ def main():
         log(f"online loop (corridor, {online_res['frames']} frames): {online_res['frames_per_s']} frames/s, "
             f"{online_res['reintegrated_keyframes']} keyframe re-integrations incl. a final pass of "
             f"{online_res['final_pass_keyframes']}")
+        online_res["held_integrations"] = online_stage(torch, scsurf, synth, integrate_every=20)
+        log(f"online loop, keyframes integrated 20 at a time: {online_res['held_integrations']['frames_per_s']} "
+            f"frames/s")
         online_res["streaming"] = online_stage(torch, scsurf, synth, stream_radius=3.0,
                                                pool_blocks=online_res["blocks"] // 4)
         log(f"online loop with streaming (pool of a quarter of the field, 3 m sphere): {online_res['streaming']}")
@@ -807,6 +828,7 @@ def main():
                    # read, one keyframe of depth, weight and RGBA8 (12 B) written, per pixel
                    "kf_fuse_hbm_frac": round(n_kf * H * Wd * (wl.kappa * 7 + 12) / fuse_s / 1e9 / HBM_PEAK_GBS, 5),
                    "integrate_keyframes_per_s": round(n_kf / integrate_s, 1),
+                   "integrate_batch_keyframes_per_s": round(n_kf / integrate_batch_s, 1),
                    # plain integration of the 200 keyframes into the empty volume: blocks written once
                    # (read and write at the method's 12 B per voxel) plus each keyframe read once
                    "integrate_hbm_frac": round((n_blocks * 512 * 2 * VOXEL_BYTES + n_kf * H * Wd * KF_PIXEL_BYTES)

@@ -251,6 +251,16 @@ sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_
 sc_status tsdf_integrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
                          void* stream);
 
+/* Integrates n_kf keyframes at poses T (host, n_kf), in order: the same
+ * result, bit for bit, as n_kf tsdf_integrate calls in that order, from the
+ * batched path (candidate blocks of all of them at once, then one
+ * persistent launch applying each voxel's integrations in order; chunks of
+ * the volume's max_batch_ops).  All keyframes must share width and height.
+ * For callers that can hold several finished keyframes before the volume
+ * must show them (the online loop between two pose-graph updates). */
+sc_status tsdf_integrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                               const sc_pose* T, void* stream);
+
 /* De-integrates one keyframe at pose T, Eq. (2) (Sec. 4.3):
  *   W' = W - w, D' = (D W - d w) / W', C' = (C W - c w) / W',
  * with W' = 0 giving the empty voxel (0, 0, 0).  Never allocates. */

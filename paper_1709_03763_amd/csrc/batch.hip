@@ -1751,6 +1751,31 @@ sc_status reintegrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
     return SC_OK;
 }
 
+sc_status tsdf_integrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
+                               const sc_pose* T, void* stream)
+{
+    if (!vol || !kfs || n_kf <= 0 || !T || !intr_valid(intr)) return SC_EINVAL;
+    for (int i = 0; i < n_kf; ++i)
+        if (!keyframe_ok(&kfs[i])) return SC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int cap = vol->p.max_batch_ops;
+    for (int done = 0; done < n_kf;) {
+        const int cnt = std::min(cap, n_kf - done);
+        OpDesc* ops = stage_begin(vol);
+        if (!ops) return SC_EDEVICE;
+        for (int j = 0; j < cnt; ++j) {
+            const int k = done + j;
+            make_op(vol, &kfs[k], intr, &T[k], +1, k, &ops[j]);
+            rec_for_integration(vol, &kfs[k], intr, &T[k], vol->sched.compact == 4, &ops[j]);
+        }
+        const sc_status st = run_chunk(vol, ops, cnt, intr, s);
+        rec_commit(vol);
+        if (st != SC_OK) return st;
+        done += cnt;
+    }
+    return hipGetLastError() == hipSuccess ? SC_OK : SC_EDEVICE;
+}
+
 // Copies the state of `src` into `dst` (same parameters), on stream s.
 static sc_status clone_state(sc_volume* dst, sc_volume* src, hipStream_t s)
 {

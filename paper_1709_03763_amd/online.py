@@ -10,7 +10,10 @@ keyframe's first view falls below a threshold (overlap, counted on the GPU
 by `sc_overlap`); a keyframe never exceeds 64 frames.  A complete
 keyframe is fused (Eq. 1 and the colour median, `kf_fuse`), packed, and
 integrated into the volume at its current pose estimate, which becomes its
-integration pose.  A pose-graph update supplies new estimates for every
+integration pose (with integrate_every = k > 1, finished keyframes are held
+and integrated k at a time by one batched call, `tsdf_integrate_batch`, and
+before every pose-graph update and the final pass: the same volume, bit for
+bit, at those points).  A pose-graph update supplies new estimates for every
 keyframe so far; the update re-integrates the selected keyframes (by default
 the m most-moved consecutive keyframes, Eq. 3) in one batched pass, and
 only those take the new pose as their integration pose.  The final pass
@@ -33,9 +36,13 @@ class OnlineSession:
     def __init__(self, vol: scsurf.Volume, intr, kappa: int, m: int, mode: int = scsurf.SEL_EQ3, stream=None,
                  strategy: str = "const", max_trans: float = 0.1, max_rot: float = 0.0873,
                  min_overlap: float = 0.8, z_min: float = 0.3, z_max: float = 4.0,
-                 stream_radius: float | None = None):
+                 stream_radius: float | None = None, integrate_every: int = 1):
         if kappa < 1 or m < 1:
             raise ValueError("kappa and m must be positive")
+        if integrate_every < 1:
+            raise ValueError("integrate_every must be positive")
+        if integrate_every > 1 and stream_radius is not None:
+            raise ValueError("held integrations and streaming do not mix: streaming moves the sphere per keyframe")
         if strategy not in ("const", "dist", "overlap"):
             raise ValueError(f"unknown keyframe strategy {strategy!r}")
         self.vol, self.intr, self.kappa, self.m, self.mode, self.stream = vol, intr, kappa, m, mode, stream
@@ -55,6 +62,8 @@ class OnlineSession:
         self.t_new = np.zeros((0, 3))
         self._kset = None
         self.reintegrated = 0  # keyframe re-integrations performed (de + re counted once)
+        self.integrate_every = integrate_every
+        self._pending: list[int] = []  # finished keyframes not yet integrated
 
     @property
     def n_keyframes(self) -> int:
@@ -108,14 +117,28 @@ class OnlineSession:
         self._depth, self._rgb, self._R, self._t = [], [], [], []
         if self.stream_radius is not None:
             self.vol.stream_out(t[0], self.stream_radius, stream=self.stream)
-        self.vol.integrate(kf, self.intr, R[0], t[0], stream=self.stream)
+        if self.integrate_every == 1:
+            self.vol.integrate(kf, self.intr, R[0], t[0], stream=self.stream)
+        else:
+            self._pending.append(self.n_keyframes)
         self.keyframes.append(kf)
         self._kset = None
         self.R_int = np.concatenate([self.R_int, R[:1]])
         self.t_int = np.concatenate([self.t_int, t[:1]])
         self.R_new = np.concatenate([self.R_new, R[:1]])
         self.t_new = np.concatenate([self.t_new, t[:1]])
+        if len(self._pending) >= self.integrate_every:
+            self.integrate_pending()
         return self.n_keyframes - 1
+
+    def integrate_pending(self):
+        """Integrates the finished keyframes held so far (integrate_every > 1)
+        at their integration poses, in order, in one batched call."""
+        if self._pending:
+            idx = self._pending
+            self.vol.integrate_batch([self.keyframes[i] for i in idx], self.intr, self.R_int[idx], self.t_int[idx],
+                                     stream=self.stream)
+            self._pending = []
 
     def _keyframe_set(self):
         if self._kset is None or len(self._kset) != self.n_keyframes:
@@ -133,6 +156,7 @@ class OnlineSession:
         self.R_new, self.t_new = R.copy(), t.copy()
         if self.n_keyframes == 0:
             return []
+        self.integrate_pending()
         if self.stream_radius is not None:
             # Sec. 4.3: the sphere around the first selected keyframe's
             # integration pose; what the update needs beyond it streams in
@@ -150,6 +174,7 @@ class OnlineSession:
         whose integration pose differs from its latest estimate, most-moved
         first.  Returns their indices."""
         self.flush()
+        self.integrate_pending()
         if self.n_keyframes == 0:
             return []
         order, (Ri, ti) = self.vol.reintegrate_batch(self._keyframe_set(), self.intr, (self.R_int, self.t_int),

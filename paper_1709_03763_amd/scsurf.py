@@ -65,6 +65,7 @@ class sc_schedule(ctypes.Structure):
 
 EXPORTS = ["sc_version", "sc_volume_create", "sc_volume_destroy", "sc_volume_reset", "sc_volume_query",
            "sc_volume_export", "sc_depth_weight", "sc_color_prep", "kf_fuse", "kf_fuse_noalloc", "hash_alloc", "tsdf_integrate",
+           "tsdf_integrate_batch",
            "tsdf_deintegrate", "sc_select", "sc_select_dist", "sc_relative_motion", "reintegrate_batch",
            "reintegrate_plain",
            "sc_set_schedule", "sc_get_schedule", "sc_autotune", "sc_autotune_clear", "sc_batch_timing", "sc_batch_timing_read",
@@ -422,6 +423,15 @@ class Volume:
         k = kf.c()
         check(lib().tsdf_integrate(self._h, ctypes.byref(k), ctypes.byref(intrinsics(intr)), ctypes.byref(pose(R, t)),
                                    stream_handle(stream)), "tsdf_integrate")
+
+    def integrate_batch(self, kfs, intr, R, t, stream=None):
+        """Integrates keyframes at poses (R (n,3,3), t (n,3)) in order, in one
+        batched pass: the same volume as integrate() called on each in turn."""
+        kset = keyframes(kfs)
+        T = poses(R, t)
+        self._check_keyframes(kset, intr, T)
+        check(lib().tsdf_integrate_batch(self._h, kset.arr, len(kset), ctypes.byref(intrinsics(intr)), T,
+                                         stream_handle(stream)), "tsdf_integrate_batch")
 
     def deintegrate(self, kf: Keyframe, intr, R, t, stream=None):
         self._check_keyframes(KeyframeSet([kf]), intr)

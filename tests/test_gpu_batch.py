@@ -515,3 +515,48 @@ def test_recorded_deintegration_candidates(scene, sched):
     compare_fields(a, ref.export())
     for v in vols:
         v.close()
+
+
+@pytest.mark.parametrize("f32,packed", [(False, False), (False, True), (True, False)])
+def test_integrate_batch_equals_sequential(scene, f32, packed):
+    """tsdf_integrate_batch applies each voxel's integrations in order: the
+    volume equals that of integrate() on each keyframe in turn, bit for bit,
+    here over chunks of 3 operations (max_batch_ops 3, 8 keyframes); the
+    oracle's field after the same integrations bounds both.  A pose-graph
+    update afterwards (whose de-integrations take the touched-block records
+    the batched integrations left) keeps them equal."""
+    wl, kfs, R, t = scene
+    _say(f"integrate_batch f32={f32} packed={packed}")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t, f32, max_batch_ops=3)
+    if packed:
+        dks = [scsurf.keyframe_pack(k) for k in dks]
+    mode = scsurf.COLOR_F32 if f32 else scsurf.COLOR_RGBA8
+    vb = scsurf.Volume(S, MU, 1 << 17, 1 << 16, color_mode=mode, max_batch_ops=3)
+    vb.integrate_batch(dks, wl.intr, R, t)
+    vb.check_error()
+    gs, gb = vol.export_sorted(), vb.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(gb[key], gs[key], err_msg=key)
+    compare_fields(gb, ref.export(), exact_color=not f32)
+    Rn, tn = synth.perturb_all(R, t, 0.02, 1.0, 12)
+    o1, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 4, scsurf.SEL_EQ3)
+    o2, _ = vb.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 4, scsurf.SEL_EQ3)
+    assert o1 == o2
+    vol.check_error()
+    vb.check_error()
+    gs, gb = vol.export_sorted(), vb.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(gb[key], gs[key], err_msg=key)
+
+
+def test_integrate_batch_rejects_bad_arguments(scene):
+    wl, kfs, R, t = scene
+    dks = [_dev_kf(k) for k in kfs[:2]]
+    vb = scsurf.Volume(S, MU, 1 << 16, 1 << 14)
+    with pytest.raises(ValueError):
+        vb.integrate_batch(dks, wl.intr, R[:1], t[:1])
+    with pytest.raises(scsurf.ScError) as e:
+        scsurf.check(scsurf.lib().tsdf_integrate_batch(vb._h, scsurf.KeyframeSet(dks).arr, 0,
+                                                       scsurf.ctypes.byref(scsurf.intrinsics(wl.intr)),
+                                                       scsurf.poses(R[:2], t[:2]), None), "tsdf_integrate_batch")
+    assert e.value.status == scsurf.SC_EINVAL

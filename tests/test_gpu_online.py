@@ -43,13 +43,17 @@ def _scenario():
     return wl, groups, frame_poses, updates
 
 
-def test_online_session_matches_oracle():
+@pytest.mark.parametrize("integrate_every", [1, 3])
+def test_online_session_matches_oracle(integrate_every):
+    """integrate_every 3: keyframes integrated three at a time by the batched
+    integration, and before each update (held groups of 1 to 3)."""
     assert torch.cuda.is_available(), "GPU tests need a device"
     wl, groups, frame_poses, updates = _scenario()
     z, rgb = synth.frames(wl, np.arange(wl.n_frames), device="cuda")
-    _say(f"online session: {len(groups)} keyframes of {KAPPA} frames, update every {EVERY}, m = {M}")
+    _say(f"online session: {len(groups)} keyframes of {KAPPA} frames, update every {EVERY}, m = {M}, "
+         f"integrations held {integrate_every}")
     vol = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
-    sess = online.OnlineSession(vol, wl.intr, KAPPA, M)
+    sess = online.OnlineSession(vol, wl.intr, KAPPA, M, integrate_every=integrate_every)
     got_orders = []
     for f in range(wl.n_frames):
         R, t = frame_poses[f]

@@ -108,3 +108,11 @@ def test_unknown_strategy_is_rejected():
     import pytest
     with pytest.raises(ValueError):
         online.OnlineSession(None, None, 5, 1, strategy="dvo")
+
+
+def test_held_integrations_are_validated():
+    import pytest
+    with pytest.raises(ValueError):
+        online.OnlineSession(None, None, 5, 3, integrate_every=0)
+    with pytest.raises(ValueError):
+        online.OnlineSession(None, None, 5, 3, integrate_every=4, stream_radius=2.0)
