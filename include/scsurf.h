@@ -251,13 +251,17 @@ sc_status hash_alloc(sc_volume* vol, const int32_t* block_xyz, int64_t n, int32_
 sc_status tsdf_integrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrinsics* intr, const sc_pose* T,
                          void* stream);
 
-/* Integrates n_kf keyframes at poses T (host, n_kf), in order: the same
- * result, bit for bit, as n_kf tsdf_integrate calls in that order, from the
- * batched path (candidate blocks of all of them at once, then one
+/* Integrates n_kf keyframes at poses T (host, n_kf), in order, each by the
+ * running weighted average of Sec. 3 (the update of tsdf_integrate above):
+ * the same result, bit for bit, as n_kf tsdf_integrate calls in that order,
+ * from the batched path (candidate blocks of all of them at once, then one
  * persistent launch applying each voxel's integrations in order; chunks of
- * the volume's max_batch_ops).  All keyframes must share width and height.
- * For callers that can hold several finished keyframes before the volume
- * must show them (the online loop between two pose-graph updates). */
+ * the volume's max_batch_ops).  All keyframes must share width and height
+ * (SC_EINVAL otherwise, and on a null pointer or n_kf <= 0, with nothing
+ * enqueued).  For the pipeline of Sec. 4.1 when several finished keyframes
+ * may wait before the volume must show them (until the next pose-graph
+ * update).  kfs and T are read during the call; the keyframes' device
+ * buffers must stay valid until the work on `stream` completes. */
 sc_status tsdf_integrate_batch(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf, const sc_intrinsics* intr,
                                const sc_pose* T, void* stream);
 
