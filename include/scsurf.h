@@ -256,9 +256,9 @@ sc_status tsdf_integrate(sc_volume* vol, const sc_keyframe* kf, const sc_intrins
  * the same result, bit for bit, as n_kf tsdf_integrate calls in that order,
  * from the batched path (candidate blocks of all of them at once, then one
  * persistent launch applying each voxel's integrations in order; chunks of
- * the volume's max_batch_ops).  All keyframes must share width and height
- * (SC_EINVAL otherwise, and on a null pointer or n_kf <= 0, with nothing
- * enqueued).  For the pipeline of Sec. 4.1 when several finished keyframes
+ * the volume's max_batch_ops).  Every keyframe is intr's width x height.
+ * SC_EINVAL on a null pointer, n_kf <= 0 or bad intrinsics, with nothing
+ * enqueued.  For the pipeline of Sec. 4.1 when several finished keyframes
  * may wait before the volume must show them (until the next pose-graph
  * update).  kfs and T are read during the call; the keyframes' device
  * buffers must stay valid until the work on `stream` completes. */
