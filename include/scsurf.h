@@ -327,7 +327,9 @@ sc_status reintegrate_plain(sc_volume* vol, const sc_keyframe* kfs, int32_t n_kf
  *                collected in a ring and updated 64 at a time, and the block
  *                geometry computed once per (block, operation).
  * Every schedule gives identical bits.  sc_set_schedule validates and stores
- * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back. */
+ * it in the volume (SC_EINVAL otherwise); sc_get_schedule reads it back.  A
+ * new volume holds {8, 2, 8, 4} (RGBA8 colour) or {8, 4, 4, 0} (FP32
+ * colour). */
 typedef struct {
     int32_t vpl;
     int32_t waves_per_wg;

@@ -609,9 +609,19 @@ sc_status sc_volume_create(const sc_volume_params* p, sc_volume** out)
                                                                                256, 0);
         vol->plain_wgs = (e == hipSuccess) ? std::max(1, std::min(n, 4)) : 1;
     }
+    // default voxel-pass schedule: RGBA8 volumes take the ring pass (two
+    // wavefronts per workgroup, eight workgroups per CU), the fastest measured
+    // on the re-integration benchmark, which also keeps touched-block records
+    // for later de-integrations; FP32-colour volumes the per-lane pass
     vol->sched.vpl = 8;
-    vol->sched.waves_per_wg = 4;
-    vol->sched.wgs_per_cu = 4;
+    if (p->color_mode == SC_COLOR_RGBA8) {
+        vol->sched.waves_per_wg = 2;
+        vol->sched.wgs_per_cu = 8;
+        vol->sched.compact = 4;
+    } else {
+        vol->sched.waves_per_wg = 4;
+        vol->sched.wgs_per_cu = 4;
+    }
     VolDev& d = vol->dev;
     d.bucket_mask = (uint32_t)(p->n_buckets - 1);
     d.max_blocks = (int32_t)p->max_blocks;
