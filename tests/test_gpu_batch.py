@@ -560,3 +560,29 @@ def test_integrate_batch_rejects_bad_arguments(scene):
                                                        scsurf.ctypes.byref(scsurf.intrinsics(wl.intr)),
                                                        scsurf.poses(R[:2], t[:2]), None), "tsdf_integrate_batch")
     assert e.value.status == scsurf.SC_EINVAL
+
+
+@pytest.mark.parametrize("sched", [(8, 2, 8, 4), (8, 2, 8, 3), (8, 1, 8, 2)])
+def test_f32_colour_compact_schedules(scene, sched):
+    """FP32-colour volumes on the LDS-staged passes (the ring pass, the
+    pipelined pass, the compact pass): the oracle's field, and the same bits
+    as the per-lane pass {8, 4, 4, 0}."""
+    wl, kfs, R, t = scene
+    Rn, tn = synth.perturb_all(R, t, 0.03, 1.5, 5)
+    _say(f"f32 colour, schedule {sched}")
+    vol, ref, dks, okf = _integrated(wl, kfs, R, t, f32=True)
+    vol.set_schedule(*sched)
+    order, _ = vol.reintegrate_batch(dks, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    _oracle_update(ref, okf, wl, R, t, Rn, tn, order)
+    vol.check_error()
+    got = vol.export_sorted()
+    compare_fields(got, ref.export(), exact_color=False)
+    base, _, dkb, _ = _integrated(wl, kfs, R, t, f32=True)
+    base.set_schedule(8, 4, 4, 0)
+    base.reintegrate_batch(dkb, wl.intr, (R, t), (Rn, tn), 8, scsurf.SEL_ALL_ORDERED)
+    base.check_error()
+    exp = base.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(got[key], exp[key], err_msg=key)
+    vol.close()
+    base.close()
