@@ -189,3 +189,30 @@ def test_streamed_corridor_session_equals_resident():
     assert st[0] <= cap and st[0] + st[1] == total
     _equal(vol.export_sorted(with_host=True), ref)
     vol.close()
+
+
+def test_streamed_batched_integration_equals_resident(room):
+    """tsdf_integrate_batch on a streamed volume whose pool holds 70 % of the
+    field (chunks of two operations, blocks evicted to the host as the pool
+    runs short) ends with the field of sequential integrations on a resident
+    volume, device pool and host store together."""
+    wl, kfs, R, t, Rn, tn = room
+    dks = [scsurf.keyframe_pack(_dev_kf(k)) for k in kfs]
+    res = scsurf.Volume(S, MU, 1 << 17, 1 << 16)
+    for k in range(len(dks)):
+        res.integrate(dks[k], wl.intr, R[k], t[k])
+    res.check_error()
+    ref = res.export_sorted()
+    total = len(ref["blocks"])
+    res.close()
+    cap = int(total * 0.7)
+    _say(f"{total} blocks; batched integration into a streamed volume with a pool of {cap}")
+    vol = scsurf.Volume(S, MU, 1 << 17, cap, max_batch_ops=2)
+    vol.stream_enable(True)
+    vol.integrate_batch(dks, wl.intr, R, t)
+    vol.check_error()
+    st = vol.stream_stats()
+    _say(f"device {st[0]}, host {st[1]}")
+    assert st[0] <= cap and st[0] + st[1] == total
+    _equal(vol.export_sorted(with_host=True), ref)
+    vol.close()
