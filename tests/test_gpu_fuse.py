@@ -157,3 +157,48 @@ def test_kf_fuse_rejects_bad_arguments(c1):
             scsurf.kf_fuse_noalloc(zz, cc, wl.R, wl.t, wl.intr, params=p)
     # the smallest accepted z_min fuses
     scsurf.kf_fuse(zz, cc, wl.R, wl.t, wl.intr, params=scsurf.fuse_params(z_min=2.0 ** -5))
+
+
+def _plane_frames(W, H, n, seed):
+    """n frames of the tilted world plane z = 1.5 + 0.1 x seen from cameras
+    a few millimetres and tenths of a degree apart (camera to world poses),
+    with a colour pattern fixed to the plane, 3 % holes and quantised depth
+    noise: every frame agrees with the others up to the noise, so the warps
+    land on many shared keyframe pixels."""
+    rng = np.random.default_rng(seed)
+    intr = synth.Intrinsics(W, H, 0.9 * W, 0.9 * W, 0.5 * (W - 1), 0.5 * (H - 1))
+    R = np.empty((n, 3, 3))
+    t = np.empty((n, 3))
+    z = np.zeros((n, H, W), np.float32)
+    rgb = np.zeros((n, H, W, 3), np.uint8)
+    uu, vv = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    for f in range(n):
+        Rf, tf = synth.se3_exp(np.concatenate([rng.normal(0, 0.004, 3), rng.normal(0, np.radians(0.3), 3)]))
+        R[f], t[f] = Rf, tf
+        d = np.stack([(uu - intr.cx) / intr.fx, (vv - intr.cy) / intr.fy, np.ones_like(uu)], -1) @ Rf.T
+        s = (1.5 + 0.1 * tf[0] - tf[2]) / (d[..., 2] - 0.1 * d[..., 0])
+        p = tf + s[..., None] * d
+        zf = np.round(s * 4096.0) / 4096.0 + 0.0005 * rng.standard_normal((H, W))
+        zf[rng.random((H, W)) < 0.03] = 0.0
+        z[f] = zf.astype(np.float32)
+        pat = np.stack([128 + 100 * np.sin(7 * p[..., 0]), 128 + 100 * np.cos(5 * p[..., 1]),
+                        128 + 60 * np.sin(3 * (p[..., 0] + p[..., 1]))], -1)
+        rgb[f] = np.clip(pat + rng.normal(0, 3, pat.shape), 0, 255).astype(np.uint8)
+    return intr, z, rgb, R, t
+
+
+@pytest.mark.parametrize("W,H,n", [(5, 4, 2), (16, 16, 1), (70, 19, 3), (641, 83, 2), (33, 40, 33)])
+def test_kf_fuse_ragged_sizes(W, H, n):
+    """Whole fusions at sizes that are no multiple of any tile (the warp's
+    16 x 16 target tiles on the extended grid, the 64 x 16 tiles of the
+    colour prep and depth weight, colour workgroups of 256 / n pixels) and
+    33 frames (poses in two argument chunks): equal to the oracle."""
+    _say(f"kf_fuse {W}x{H}, {n} frames")
+    intr, z, rgb, R, t = _plane_frames(W, H, n, W * 31 + H * 7 + n)
+    kf = scsurf.kf_fuse(torch.from_numpy(z).cuda(), torch.from_numpy(rgb).cuda(), R, t, intr)
+    ref = oracle.kf_fuse(z, rgb, intr, R, t)
+    np.testing.assert_array_equal(kf.weight.cpu().numpy(), ref["weight"])
+    np.testing.assert_array_equal(kf.depth.cpu().numpy(), ref["depth"])
+    np.testing.assert_array_equal(kf.color.cpu().numpy(), ref["color"])
+    if W * H >= 1000:
+        assert (ref["weight"] > 0).mean() > 0.5
