@@ -117,3 +117,23 @@ def test_whole_field_after_updates(headline):
         for j in order:
             assert ref.integrate(kfs[j], wl.intr, Tn[0][j], Tn[1][j]) == oracle.OK
         compare_fields(vol.export_sorted(), ref.export())
+
+
+def test_batched_integration_equals_sequential(headline):
+    """tsdf_integrate_batch of the 200 packed keyframes (one chunk of 200
+    integrations) leaves the whole field of 200 tsdf_integrate calls in the
+    same order, bit for bit, at the benchmark's size."""
+    wl, kfs, dks, vol, A, B = headline
+    vs = scsurf.Volume(S, MU, 1 << 21, 1 << 21, scsurf.COLOR_RGBA8, max_batch_ops=512)
+    for j in range(N_KF):
+        vs.integrate(dks[j], wl.intr, A[0][j], A[1][j])
+    vs.check_error()
+    vb = scsurf.Volume(S, MU, 1 << 21, 1 << 21, scsurf.COLOR_RGBA8, max_batch_ops=512)
+    vb.integrate_batch(dks, wl.intr, *A)
+    n = vb.check_error()
+    _say(f"batched integration: {n} blocks")
+    gs, gb = vs.export_sorted(), vb.export_sorted()
+    for key in ("blocks", "D", "W", "C"):
+        np.testing.assert_array_equal(gb[key], gs[key], err_msg=key)
+    vs.close()
+    vb.close()
