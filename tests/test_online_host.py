@@ -116,3 +116,56 @@ def test_held_integrations_are_validated():
         online.OnlineSession(None, None, 5, 3, integrate_every=0)
     with pytest.raises(ValueError):
         online.OnlineSession(None, None, 5, 3, integrate_every=4, stream_radius=2.0)
+
+
+class _CallLog:
+    """A volume stand-in that records the session's calls."""
+
+    def __init__(self):
+        self.calls = []
+
+    def integrate(self, kf, intr, R, t, stream=None):
+        self.calls.append(("integrate", kf))
+
+    def integrate_batch(self, kfs, intr, R, t, stream=None):
+        assert len(kfs) == len(R) == len(t)
+        self.calls.append(("integrate_batch", list(kfs)))
+
+    def reintegrate_batch(self, kset, intr, T_int, T_new, m, mode, stream=None):
+        self.calls.append(("update", len(kset)))
+        return [], T_new
+
+
+def _held_session(monkeypatch, every, n_frames, updates_at, kappa=2):
+    """Frames through a session whose fusion and packing are stubbed (the
+    keyframe is its index), with pose-graph updates after the given numbers
+    of keyframes; returns the recorded volume calls."""
+    import torch
+    counter = iter(range(1000))
+    monkeypatch.setattr(online.scsurf, "kf_fuse", lambda *a, **k: next(counter))
+    monkeypatch.setattr(online.scsurf, "keyframe_pack", lambda kf, stream=None: kf)
+    monkeypatch.setattr(online.scsurf, "KeyframeSet", lambda kfs: list(kfs))
+    vol = _CallLog()
+    sess = online.OnlineSession(vol, None, kappa, 2, integrate_every=every)
+    z, c = torch.zeros((4, 4)), torch.zeros((4, 4, 3), dtype=torch.uint8)
+    for f in range(n_frames):
+        k = sess.add_frame(z, c, np.eye(3), np.zeros(3))
+        if k is not None and (k + 1) in updates_at:
+            sess.pose_update(np.repeat(np.eye(3)[None], k + 1, 0), np.zeros((k + 1, 3)))
+    sess.final_pass()
+    return vol.calls
+
+
+def test_held_integrations_flush_in_order(monkeypatch):
+    # 11 keyframes of 2 frames (the last one completed by the final pass),
+    # held 3 at a time, updates after keyframes 5 and 9
+    calls = _held_session(monkeypatch, 3, 21, {5, 9})
+    assert calls == [("integrate_batch", [0, 1, 2]), ("integrate_batch", [3, 4]), ("update", 5),
+                     ("integrate_batch", [5, 6, 7]), ("integrate_batch", [8]), ("update", 9),
+                     ("integrate_batch", [9, 10]), ("update", 11)]
+
+
+def test_unheld_integrations_are_one_at_a_time(monkeypatch):
+    calls = _held_session(monkeypatch, 1, 8, {2})
+    assert calls == [("integrate", 0), ("integrate", 1), ("update", 2), ("integrate", 2), ("integrate", 3),
+                     ("update", 4)]
