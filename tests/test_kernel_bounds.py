@@ -1,9 +1,10 @@
-"""Host checks of the error bounds two kernel shortcuts rest on, with IEEE
-FP32 arithmetic emulated in numpy (float32 operations round to nearest even
-as the GPU's do; a fused multiply-add is formed exactly in float64 and
-rounded once).  Neither test runs GPU code: they check that the bound
+"""Host checks of the rules three kernel shortcuts rest on, with IEEE FP32
+arithmetic emulated in numpy where it matters (float32 operations round to
+nearest even as the GPU's do; a fused multiply-add is formed exactly in
+float64 and rounded once).  No test runs GPU code: they check that the
 derivations in the kernel sources accept no wrong result, on random and on
-adversarial inputs (values placed next to the rounding boundaries).
+adversarial inputs (values placed next to the rounding boundaries, many
+equal values).
 
 1. The nearest-pixel shortcut of the voxel pass: with tq = fl(a r) for an
    approximate reciprocal r of z, yq = fl(tq + c), the convention's
@@ -14,6 +15,9 @@ adversarial inputs (values placed next to the rounding boundaries).
    the exact round-half-even of (C Wq + c swq) / M, clamped to [0, 255],
    whenever |y' - rint(y')| + fma(|y'|, 2^-22, E0) <= 1/2,
    E0 = fma(fl(Wq fl(1/M)), 255 2^-22, 2^-22).
+3. The colour median's per-observation test: the observation whose
+   strictly-before weight is below half the total and reaches half with its
+   own is the one lower weighted median.
 """
 import numpy as np
 
@@ -136,3 +140,38 @@ def test_colour_estimate_accepts_no_wrong_byte():
     c = rng.integers(0, 256, len(Wq)).astype(np.int64)
     ok, _ = _fast_channel(C, c, Wq, swq)
     assert ok.mean() > 0.99
+
+
+def test_median_rule_picks_exactly_the_lower_weighted_median():
+    """The colour median's per-observation rule: with the valid observations
+    ordered by (value, frame), observation j passes when the weight ordered
+    strictly before it is below half the total and that weight plus its own
+    reaches half.  Exactly one passes, and it is the lower weighted median
+    (the first in that order whose cumulative weight reaches half), on random
+    cases with many equal values, missing frames (weight 0) and weights on
+    the 2^-20 grid up to 2^31."""
+    rng = np.random.default_rng(17)
+    for trial in range(20000):
+        m = int(rng.integers(1, 65))
+        c = rng.integers(0, 4 if trial % 2 else 65281, m).astype(np.float64)
+        w = rng.integers(1, 2 ** (int(rng.integers(1, 32))), m, dtype=np.int64)
+        w[rng.random(m) < 0.2] = 0
+        if not (w > 0).any():
+            continue
+        total = int(w.sum())
+        idx = [j for j in range(m) if w[j] > 0]
+        # brute force: sorted by (value, frame), first cumulative >= half
+        srt = sorted(idx, key=lambda j: (c[j], j))
+        cum, brute = 0, None
+        for j in srt:
+            cum += int(w[j])
+            if 2 * cum >= total:
+                brute = c[j]
+                break
+        passed = []
+        for j in idx:
+            below = sum(int(w[l]) for l in idx if c[l] < c[j] or (c[l] == c[j] and l < j))
+            if 2 * below < total <= 2 * (below + int(w[j])):
+                passed.append(j)
+        assert len(passed) == 1, (trial, passed)
+        assert c[passed[0]] == brute
